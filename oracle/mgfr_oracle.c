@@ -1,0 +1,429 @@
+/*
+ * mgfr_oracle.c -- plain, slow FP64 CPU reference of the f(R) field solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity judge for the HIP
+ * library: only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.  It shares no code, header, table or helper with the
+ * GPU path; it is single-threaded, unblocked and unfused on purpose so that it
+ * can be read against the paper (Puchwein, Baldi & Springel 2013, "Modified
+ * Gravity-GADGET") line by line.
+ *
+ * Units and form.  Positions are comoving Mpc/h, the cell side h = L/N is
+ * comoving.  The paper's discrete field equation (Sec. 3.2, Eq.
+ * u_discrete_field_eq) is written in physical units; multiplying it by a^2
+ * and using 8 pi G rho_bar = 3 H0^2 Omega_m a^-3 and R_bar = 3 H0^2 C(a)
+ * (Sec. 2, background curvature of flat LCDM) gives the dimensionless form
+ * used throughout:
+ *
+ *   L_c(u) = (1/h^2) sum_nb 1/2 (e^{u_nb} + e^{u_c}) (u_nb - u_c)
+ *            - beta C (1 - e^{-u_c/(n+1)})
+ *   f_c    = beta Omega_m a^-3 delta_c
+ *   beta   = a^2 (H0/c)^2 / |fbar_R(a)|,  C(a) = Omega_m a^-3 + 4 Omega_L
+ *
+ * which is the paper's operator and source times a^2 (an exact rescaling: the
+ * relative residual is unchanged).  For n = 1 the curvature term is the
+ * paper's Eq. dR_fR; for general n it follows from the large-curvature
+ * relation f_R ~ R^-(n+1) (Sec. 2, Eq. fR-R,n_relation).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_C_OVER_H0 2997.92458   /* c/H0 in Mpc/h */
+#define OR_C_KMS 299792.458       /* c in km/s */
+#define OR_MAX_HIST 512
+
+typedef struct {
+    double box;      /* comoving box side, Mpc/h */
+    double a;        /* scale factor */
+    double omega_m, omega_l;
+    double fr0_abs;  /* |fbar_R0| */
+    int n;           /* Hu-Sawicki exponent */
+    int mesh;        /* N, mesh cells per side (power of two >= 8) */
+    double tol;      /* relative max-norm residual threshold */
+    int pre_smooth, post_smooth, coarse_sweeps, max_vcycles;
+    int prolong;     /* 0 = linear (gradient-based) reconstruction, 1 = straight injection */
+    double max_du;   /* limit on |Newton step| per update; <= 0: no limit */
+} or_params;
+
+typedef struct {
+    int vcycles;
+    int status;      /* 0 converged, 1 not converged, -3 non-finite */
+    double res0, res, scale;
+    double res_hist[OR_MAX_HIST];
+} or_stats;
+
+/* ---------------------------------------------------------------- background */
+
+/* Sec. 2: R_bar(a) = 3 m^2 (a^-3 + 4 Omega_L/Omega_m) with m^2 = H0^2 Omega_m,
+ * and fbar_R(a) = fbar_R0 (R_bar0 / R_bar(a))^(n+1) (Eq. fR_mean for n = 1,
+ * Eq. fR-R,n_relation for general n).  Returns |fbar_R(a)|, beta and C. */
+void or_background(const or_params *p, double *fbar, double *beta, double *C)
+{
+    double r = 4.0 * p->omega_l / p->omega_m;
+    double a3 = 1.0 / (p->a * p->a * p->a);
+    double fb = p->fr0_abs * pow((1.0 + r) / (a3 + r), p->n + 1);
+    *fbar = fb;
+    *C = p->omega_m * a3 + 4.0 * p->omega_l;
+    *beta = p->a * p->a / (OR_C_OVER_H0 * OR_C_OVER_H0) / fb;
+}
+
+/* ------------------------------------------------------------ mass assignment */
+
+static long wrapi(long i, long N) { long r = i % N; return r < 0 ? r + N : r; }
+
+/* Sec. 3.1: cloud-in-cell.  Each particle is a cube of one cell side; cell
+ * (i,j,k) covers [ih,(i+1)h) per axis, centre (i+1/2)h; the weights are the
+ * overlap volumes.  Periodic.  mass == NULL means unit masses. */
+void or_cic_assign(int N, double box, int64_t np, const float *pos,
+                   const double *mass, double *m)
+{
+    double h = box / N;
+    memset(m, 0, sizeof(double) * (size_t)N * N * N);
+    for (int64_t p = 0; p < np; ++p) {
+        long i0[3];
+        double t[3];
+        for (int d = 0; d < 3; ++d) {
+            double xi = (double)pos[3 * p + d] / h - 0.5;
+            double fl = floor(xi);
+            t[d] = xi - fl;
+            i0[d] = (long)fl;
+        }
+        double mp = mass ? mass[p] : 1.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    double w = (a ? t[0] : 1.0 - t[0]) * (b ? t[1] : 1.0 - t[1]) *
+                               (c ? t[2] : 1.0 - t[2]);
+                    long ii = wrapi(i0[0] + a, N), jj = wrapi(i0[1] + b, N), kk = wrapi(i0[2] + c, N);
+                    m[(ii * N + jj) * N + kk] += w * mp;
+                }
+    }
+}
+
+/* delta = m / m_bar - 1 with m_bar the mean assigned cell mass. */
+void or_delta(int N, const double *m, double *delta)
+{
+    size_t n3 = (size_t)N * N * N;
+    double s = 0.0;
+    for (size_t c = 0; c < n3; ++c) s += m[c];
+    double mbar = s / (double)n3;
+    for (size_t c = 0; c < n3; ++c) delta[c] = m[c] / mbar - 1.0;
+}
+
+/* Source term (Sec. 3.2, f_ijk) in the dimensionless form: beta Omega_m a^-3 delta. */
+void or_source(const or_params *p, const double *delta, double *f)
+{
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    size_t n3 = (size_t)p->mesh * p->mesh * p->mesh;
+    double s = beta * p->omega_m / (p->a * p->a * p->a);
+    for (size_t c = 0; c < n3; ++c) f[c] = s * delta[c];
+}
+
+/* ---------------------------------------------------------------- operator */
+
+#define IDX(i, j, k) ((((size_t)(i)) * N + (j)) * N + (k))
+
+/* L_c and its derivative with respect to u_c at one cell.  The flux-form
+ * Laplacian of e^u uses face coefficients b = (e^{u_a} + e^{u_b})/2 times the
+ * differences of u (Sec. 3.2); the derivative includes the u_c dependence of
+ * the face coefficients (Newton's d L / d u of Eq. iterative_correction). */
+static double op_cell(const double *u, int N, int i, int j, int k, double ih2,
+                      double bC, double q, double *J)
+{
+    int ip = (i + 1) % N, im = (i + N - 1) % N;
+    int jp = (j + 1) % N, jm = (j + N - 1) % N;
+    int kp = (k + 1) % N, km = (k + N - 1) % N;
+    double uc = u[IDX(i, j, k)];
+    double nb[6] = {u[IDX(ip, j, k)], u[IDX(im, j, k)], u[IDX(i, jp, k)],
+                    u[IDX(i, jm, k)], u[IDX(i, j, kp)], u[IDX(i, j, km)]};
+    double ec = exp(uc);
+    double lap = 0.0, dlap = 0.0;
+    for (int s = 0; s < 6; ++s) {
+        double en = exp(nb[s]);
+        lap += 0.5 * (en + ec) * (nb[s] - uc);
+        dlap += 0.5 * (ec * (nb[s] - uc - 1.0) - en);
+    }
+    /* 1 - e^{-q u} via expm1: no cancellation for small |u| */
+    double em = expm1(-q * uc);
+    if (J) *J = ih2 * dlap - bC * q * (1.0 + em);
+    return ih2 * lap + bC * em;
+}
+
+/* Apply L to the whole periodic N^3 mesh with cell side h. */
+void or_apply_L(int N, double h, double bC, int n, const double *u, double *L)
+{
+    double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) L[IDX(i, j, k)] = op_cell(u, N, i, j, k, ih2, bC, q, NULL);
+}
+
+/* d L_c / d u_c at every cell (used by tests to check the derivative). */
+void or_apply_J(int N, double h, double bC, int n, const double *u, double *Jout)
+{
+    double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) op_cell(u, N, i, j, k, ih2, bC, q, &Jout[IDX(i, j, k)]);
+}
+
+/* Max-norm of f - L(u). */
+double or_residual_max(int N, double h, double bC, int n, const double *u, const double *f)
+{
+    double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1), mx = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) {
+                double r = fabs(f[IDX(i, j, k)] - op_cell(u, N, i, j, k, ih2, bC, q, NULL));
+                if (!(r <= mx)) mx = r; /* NaN propagates */
+            }
+    return mx;
+}
+
+/* One red-black Newton-Gauss-Seidel sweep (Sec. 3.3, Eq. iterative_correction):
+ * first every red cell ((i+j+k) even) is updated from its six neighbours,
+ * then every black cell, each by u <- u - (L - f) / (dL/du).  The paper
+ * names no safeguard; a step limit |du| <= max_du (off when max_du <= 0) keeps
+ * a cold start from overshooting into overflow of e^{-u/(n+1)} in deeply
+ * screened cells, where the curvature term makes the update strongly convex. */
+void or_ngs_sweep(int N, double h, double bC, int n, double max_du, double *u, const double *f)
+{
+    double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
+    for (int colour = 0; colour < 2; ++colour)
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                for (int k = 0; k < N; ++k) {
+                    if (((i + j + k) & 1) != colour) continue;
+                    double J;
+                    double L = op_cell(u, N, i, j, k, ih2, bC, q, &J);
+                    double du = -(L - f[IDX(i, j, k)]) / J;
+                    if (max_du > 0.0) du = fmin(fmax(du, -max_du), max_du);
+                    u[IDX(i, j, k)] += du;
+                }
+}
+
+/* ------------------------------------------------------------- grid transfer */
+
+/* Restriction R (Sec. 3.3): a parent value is the mean of its 8 daughters. */
+void or_restrict(int Nf, const double *fine, double *coarse)
+{
+    int N = Nf / 2;
+    for (int I = 0; I < N; ++I)
+        for (int J = 0; J < N; ++J)
+            for (int K = 0; K < N; ++K) {
+                double s = 0.0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b)
+                        for (int c = 0; c < 2; ++c)
+                            s += fine[(((size_t)(2 * I + a)) * Nf + (2 * J + b)) * Nf + (2 * K + c)];
+                coarse[IDX(I, J, K)] = s / 8.0;
+            }
+}
+
+/* Fine-grid correction u += P(uc - ubar) (Sec. 3.3, Eq. fine_correction).
+ * P is straight injection (mode 1) or the linear reconstruction from the
+ * parent value and the central-difference gradient at the parent centre
+ * (mode 0): a daughter displaced by s_d h/2 (s_d = -1 or +1) along axis d
+ * gets e_P + sum_d s_d (e_{P+d} - e_{P-d}) / 8.  Periodic. */
+void or_prolong_add(int Nf, int mode, const double *uc, const double *ubar, double *u)
+{
+    int N = Nf / 2;
+    for (int i = 0; i < Nf; ++i)
+        for (int j = 0; j < Nf; ++j)
+            for (int k = 0; k < Nf; ++k) {
+                int I = i / 2, J = j / 2, K = k / 2;
+#define E(a, b, c) (uc[IDX(a, b, c)] - ubar[IDX(a, b, c)])
+                double v = E(I, J, K);
+                if (mode == 0) {
+                    double si = (i & 1) ? 1.0 : -1.0, sj = (j & 1) ? 1.0 : -1.0, sk = (k & 1) ? 1.0 : -1.0;
+                    v += si * (E((I + 1) % N, J, K) - E((I + N - 1) % N, J, K)) / 8.0;
+                    v += sj * (E(I, (J + 1) % N, K) - E(I, (J + N - 1) % N, K)) / 8.0;
+                    v += sk * (E(I, J, (K + 1) % N) - E(I, J, (K + N - 1) % N)) / 8.0;
+                }
+#undef E
+                u[(((size_t)i) * Nf + j) * Nf + k] += v;
+            }
+}
+
+/* ---------------------------------------------------------------- multigrid */
+
+typedef struct {
+    int nlev;
+    int Ns[32];
+    double hs[32];
+    double *u[32], *f[32], *ubar[32], *tmp[32];
+} or_hier;
+
+static void hier_free(or_hier *H)
+{
+    for (int l = 0; l < H->nlev; ++l) {
+        if (l > 0) { free(H->u[l]); free(H->f[l]); }
+        free(H->ubar[l]);
+        free(H->tmp[l]);
+    }
+}
+
+/* One FAS V-cycle on level l (Sec. 3.3, steps 3-7). */
+static void vcycle(or_hier *H, int l, const or_params *p, double bC)
+{
+    int N = H->Ns[l];
+    double h = H->hs[l];
+    if (l == H->nlev - 1) { /* coarsest (4^3): NGS directly */
+        for (int s = 0; s < p->coarse_sweeps; ++s) or_ngs_sweep(N, h, bC, p->n, p->max_du, H->u[l], H->f[l]);
+        return;
+    }
+    for (int s = 0; s < p->pre_smooth; ++s) or_ngs_sweep(N, h, bC, p->n, p->max_du, H->u[l], H->f[l]);
+    size_t n3 = (size_t)N * N * N;
+    int Nc = H->Ns[l + 1];
+    size_t nc3 = (size_t)Nc * Nc * Nc;
+    /* residual r = f - L(u) on this level */
+    or_apply_L(N, h, bC, p->n, H->u[l], H->tmp[l]);
+    for (size_t c = 0; c < n3; ++c) H->tmp[l][c] = H->f[l][c] - H->tmp[l][c];
+    /* coarse problem: f_c = L_c(R u) + R(f - L(u)), initial guess R u */
+    or_restrict(N, H->u[l], H->ubar[l + 1]);
+    or_restrict(N, H->tmp[l], H->f[l + 1]);
+    or_apply_L(Nc, H->hs[l + 1], bC, p->n, H->ubar[l + 1], H->tmp[l + 1]);
+    for (size_t c = 0; c < nc3; ++c) H->f[l + 1][c] += H->tmp[l + 1][c];
+    memcpy(H->u[l + 1], H->ubar[l + 1], nc3 * sizeof(double));
+    vcycle(H, l + 1, p, bC);
+    or_prolong_add(N, p->prolong, H->u[l + 1], H->ubar[l + 1], H->u[l]);
+    for (int s = 0; s < p->post_smooth; ++s) or_ngs_sweep(N, h, bC, p->n, p->max_du, H->u[l], H->f[l]);
+}
+
+/* Number of levels from N down to the 4^3 coarsest grid (Sec. 3.3, step 5). */
+int or_num_levels(int N)
+{
+    int l = 1;
+    while (N > 4) { N /= 2; ++l; }
+    return l;
+}
+
+/* Solve L(u) = f for u on the periodic N^3 mesh (Sec. 3.3, steps 1-8).
+ * u holds the initial guess on entry (0 = background) and the result on exit;
+ * dfr (nullable) receives delta f_R = fbar_R (e^u - 1) = -|fbar| expm1(u).
+ * Acceptance: max |f - L(u)| / D <= tol with D = max |f| (beta C if f == 0),
+ * tested before the first cycle and after every cycle. */
+int or_solve(const or_params *p, const double *delta, double *u, double *dfr, or_stats *st)
+{
+    int N = p->mesh;
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    double bC = beta * C;
+    or_hier H;
+    memset(&H, 0, sizeof H);
+    H.nlev = or_num_levels(N);
+    for (int l = 0, n = N; l < H.nlev; ++l, n /= 2) {
+        size_t n3 = (size_t)n * n * n;
+        H.Ns[l] = n;
+        H.hs[l] = p->box / n;
+        H.u[l] = l ? malloc(n3 * sizeof(double)) : u;
+        H.f[l] = l ? malloc(n3 * sizeof(double)) : malloc(n3 * sizeof(double));
+        H.ubar[l] = malloc(n3 * sizeof(double));
+        H.tmp[l] = malloc(n3 * sizeof(double));
+    }
+    size_t n3 = (size_t)N * N * N;
+    or_source(p, delta, H.f[0]);
+    double D = 0.0;
+    for (size_t c = 0; c < n3; ++c) if (!(fabs(H.f[0][c]) <= D)) D = fabs(H.f[0][c]);
+    if (D == 0.0) D = bC;
+    memset(st, 0, sizeof *st);
+    st->scale = D;
+    int status = 1;
+    double res = or_residual_max(N, H.hs[0], bC, p->n, u, H.f[0]) / D;
+    st->res0 = res;
+    int cyc = 0;
+    for (;;) {
+        if (!isfinite(res)) { status = -3; break; }
+        if (res <= p->tol) { status = 0; break; }
+        if (cyc >= p->max_vcycles) { status = 1; break; }
+        vcycle(&H, 0, p, bC);
+        res = or_residual_max(N, H.hs[0], bC, p->n, u, H.f[0]) / D;
+        if (cyc < OR_MAX_HIST) st->res_hist[cyc] = res;
+        ++cyc;
+    }
+    st->vcycles = cyc;
+    st->res = res;
+    st->status = status;
+    if (dfr) for (size_t c = 0; c < n3; ++c) dfr[c] = -fb * expm1(u[c]);
+    free(H.f[0]);
+    hier_free(&H);
+    return status;
+}
+
+/* One V-cycle on a given level set-up, exposed for per-step parity tests. */
+void or_vcycle_once(const or_params *p, const double *f, double *u)
+{
+    int N = p->mesh;
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    or_hier H;
+    memset(&H, 0, sizeof H);
+    H.nlev = or_num_levels(N);
+    for (int l = 0, n = N; l < H.nlev; ++l, n /= 2) {
+        size_t n3 = (size_t)n * n * n;
+        H.Ns[l] = n;
+        H.hs[l] = p->box / n;
+        H.u[l] = l ? malloc(n3 * sizeof(double)) : u;
+        H.f[l] = l ? malloc(n3 * sizeof(double)) : malloc(n3 * sizeof(double));
+        H.ubar[l] = malloc(n3 * sizeof(double));
+        H.tmp[l] = malloc(n3 * sizeof(double));
+    }
+    memcpy(H.f[0], f, sizeof(double) * (size_t)N * N * N);
+    vcycle(&H, 0, p, beta * C);
+    free(H.f[0]);
+    hier_free(&H);
+}
+
+/* ------------------------------------------------------------- fifth force */
+
+/* a_MG = (c^2/2) grad_phys f_R (Sec. 2, Eq. modgrav_accel) = c^2/(2a) grad_x f_R
+ * in comoving x, f_R = fbar_R e^u.  The gradient at cell centres is the
+ * two-point central difference; it is interpolated to the particles with
+ * the same cloud-in-cell weights as the mass assignment.  Units of acc:
+ * (km/s)^2 h/Mpc. */
+void or_fifth_force(const or_params *p, const double *u, int64_t np, const float *pos, double *acc)
+{
+    int N = p->mesh;
+    double h = p->box / N;
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    size_t n3 = (size_t)N * N * N;
+    double *fr = malloc(n3 * sizeof(double));
+    double *g = malloc(3 * n3 * sizeof(double));
+    for (size_t c = 0; c < n3; ++c) fr[c] = -fb * exp(u[c]);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) {
+                size_t c = IDX(i, j, k);
+                g[3 * c + 0] = (fr[IDX((i + 1) % N, j, k)] - fr[IDX((i + N - 1) % N, j, k)]) / (2 * h);
+                g[3 * c + 1] = (fr[IDX(i, (j + 1) % N, k)] - fr[IDX(i, (j + N - 1) % N, k)]) / (2 * h);
+                g[3 * c + 2] = (fr[IDX(i, j, (k + 1) % N)] - fr[IDX(i, j, (k + N - 1) % N)]) / (2 * h);
+            }
+    double pref = OR_C_KMS * OR_C_KMS / (2.0 * p->a);
+    for (int64_t q = 0; q < np; ++q) {
+        long i0[3];
+        double t[3];
+        for (int d = 0; d < 3; ++d) {
+            double xi = (double)pos[3 * q + d] / h - 0.5;
+            double fl = floor(xi);
+            t[d] = xi - fl;
+            i0[d] = (long)fl;
+        }
+        double s[3] = {0, 0, 0};
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    double w = (a ? t[0] : 1.0 - t[0]) * (b ? t[1] : 1.0 - t[1]) *
+                               (c ? t[2] : 1.0 - t[2]);
+                    size_t cell = ((size_t)wrapi(i0[0] + a, N) * N + wrapi(i0[1] + b, N)) * N +
+                                  wrapi(i0[2] + c, N);
+                    for (int d = 0; d < 3; ++d) s[d] += w * g[3 * cell + d];
+                }
+        for (int d = 0; d < 3; ++d) acc[3 * q + d] = pref * s[d];
+    }
+    free(fr);
+    free(g);
+}

@@ -1,0 +1,190 @@
+"""ctypes front end of the plain FP64 CPU oracle (``mgfr_oracle.c``).
+
+Test infrastructure only: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg use it to judge the HIP library; the library never calls it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mgfr_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+C_OVER_H0 = 2997.92458
+C_KMS = 299792.458
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, single thread)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("box", C.c_double), ("a", C.c_double), ("omega_m", C.c_double),
+                ("omega_l", C.c_double), ("fr0_abs", C.c_double), ("n", C.c_int),
+                ("mesh", C.c_int), ("tol", C.c_double), ("pre_smooth", C.c_int),
+                ("post_smooth", C.c_int), ("coarse_sweeps", C.c_int),
+                ("max_vcycles", C.c_int), ("prolong", C.c_int), ("max_du", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("vcycles", C.c_int), ("status", C.c_int), ("res0", C.c_double),
+                ("res", C.c_double), ("scale", C.c_double), ("res_hist", C.c_double * 512)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        fp = C.POINTER(C.c_float)
+        L.or_background.argtypes = [C.POINTER(Params), dp, dp, dp]
+        L.or_cic_assign.argtypes = [C.c_int, C.c_double, C.c_int64, fp, dp, dp]
+        L.or_delta.argtypes = [C.c_int, dp, dp]
+        L.or_source.argtypes = [C.POINTER(Params), dp, dp]
+        L.or_apply_L.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
+        L.or_apply_J.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
+        L.or_residual_max.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
+        L.or_residual_max.restype = C.c_double
+        L.or_ngs_sweep.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, dp, dp]
+        L.or_restrict.argtypes = [C.c_int, dp, dp]
+        L.or_prolong_add.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        L.or_num_levels.argtypes = [C.c_int]
+        L.or_num_levels.restype = C.c_int
+        L.or_solve.argtypes = [C.POINTER(Params), dp, dp, dp, C.POINTER(Stats)]
+        L.or_solve.restype = C.c_int
+        L.or_vcycle_once.argtypes = [C.POINTER(Params), dp, dp]
+        L.or_fifth_force.argtypes = [C.POINTER(Params), dp, C.c_int64, fp, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f(a):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def params(mesh=32, box=100.0, a=1.0, omega_m=0.3, omega_l=0.7, fr0_abs=1e-5, n=1,
+           tol=1e-8, pre_smooth=2, post_smooth=2, coarse_sweeps=30, max_vcycles=100,
+           prolong=0, max_du=2.0) -> Params:
+    return Params(box, a, omega_m, omega_l, fr0_abs, n, mesh, tol, pre_smooth, post_smooth,
+                  coarse_sweeps, max_vcycles, prolong, max_du)
+
+
+def background(p: Params):
+    fb, beta, Cc = C.c_double(), C.c_double(), C.c_double()
+    lib().or_background(C.byref(p), C.byref(fb), C.byref(beta), C.byref(Cc))
+    return fb.value, beta.value, Cc.value
+
+
+def cic_assign(N, box, pos, mass=None):
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    m = np.zeros((N, N, N), np.float64)
+    mp = None if mass is None else _d(np.ascontiguousarray(mass, np.float64))
+    lib().or_cic_assign(N, box, pos.shape[0], _f(pos), mp, _d(m))
+    return m
+
+
+def density_contrast(m):
+    m = np.ascontiguousarray(m, np.float64)
+    d = np.empty_like(m)
+    lib().or_delta(m.shape[0], _d(m), _d(d))
+    return d
+
+
+def source(p, delta):
+    delta = np.ascontiguousarray(delta, np.float64)
+    f = np.empty_like(delta)
+    lib().or_source(C.byref(p), _d(delta), _d(f))
+    return f
+
+
+def apply_L(u, h, bC, n=1):
+    u = np.ascontiguousarray(u, np.float64)
+    out = np.empty_like(u)
+    lib().or_apply_L(u.shape[0], h, bC, n, _d(u), _d(out))
+    return out
+
+
+def apply_J(u, h, bC, n=1):
+    u = np.ascontiguousarray(u, np.float64)
+    out = np.empty_like(u)
+    lib().or_apply_J(u.shape[0], h, bC, n, _d(u), _d(out))
+    return out
+
+
+def residual_max(u, f, h, bC, n=1):
+    u = np.ascontiguousarray(u, np.float64)
+    f = np.ascontiguousarray(f, np.float64)
+    return lib().or_residual_max(u.shape[0], h, bC, n, _d(u), _d(f))
+
+
+def ngs_sweep(u, f, h, bC, n=1, max_du=2.0):
+    """One red+black sweep; returns a new array."""
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    f = np.ascontiguousarray(f, np.float64)
+    lib().or_ngs_sweep(u.shape[0], h, bC, n, max_du, _d(u), _d(f))
+    return u
+
+
+def restrict(fine):
+    fine = np.ascontiguousarray(fine, np.float64)
+    N = fine.shape[0] // 2
+    c = np.empty((N, N, N), np.float64)
+    lib().or_restrict(fine.shape[0], _d(fine), _d(c))
+    return c
+
+
+def prolong_add(u, uc, ubar, mode=0):
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    lib().or_prolong_add(u.shape[0], mode, _d(np.ascontiguousarray(uc, np.float64)),
+                         _d(np.ascontiguousarray(ubar, np.float64)), _d(u))
+    return u
+
+
+def num_levels(N):
+    return lib().or_num_levels(N)
+
+
+def solve(p, delta, u0=None, want_dfr=True):
+    """Returns (status, u, dfr, stats)."""
+    delta = np.ascontiguousarray(delta, np.float64)
+    N = p.mesh
+    u = np.zeros((N, N, N), np.float64) if u0 is None else np.array(u0, np.float64, order="C", copy=True)
+    dfr = np.empty_like(u) if want_dfr else None
+    st = Stats()
+    s = lib().or_solve(C.byref(p), _d(delta), _d(u), _d(dfr) if want_dfr else None, C.byref(st))
+    return s, u, dfr, st
+
+
+def vcycle_once(p, f, u):
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    lib().or_vcycle_once(C.byref(p), _d(np.ascontiguousarray(f, np.float64)), _d(u))
+    return u
+
+
+def fifth_force(p, u, pos):
+    pos = np.ascontiguousarray(pos, np.float32)
+    u = np.ascontiguousarray(u, np.float64)
+    acc = np.empty((pos.shape[0], 3), np.float64)
+    lib().or_fifth_force(C.byref(p), _d(u), pos.shape[0], _f(pos), _d(acc))
+    return acc

@@ -1,0 +1,487 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Every test here checks the oracle against something other than itself: the
+Hu-Sawicki model evaluated exactly, hand-derived stencil values, finite
+differences, the periodic linear (Yukawa) solution by FFT, the paper's
+point-mass formula, brute-force dense Newton, the paper's printed 1D-peak
+normalisation, and invariants of the discrete equations.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import oracle as O
+from paper_1305_2418_amd import synth
+from tests import refs
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def bc_of(p):
+    fb, beta, C = O.background(p)
+    return fb, beta, C, beta * C
+
+
+# ------------------------------------------------------------------ background (Sec. 2)
+
+@pytest.mark.parametrize("a", [1.0, 0.5, 0.25])
+@pytest.mark.parametrize("n", [1, 2])
+@pytest.mark.parametrize("fr0", [1e-5, 1e-6, 1e-7])
+def test_fbar_matches_exact_hu_sawicki(a, n, fr0):
+    p = O.params(a=a, n=n, fr0_abs=fr0)
+    fb, _, _ = O.background(p)
+    ex = refs.fbar_exact(a, fr0, n, 0.3, 0.7)
+    # the oracle uses the large-curvature form; its relative error is O(|fR| R/m^2 / (c1/c2))
+    assert abs(fb / ex - 1) < 2e-4
+
+
+@pytest.mark.parametrize("a", [1.0, 0.5, 0.1])
+def test_curvature_matches_friedmann(a):
+    _, _, C = O.background(O.params(a=a))
+    assert abs(3 * C / refs.rbar_from_friedmann(a, 0.3, 0.7) - 1) < 1e-8
+
+
+@pytest.mark.parametrize("a", [1.0, 0.5])
+@pytest.mark.parametrize("fr0", [1e-4, 1e-5, 1e-6])
+def test_screening_mass_matches_paper_lambda(a, fr0):
+    """beta C / (n+1) is the comoving a^2 lambda^2 of the paper's Yukawa solution (Sec. 4.1)."""
+    p = O.params(a=a, fr0_abs=fr0)
+    _, _, _, bC = bc_of(p)
+    lam2 = refs.lambda2_comoving(a, fr0, 1, 0.3, 0.7)
+    assert abs(bC / 2 / lam2 - 1) < 5e-4
+
+
+# ------------------------------------------------------------------- operator (Sec. 3.2)
+
+H, BC = 3.125, 0.0345
+
+
+def test_operator_constant_field():
+    for c in (-3.0, -0.5, 0.0, 0.7):
+        u = np.full((8, 8, 8), c)
+        L = O.apply_L(u, H, BC)
+        assert np.allclose(L, -BC * (1 - math.exp(-c / 2)), rtol=1e-15, atol=1e-18)
+
+
+def test_operator_single_bump_hand_values():
+    """u = eps at one cell, 0 elsewhere: the printed flux form gives, at the bump,
+    6 * (1 + e^eps)/2 * (0 - eps) / h^2 - bC (1 - e^{-eps/2}), and at each of its six
+    neighbours (e^eps + 1)/2 * eps / h^2; zero further away."""
+    eps = 0.3
+    u = np.zeros((8, 8, 8))
+    u[3, 4, 5] = eps
+    L = O.apply_L(u, H, BC)
+    bump = -6 * 0.5 * (1 + math.exp(eps)) * eps / H ** 2 - BC * (1 - math.exp(-eps / 2))
+    nb = 0.5 * (math.exp(eps) + 1) * eps / H ** 2
+    assert L[3, 4, 5] == pytest.approx(bump, rel=1e-14)
+    for d in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+        assert L[3 + d[0], 4 + d[1], 5 + d[2]] == pytest.approx(nb, rel=1e-14)
+    L[3, 4, 5] = 0
+    for d in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+        L[3 + d[0], 4 + d[1], 5 + d[2]] = 0
+    assert np.abs(L).max() == 0.0
+
+
+def test_operator_periodic_wrap():
+    u = np.zeros((8, 8, 8))
+    u[0, 0, 0] = 0.2
+    L = O.apply_L(u, H, BC)
+    nb = 0.5 * (math.exp(0.2) + 1) * 0.2 / H ** 2
+    for c in [(7, 0, 0), (0, 7, 0), (0, 0, 7), (1, 0, 0)]:
+        assert L[c] == pytest.approx(nb, rel=1e-14)
+
+
+def test_operator_matches_vectorised_numpy():
+    rng = np.random.default_rng(0)
+    u = rng.normal(-1, 1.5, (8, 8, 8))
+    for n in (1, 2, 3):
+        assert np.allclose(O.apply_L(u, H, BC, n), refs.L_numpy(u, H, BC, n), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_newton_derivative_finite_difference(n):
+    """d L_c / d u_c (Newton denominator of Eq. iterative_correction) vs central differences."""
+    rng = np.random.default_rng(1)
+    u = rng.normal(-2, 2, (8, 8, 8))
+    J = O.apply_J(u, H, BC, n)
+    for c in [(0, 0, 0), (3, 5, 1), (7, 2, 6)]:
+        d = 1e-6
+        up, um = u.copy(), u.copy()
+        up[c] += d
+        um[c] -= d
+        fd = (O.apply_L(up, H, BC, n)[c] - O.apply_L(um, H, BC, n)[c]) / (2 * d)
+        assert J[c] == pytest.approx(fd, rel=1e-7)
+    assert (J < 0).all()
+
+
+# ------------------------------------------------------------------ transfers (Sec. 3.3)
+
+def test_restriction_is_daughter_mean():
+    rng = np.random.default_rng(2)
+    f = rng.normal(size=(16, 16, 16))
+    ref = f.reshape(8, 2, 8, 2, 8, 2).mean(axis=(1, 3, 5))
+    assert np.allclose(O.restrict(f), ref, rtol=1e-15, atol=1e-15)
+
+
+def test_prolongation_injection_and_linear():
+    N = 8
+    I = np.arange(N)[:, None, None] + 0 * np.arange(N)[None, :, None] + 0 * np.arange(N)[None, None, :]
+    uc = (1.0 * I + 2.0 * I.transpose(1, 0, 2) - 0.5 * I.transpose(2, 1, 0)).astype(np.float64)
+    ubar = np.zeros_like(uc)
+    zero = np.zeros((2 * N,) * 3)
+    inj = O.prolong_add(zero, uc, ubar, mode=1)
+    assert np.array_equal(inj, np.repeat(np.repeat(np.repeat(uc, 2, 0), 2, 1), 2, 2))
+    lin = O.prolong_add(zero, uc, ubar, mode=0)
+    # a linear coarse field is reproduced exactly at fine centres away from the periodic seam:
+    # fine centre i sits at coarse coordinate (i - 1/2)/2
+    x = (np.arange(2 * N) - 0.5) / 2
+    exact = (1.0 * x[:, None, None] + 2.0 * x[None, :, None] - 0.5 * x[None, None, :])
+    sl = slice(2, 2 * N - 2)
+    assert np.allclose(lin[sl, sl, sl], exact[sl, sl, sl], atol=1e-13)
+    # correction form: no change when uc == ubar
+    u0 = np.random.default_rng(3).normal(size=(2 * N,) * 3)
+    assert np.array_equal(O.prolong_add(u0, uc, uc, 0), u0)
+
+
+def test_num_levels_reach_4cubed():
+    assert O.num_levels(32) == 4 and O.num_levels(512) == 8 and O.num_levels(8) == 2
+    assert GOLD["multigrid"]["coarsest"] == 4
+
+
+# ---------------------------------------------------------------- mass assignment (Sec. 3.1)
+
+def test_cic_single_particle_weights():
+    N, box = 8, 8.0
+    m = O.cic_assign(N, box, np.array([[2.5, 3.5, 4.5]], np.float32))  # a cell centre
+    assert m[2, 3, 4] == 1.0 and m.sum() == 1.0
+    m = O.cic_assign(N, box, np.array([[3.0, 0.0, 5.75]], np.float32))  # on faces / quarter
+    # x: halfway between cells 2 and 3; y: halfway between 7 (wrapped) and 0; z: 5.75 -> 0.75/0.25
+    assert m[2, 7, 5] == pytest.approx(0.25 * 0.75)
+    assert m[3, 0, 5] == pytest.approx(0.25 * 0.75)
+    assert m[2, 0, 6] == pytest.approx(0.25 * 0.25)
+    assert m.sum() == pytest.approx(1.0, abs=1e-15)
+
+
+def test_cic_mass_conservation_and_lattice():
+    pos = synth.clustered_load(16, 100.0, rms=1.0, seed=5).numpy()
+    mass = np.random.default_rng(4).uniform(0.5, 2.0, pos.shape[0])
+    m = O.cic_assign(16, 100.0, pos, mass)
+    assert m.sum() == pytest.approx(mass.sum(), rel=1e-13)
+    lat = synth.to_f32(synth.lattice(16, 100.0), 100.0).numpy()
+    d = O.density_contrast(O.cic_assign(16, 100.0, lat))
+    assert np.abs(d).max() < 1e-6  # float32 lattice positions at cell centres
+    lat2 = synth.to_f32(synth.lattice(32, 100.0), 100.0).numpy()  # 8 particles per cell
+    d2 = O.density_contrast(O.cic_assign(16, 100.0, lat2))
+    assert np.abs(d2).max() < 1e-5
+
+
+# --------------------------------------------------------------------- solver: T1-T4
+
+def test_uniform_density_gives_zero_field():
+    p = O.params(mesh=16, box=100.0)
+    s, u, dfr, st = O.solve(p, np.zeros((16, 16, 16)))
+    assert s == 0 and st.vcycles == 0 and np.all(u == 0) and np.all(dfr == 0)
+    u0 = np.random.default_rng(5).normal(0, 0.3, (16, 16, 16))
+    p = O.params(mesh=16, box=100.0, tol=1e-13)
+    s, u, dfr, st = O.solve(p, np.zeros((16, 16, 16)), u0=u0)
+    assert s == 0 and np.abs(u).max() < 1e-11
+
+
+@pytest.mark.parametrize("a", [1.0, 0.5])
+@pytest.mark.parametrize("kind", ["cos", "gauss"])
+def test_linear_regime_matches_discrete_yukawa(a, kind):
+    """Small delta: u -> -f_k / (k_hat^2 + mu^2), mu^2 = beta C/(n+1) (Sec. 4.1 linearisation).
+    Richardson in the amplitude removes the O(eps^2) term."""
+    N, box, fr0 = 32, 100.0, 1e-5
+    p = O.params(mesh=N, box=box, a=a, fr0_abs=fr0, tol=1e-13, max_vcycles=60)
+    fb, beta, C, bC = bc_of(p)
+    if kind == "cos":
+        shape = synth.cosine_delta(N, 1.0, mode=(1, 2, 0))
+    else:
+        shape = synth.gaussian_sphere_delta(N, box, 8.0, 20.0)
+    eps = 1e-3 / np.abs(shape).max()
+    us = []
+    for e in (eps, 2 * eps):
+        s, u, _, _ = O.solve(p, e * shape)
+        assert s == 0
+        us.append(u)
+    u_rich = 2 * us[0] - us[1] / 2
+    f = beta * 0.3 / a ** 3 * eps * shape
+    ulin = refs.linear_solution(f, box / N, bC / 2)
+    assert np.abs(u_rich - ulin).max() < 1e-5 * np.abs(ulin).max()
+    assert np.abs(us[0] - ulin).max() < 2e-3 * np.abs(ulin).max()
+
+
+def test_manufactured_solution_recovered():
+    """f = L(u*) for a deeply screened smooth u*: the FAS solve returns u* to the FP64 floor."""
+    N, box = 32, 100.0
+    p = O.params(mesh=N, box=box, fr0_abs=1e-6, tol=1e-12, max_vcycles=80)
+    fb, beta, C, bC = bc_of(p)
+    h = box / N
+    x = (np.arange(N) + 0.5) * h - box / 2
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    rng = np.random.default_rng(6)
+    noise = np.real(np.fft.ifftn(np.fft.fftn(rng.normal(size=(N, N, N))) * np.exp(-refs.discrete_k2(N, h) * 20)))
+    ustar = np.log(1 - 0.999 * np.exp(-r2 / 15.0 ** 2)) + 0.3 * noise / np.abs(noise).max()
+    f = refs.L_numpy(ustar, h, bC)
+    delta = f / (beta * 0.3)
+    s, u, _, st = O.solve(p, delta)
+    assert s == 0
+    assert np.abs(u - ustar).max() < 1e-9
+
+
+def test_brute_force_newton_8cubed():
+    """Dense-Jacobian Newton on the 8^3 discrete problem (independent of NGS/FAS)."""
+    N, box = 8, 40.0
+    rng = np.random.default_rng(7)
+    delta = np.exp(rng.normal(0, 1.5, (N, N, N)))
+    delta = delta / delta.mean() - 1
+    p = O.params(mesh=N, box=box, fr0_abs=1e-6, tol=1e-15, max_vcycles=200)
+    fb, beta, C, bC = bc_of(p)
+    f = beta * 0.3 * delta
+    un, fres = refs.dense_newton(f, box / N, bC, tol=1e-13 * np.abs(f).max())
+    s, u, _, st = O.solve(p, delta)
+    assert np.abs(u - un).max() < 1e-11
+    assert un.min() < -1.0  # the problem is non-linear (screened cells)
+
+
+# --------------------------------------------------------------------- T5: 1D peak
+
+def _peak_A():
+    g = GOLD["one_d_peak"]
+    L, w, al, fb = g["box"], g["w"], g["alpha"], g["fbar"]
+    f = lambda x: (1 - al * math.exp(-((x - L / 2) ** 2) / w ** 2)) ** -0.5
+    I, _ = integrate.quad(f, 0, L, points=[L / 2], limit=400, epsabs=1e-13, epsrel=1e-13)
+    return fb * (I / L) ** 2
+
+
+def test_one_d_peak_normalisation_matches_paper():
+    """Zero mean density perturbation fixes A; the paper prints A ~ 2.7e-5 (Sec. 4.2)."""
+    A = _peak_A()
+    g = GOLD["one_d_peak"]
+    assert abs(A / g["A_printed"] - 1) < 0.03
+    assert A == pytest.approx(2.7666e-5, rel=2e-4)
+
+
+def _peak_problem(N):
+    g = GOLD["one_d_peak"]
+    L, w, al, fb = g["box"], g["w"], g["alpha"], g["fbar"]
+    A = _peak_A()
+    h = L / N
+    # cell-averaged delta along x by quadrature (the density only depends on x)
+    Cc = 0.3 + 4 * 0.7
+    def dens(x):
+        dx = x - L / 2
+        gg = math.exp(-dx * dx / w ** 2)
+        fR = -A * (1 - al * gg)
+        d2 = A * al * gg * (4 * dx * dx / w ** 4 - 2 / w ** 2)
+        return (Cc * (math.sqrt(fb / -fR) - 1) - refs.C_OVER_H0 ** 2 * d2) / 0.3
+    prof = np.array([integrate.quad(dens, i * h, (i + 1) * h, limit=200)[0] / h for i in range(N)])
+    prof -= prof.mean()
+    delta = np.broadcast_to(prof[:, None, None], (N, N, N)).copy()
+    x = (np.arange(N) + 0.5) * h
+    fR = -A * (1 - al * np.exp(-((x - L / 2) ** 2) / w ** 2))
+    return delta, fR, fb
+
+
+def test_one_d_peak_converges_to_analytic():
+    """The discrete solution approaches the analytic f_R as h halves (Sec. 4.2 test)."""
+    errs = []
+    for N in (16, 32, 64):
+        delta, fR, fb = _peak_problem(N)
+        p = O.params(mesh=N, box=256.0, fr0_abs=fb, tol=1e-10, max_vcycles=80)
+        s, u, _, _ = O.solve(p, delta)
+        assert s == 0
+        fnum = -fb * np.exp(u[:, 0, 0])
+        assert np.allclose(u, u[:, :1, :1], atol=1e-10)  # stays one-dimensional
+        h = 256.0 / N
+        x = (np.arange(N) + 0.5) * h
+        far = np.abs(x - 128.0) > 20.0  # away from the unresolved spike
+        errs.append(np.abs(fnum - fR)[far].max() / abs(fR).max())
+    assert errs[2] < errs[1] < errs[0]
+    assert errs[1] / errs[2] > 2.5 and errs[2] < 0.02
+
+
+# ----------------------------------------------------------------- T6/T7: point mass
+
+@pytest.mark.parametrize("fbar", [1e-4, 1e-5])
+def test_point_mass_matches_yukawa(fbar):
+    g = GOLD["point_mass"]
+    N, box, amp = g["mesh"], g["box"], g["amp"]
+    c = (N // 2, N // 2, N // 2)
+    delta = synth.point_mass_delta(N, amp, cell=c)
+    p = O.params(mesh=N, box=box, fr0_abs=fbar, tol=1e-9)
+    fb, beta, C, bC = bc_of(p)
+    s, u, dfr, st = O.solve(p, delta)
+    assert s == 0
+    h = box / N
+    lam = math.sqrt(refs.lambda2_comoving(1.0, fbar, 1, 0.3, 0.7))
+    mass_term = (1 / refs.C_OVER_H0) ** 2 * 0.3 * amp * (N ** 3 - 1) * h ** 3 / (4 * math.pi)
+    r = np.arange(1, N // 2) * h
+    line = dfr[c[0] + np.arange(1, N // 2), c[1], c[2]]
+    # point-mass Yukawa plus the constant response to the uniform -amp underdensity
+    background = -(1 / refs.C_OVER_H0) ** 2 * 0.3 * amp / lam ** 2
+    point = refs.yukawa_point(r, mass_term, lam)
+    yk = point + background
+    # grid scatter inside ~8 Mpc/h is expected (Sec. 4.1); beyond a few cells it is small
+    # wherever the point mass dominates the field
+    mid = (r >= 12.0) & (point > 10 * abs(background))
+    assert mid.sum() >= 3
+    assert np.abs(line[mid] / yk[mid] - 1).max() < 0.02
+    # at 1e-4 the field is linear down to the grid scale (Sec. 4.1): the periodic linear
+    # solution agrees to the size of the non-linearity, u(0) ~ -0.07
+    if fbar == 1e-4:
+        ulin = refs.linear_solution(beta * 0.3 * delta, h, bC / 2)
+        assert np.abs(u - ulin).max() < 0.1 * np.abs(ulin).max()
+
+
+def test_gaussian_sphere_is_screened():
+    """|fbar| = 1e-6, Gaussian of the point mass's mass (Sec. 4.1): the linear solution
+    exceeds |fbar| at the centre, i.e. would flip the sign of f_R; the non-linear
+    field stays negative and below the linear prediction."""
+    g = GOLD["gaussian_sphere"]
+    N, box = 64, 128.0  # same 2 Mpc/h cells as the paper's 128^3 / 256 Mpc/h grid
+    h = box / N
+    cells = GOLD["point_mass"]["amp"] * (128 ** 3 - 1) * 8.0 / h ** 3
+    c = N // 2
+    delta = synth.gaussian_sphere_delta(N, box, g["width"], cells, centre=((c + 0.5) * h,) * 3)
+    p = O.params(mesh=N, box=box, fr0_abs=g["fbar"], tol=1e-9)
+    fb, beta, C, bC = bc_of(p)
+    s, u, dfr, st = O.solve(p, delta)
+    assert s == 0
+    # the paper's statement for the point-mass Yukawa profile: it exceeds |fbar| inside ~2 Mpc/h
+    lam = math.sqrt(refs.lambda2_comoving(1.0, g["fbar"], 1, 0.3, 0.7))
+    mass_term = (1 / refs.C_OVER_H0) ** 2 * 0.3 * cells * h ** 3 / (4 * math.pi)
+    rr = np.linspace(0.5, 5.0, 4501)
+    r_star = rr[np.argmin(np.abs(refs.yukawa_point(rr, mass_term, lam) - fb))]
+    assert abs(r_star / g["linear_exceeds_fbar_below_r"] - 1) < 0.1
+    ulin = refs.linear_solution(beta * 0.3 * delta, h, bC / 2)
+    assert -fb * ulin[c, c, c] > fb
+    assert (-fb * np.exp(u) < 0).all()
+    assert 0 < dfr[c, c, c] < fb and dfr[c, c, c] < -fb * ulin[c, c, c]
+
+
+def test_deeply_screened_core_balance():
+    """Inside a large dense sphere grad e^u vanishes and the curvature term balances the
+    density: e^{-u/(n+1)} - 1 = Omega_m a^-3 delta / C (the GR limit of Eq. u_field_eq)."""
+    N, box = 32, 100.0
+    h = box / N
+    x = (np.arange(N) + 0.5) * h - box / 2
+    r = np.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    delta = 200.0 * 0.5 * (1 - np.tanh((r - 20.0) / 3.0))
+    delta -= delta.mean()
+    p = O.params(mesh=N, box=box, fr0_abs=1e-6, tol=1e-10)
+    fb, beta, C, bC = bc_of(p)
+    s, u, _, _ = O.solve(p, delta)
+    assert s == 0
+    core = r < 8.0
+    lhs = np.exp(-u[core] / 2) - 1
+    rhs = 0.3 * delta[core] / C
+    assert np.abs(lhs / rhs - 1).max() < 0.01
+
+
+# ------------------------------------------------------------------------ T8 invariants
+
+def _cfg1_delta(N=32, seed=1, rms=1.0, halos=0):
+    pos = synth.clustered_load(N, 100.0, rms=rms, seed=seed, n_halos=halos).numpy()
+    return O.density_contrast(O.cic_assign(N, 100.0, pos))
+
+
+def test_invariants_on_clustered_load():
+    delta = _cfg1_delta(32, rms=5.0, halos=20)
+    assert abs(delta.sum()) < 1e-9 * np.abs(delta).sum()
+    p = O.params(mesh=32, fr0_abs=1e-6, tol=1e-10)
+    fb, beta, C, bC = bc_of(p)
+    s, u, dfr, st = O.solve(p, delta)
+    assert s == 0
+    hist = np.array(st.res_hist[:st.vcycles])
+    assert np.all(np.diff(hist) < 0)  # monotone residual decrease per V-cycle
+    f = beta * 0.3 * delta
+    rmax = O.residual_max(u, f, 100.0 / 32, bC)
+    # flux terms telescope: sum of the curvature term equals sum f = 0 up to the residual
+    assert abs(np.mean(1 - np.exp(-u / 2))) <= rmax / bC + 1e-14
+
+
+@pytest.mark.parametrize("shift", [(16, 0, 0), (0, 8, 8), (0, 0, 16)])
+def test_shift_equivariance_bitwise(shift):
+    """Shifts that keep every level's 2x2x2 blocks and the colouring aligned commute
+    with the whole solve, bit for bit."""
+    delta = _cfg1_delta(32)
+    p = O.params(mesh=32, max_vcycles=6, tol=1e-30)
+    _, u1, _, _ = O.solve(p, delta)
+    _, u2, _, _ = O.solve(p, np.roll(delta, shift, axis=(0, 1, 2)))
+    assert np.array_equal(np.roll(u1, shift, axis=(0, 1, 2)), u2)
+
+
+def test_injection_prolongation_also_converges():
+    delta = _cfg1_delta(32)
+    s, u, _, st = O.solve(O.params(mesh=32, prolong=1, tol=1e-10), delta)
+    s2, u2, _, st2 = O.solve(O.params(mesh=32, prolong=0, tol=1e-10), delta)
+    assert s == 0 and s2 == 0
+    assert np.abs(u - u2).max() < 1e-8
+
+
+def test_nonconvergence_and_nonfinite_status():
+    delta = _cfg1_delta(32)
+    s, u, _, st = O.solve(O.params(mesh=32, max_vcycles=1), delta)
+    assert s == 1 and st.vcycles == 1
+    bad = delta.copy()
+    bad[1, 2, 3] = np.nan
+    s, u, _, st = O.solve(O.params(mesh=32), bad)
+    assert s == -3
+
+
+# ------------------------------------------------------------------------ T9 fifth force
+
+def test_fifth_force_uniform_is_zero():
+    p = O.params(mesh=16)
+    pos = np.random.default_rng(8).uniform(0, 100, (200, 3)).astype(np.float32)
+    acc = O.fifth_force(p, np.zeros((16, 16, 16)), pos)
+    assert np.abs(acc).max() == 0.0
+
+
+def test_fifth_force_sinusoid_closed_form():
+    """u with f_R = fbar_R (1 + eps sin(2 pi x / L)) exactly; the central difference of a
+    sinusoid is sin(kh)/h times its cosine, CIC-interpolated (linear in each axis)."""
+    N, box, a = 16, 100.0, 0.8
+    p = O.params(mesh=N, box=box, a=a)
+    fb, _, _, _ = bc_of(p)
+    h = box / N
+    eps = 0.01
+    x = (np.arange(N) + 0.5) * h
+    k = 2 * np.pi / box
+    u = np.broadcast_to(np.log1p(eps * np.sin(k * x))[:, None, None], (N, N, N)).copy()
+    rng = np.random.default_rng(9)
+    pos = rng.uniform(0, box, (300, 3)).astype(np.float32)
+    acc = O.fifth_force(p, u, pos)
+    # grad f_R at centres: -fbar eps cos(k x) sin(k h)/h ; CIC interpolation in x
+    gc = -fb * eps * np.cos(k * x) * math.sin(k * h) / h
+    xi = pos[:, 0].astype(np.float64) / h - 0.5
+    i0 = np.floor(xi).astype(int)
+    t = xi - i0
+    gi = (1 - t) * gc[i0 % N] + t * gc[(i0 + 1) % N]
+    pref = refs.C_OVER_H0 ** 0 * (299792.458 ** 2) / (2 * a)
+    assert np.allclose(acc[:, 0], pref * gi, rtol=1e-10, atol=1e-12 * np.abs(pref * gi).max())
+    assert np.abs(acc[:, 1:]).max() < 1e-9 * np.abs(acc[:, 0]).max()
+
+
+def test_assignment_gather_adjointness():
+    """<assign(w), g> = <w, gather(g)> for the shared CIC weights (gather via the force
+    of a field whose gradient is known cell by cell is not needed: use a linear u)."""
+    N, box = 8, 8.0
+    rng = np.random.default_rng(10)
+    pos = rng.uniform(0, box, (50, 3)).astype(np.float32)
+    w = rng.uniform(0.1, 1.0, 50)
+    m = O.cic_assign(N, box, pos, w)
+    # gather a cell field G through the force routine: choose f_R whose x-gradient is G
+    # is awkward; instead check the assignment's transpose directly with unit vectors
+    for c in [(0, 0, 0), (3, 4, 5), (7, 7, 7)]:
+        G = np.zeros((N, N, N))
+        G[c] = 1.0
+        # weight of particle p on cell c, from single-particle assignments
+        wp = np.array([O.cic_assign(N, box, pos[i:i + 1])[c] for i in range(50)])
+        assert (m * G).sum() == pytest.approx((w * wp).sum(), rel=1e-13)

@@ -1,0 +1,166 @@
+/*
+ * mgfr.h -- C ABI of the MI355X f(R) field solver.
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the per-step
+ * solve of the Hu-Sawicki f(R) scalar field of Puchwein, Baldi & Springel
+ * (2013), "Modified Gravity-GADGET":
+ *
+ *   1. cloud-in-cell mass assignment of particles onto a periodic mesh
+ *      (Sec. 3.1);
+ *   2. the non-linear field equation for u = ln(f_R / fbar_R) (Sec. 3.2,
+ *      Eqs. fR_u, u_field_eq, u_discrete_field_eq) solved by FAS multigrid
+ *      V-cycles with red-black Newton-Gauss-Seidel smoothing (Sec. 3.3,
+ *      Eq. iterative_correction, Eq. fine_correction, steps 1-8);
+ *   3. the fifth force a_MG = (c^2/2) grad f_R (Sec. 2, Eq. modgrav_accel)
+ *      interpolated back to the particles.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller; the
+ *   library never frees or keeps it beyond the call.  Work is enqueued on
+ *   the HIP stream given to mgfr_create (a hipStream_t passed as void*;
+ *   NULL = the legacy default stream).  Calls return when their results are
+ *   ready on that stream (mgfr_solve synchronises once per V-cycle to test
+ *   convergence; the other calls do not synchronise).
+ * - Meshes are N^3 float64 arrays in C order: index (i*N + j)*N + k with i
+ *   along x, k along z (fastest).  Cell (i,j,k) covers [ih,(i+1)h) x ... with
+ *   h = box/N, centre ((i+1/2)h, ...).  Boundaries are periodic.
+ * - Positions are float32 [np][3] comoving Mpc/h; any real value is wrapped
+ *   into the box.
+ * - The library owns only its context workspace (level hierarchy, scratch),
+ *   allocated in mgfr_create and freed in mgfr_destroy.  mgfr_solve,
+ *   mgfr_assign_density and mgfr_fifth_force allocate nothing.
+ * - Return codes: 0 OK, 1 not converged (outputs valid), negative = error;
+ *   on error the message is available from mgfr_last_error() (thread-local)
+ *   and caller buffers may have been partly written only where stated.
+ * - One context must not be used from two host threads at once.
+ */
+#ifndef MGFR_H
+#define MGFR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGFR_OK 0
+#define MGFR_NOT_CONVERGED 1
+#define MGFR_ERR_ARG (-1)       /* invalid argument (message says which) */
+#define MGFR_ERR_HIP (-2)       /* a HIP runtime call failed */
+#define MGFR_ERR_NONFINITE (-3) /* NaN/Inf in an input or in the iteration */
+#define MGFR_ERR_OOM (-4)       /* device allocation failed */
+
+#define MGFR_PROLONG_LINEAR 0 /* parent value + central-difference gradient (Sec. 3.3) */
+#define MGFR_PROLONG_INJECT 1 /* straight injection (Sec. 3.3) */
+
+#define MGFR_FP64 0  /* every level and sweep in float64 */
+#define MGFR_MIXED 1 /* float32 correction V-cycles inside a float64 defect-correction loop */
+
+#define MGFR_NN_NONE 0   /* initial guess = the u passed in */
+#define MGFR_NN_COARSE 1 /* initial guess from the learned network at the N/4 level */
+
+#define MGFR_MAX_HIST 256
+
+/* Problem and solver parameters (Sec. 2 model, Sec. 3.3 solver). */
+typedef struct mgfr_params {
+    double box;      /* comoving box side L in Mpc/h, > 0 */
+    double a;        /* scale factor, > 0 */
+    double omega_m;  /* matter density parameter, > 0 */
+    double omega_l;  /* vacuum density parameter, >= 0 */
+    double fr0_abs;  /* |fbar_R0| > 0 (the paper's fbar_R0 is negative) */
+    int n;           /* Hu-Sawicki exponent n >= 1 (the paper runs n = 1) */
+    int mesh;        /* N: cells per side, a power of two, 8 <= N <= 2048 */
+    int refine_levels; /* must be 0 for the uniform-mesh context */
+    double tol;      /* accept when max|f - L(u)| / D <= tol, D = max|f| (Sec. 3.3 step 8); > 0 */
+    int pre_smooth;  /* red-black sweeps before restriction, >= 0 */
+    int post_smooth; /* red-black sweeps after the correction, >= 0 */
+    int coarse_sweeps; /* sweeps on the 4^3 coarsest grid, >= 1 */
+    int max_vcycles; /* V-cycle limit, >= 0 */
+    int prolong;     /* MGFR_PROLONG_LINEAR or MGFR_PROLONG_INJECT */
+    int precision;   /* MGFR_FP64 or MGFR_MIXED */
+    int nn_mode;     /* MGFR_NN_NONE or MGFR_NN_COARSE */
+    double max_du;   /* limit on |Newton step| per cell update; <= 0 disables the limit */
+} mgfr_params;
+
+/* Per-solve report. */
+typedef struct mgfr_stats {
+    int status;       /* the return code of the solve */
+    int vcycles;      /* V-cycles run (FP64) or inner V-cycles (mixed) */
+    int outer_iters;  /* float64 defect-correction iterations (mixed), else = vcycles */
+    int fell_back;    /* 1 if the mixed/learned solve restarted as plain FP64 from u = 0 */
+    double res0;      /* relative max residual of the initial guess */
+    double res;       /* relative max residual of the returned u */
+    double scale;     /* D, the residual normalisation */
+    double l2res;     /* relative rms residual of the returned u */
+    double res_hist[MGFR_MAX_HIST]; /* relative max residual after each (outer) cycle */
+    double t_solve_ms;   /* device time of the solve between two HIP events */
+    double t_sweep_ms;   /* summed HIP-event time of finest-level smoothing launches (timing on) */
+    int n_sweep_launches; /* number of launches in t_sweep_ms */
+    double t_nn_ms;      /* HIP-event time of the network warm start, if any */
+} mgfr_stats;
+
+typedef struct mgfr_ctx mgfr_ctx;
+
+/* Background quantities of Sec. 2 for these parameters: |fbar_R(a)|,
+ * beta = a^2 (H0/c)^2 / |fbar_R(a)| in (h/Mpc)^2 and C = Omega_m a^-3 + 4 Omega_L.
+ * Host only; returns MGFR_ERR_ARG on invalid parameters. */
+int mgfr_background(const mgfr_params *p, double *fbar, double *beta, double *C);
+
+/* Validate p and allocate the level hierarchy for an N^3 mesh on the current
+ * HIP device.  stream: hipStream_t as void* (NULL = default stream).
+ * Errors: MGFR_ERR_ARG, MGFR_ERR_OOM, MGFR_ERR_HIP; *out is NULL on error. */
+int mgfr_create(const mgfr_params *p, void *stream, mgfr_ctx **out);
+
+/* Free the context (NULL is allowed). */
+void mgfr_destroy(mgfr_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+int mgfr_set_stream(mgfr_ctx *ctx, void *stream);
+
+/* Turn per-launch HIP-event timing of the finest-level smoothing kernel on
+ * or off (reported in mgfr_stats.t_sweep_ms). */
+int mgfr_set_timing(mgfr_ctx *ctx, int on);
+
+/* Cloud-in-cell assignment (Sec. 3.1) of np particles onto the N^3 mesh and
+ * delta = m / m_bar - 1 with m_bar the mean cell mass of the assignment.
+ * pos: float32 [np][3]; mass: float64 [np] or NULL for equal masses;
+ * delta: float64 [N^3] output.  np >= 1.  Non-finite positions give
+ * MGFR_ERR_NONFINITE (delta then holds unspecified values). */
+int mgfr_assign_density(mgfr_ctx *ctx, const float *pos, const double *mass, int64_t np,
+                        double *delta);
+
+/* Solve L(u) = f for u (Sec. 3.2 Eq. u_discrete_field_eq; Sec. 3.3).
+ * delta: float64 [N^3] density contrast (input, unchanged);
+ * u: float64 [N^3], in: initial guess (zeros = the background, or the
+ *    previous step's solution, Sec. 3.3 step 2), out: the solution;
+ * dfr: float64 [N^3] or NULL, out: delta f_R = fbar_R (e^u - 1);
+ * st: may be NULL.
+ * Returns MGFR_OK when the relative max residual is <= tol,
+ * MGFR_NOT_CONVERGED after max_vcycles (u, dfr valid), MGFR_ERR_NONFINITE
+ * if delta or the iteration is not finite. */
+int mgfr_solve(mgfr_ctx *ctx, const double *delta, double *u, double *dfr, mgfr_stats *st);
+
+/* Fifth force a_MG = c^2/(2a) grad_x f_R (Sec. 2, Eq. modgrav_accel; c in
+ * km/s, x comoving Mpc/h, so acc is in (km/s)^2 h/Mpc), with f_R = fbar_R e^u,
+ * the gradient a two-point central difference at cell centres, interpolated
+ * to the particles with cloud-in-cell weights.
+ * u: float64 [N^3]; pos: float32 [np][3]; acc: float32 [np][3] output. */
+int mgfr_fifth_force(mgfr_ctx *ctx, const double *u, const float *pos, int64_t np, float *acc);
+
+/* Per-step entry points (Sec. 3.3), used to check single steps.
+ * mgfr_ngs_sweep: `sweeps` red-black sweeps on the finest level, u updated
+ * in place, f = the source of L(u) = f.  mgfr_vcycle: one V-cycle on u with
+ * source f.  mgfr_residual: r = f - L(u) on the finest level. */
+int mgfr_ngs_sweep(mgfr_ctx *ctx, double *u, const double *f, int sweeps);
+int mgfr_vcycle(mgfr_ctx *ctx, double *u, const double *f);
+int mgfr_residual(mgfr_ctx *ctx, const double *u, const double *f, double *r);
+
+/* Last error message of this host thread ("" if none). */
+const char *mgfr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGFR_H */

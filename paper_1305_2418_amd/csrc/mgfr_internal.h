@@ -1,0 +1,103 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mgfr.h"
+
+namespace mgfr {
+
+constexpr double kCOverH0 = 2997.92458;  // c/H0 in Mpc/h
+constexpr double kCkms = 299792.458;     // c in km/s
+constexpr int kTailN = 16;               // levels with N <= kTailN run inside one workgroup
+constexpr int kBlock = 256;
+constexpr int kTailThreads = 1024;
+constexpr int kMaxLevels = 12;
+
+// Constants of the dimensionless operator on one level.
+struct OpConst {
+    double ih2;     // 1/h^2 of the level
+    double bC;      // beta * C
+    double q;       // 1/(n+1)
+    double max_du;  // Newton step limit (<= 0: none)
+};
+
+struct Level {
+    int N = 0, lg = 0;
+    double h = 0;
+    double *u = nullptr, *f = nullptr, *ubar = nullptr;
+    // float32 mirrors for the mixed-precision inner cycle
+    float *e32 = nullptr, *r32 = nullptr, *u32 = nullptr, *ebar32 = nullptr;
+};
+
+struct Timer {
+    std::vector<hipEvent_t> ev;
+    int used = 0;
+};
+
+}  // namespace mgfr
+
+struct mgfr_ctx {
+    mgfr_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double fbar = 0, beta = 0, C = 0, bC = 0, q = 0;
+    int nlev = 0;
+    mgfr::Level lev[mgfr::kMaxLevels];
+    // reduction scratch
+    double *partial = nullptr;  // [2 * nparts]
+    int nparts = 0;
+    double *dscal = nullptr;    // device scalars [8]
+    double *hscal = nullptr;    // pinned host scalars [8]
+    int *dflag = nullptr;       // device flag
+    // mixed precision float64 scratch
+    double *r64 = nullptr;
+    // timing
+    bool timing = false;
+    mgfr::Timer sweep_timer;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
+    // learned warm start (owned by the network module)
+    void *nn = nullptr;
+};
+
+namespace mgfr {
+
+int set_error(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define MGFR_HIP(call)                                                     \
+    do {                                                                   \
+        hipError_t _e = (call);                                            \
+        if (_e != hipSuccess) return mgfr::hip_fail(_e, #call, __FILE__, __LINE__); \
+    } while (0)
+
+inline OpConst level_const(const mgfr_ctx *c, int l)
+{
+    OpConst k;
+    k.ih2 = 1.0 / (c->lev[l].h * c->lev[l].h);
+    k.bC = c->bC;
+    k.q = c->q;
+    k.max_du = c->p.max_du;
+    return k;
+}
+
+// launch helpers implemented in mgfr_solver.hip
+int launch_sweep64(mgfr_ctx *c, int l, double *u, const double *f, int sweeps, bool timed);
+int launch_residual_norm64(mgfr_ctx *c, int l, const double *u, const double *f, double *rmax,
+                           double *rsumsq);
+int vcycle64(mgfr_ctx *c, int l);
+
+// mixed precision (mgfr_mixed.hip)
+int mixed_alloc(mgfr_ctx *c);
+int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D);
+
+// learned warm start (mgfr_nn.hip)
+int nn_warm_start(mgfr_ctx *c, const double *delta, double *u, double *t_ms);
+void nn_free(mgfr_ctx *c);
+
+}  // namespace mgfr

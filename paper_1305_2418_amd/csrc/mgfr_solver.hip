@@ -1,0 +1,826 @@
+// FP64 multigrid path of the f(R) field solve on gfx950.
+//
+// Operator (Sec. 3.2, Eq. u_discrete_field_eq, multiplied by a^2 to the
+// comoving dimensionless form):
+//   L_c(u) = (1/h^2) sum_nb (e^{u_nb} + e^{u_c})/2 (u_nb - u_c) - bC (1 - e^{-q u_c})
+//   f_c    = beta Omega_m a^-3 delta_c,      q = 1/(n+1)
+// Smoother: red-black Newton-Gauss-Seidel (Sec. 3.3, Eq. iterative_correction).
+// Cycle: FAS V-cycle with 8-daughter-mean restriction, coarse source
+// f_2h = L_2h(R u) + R(f - L_h u) and correction u += P(u_2h - R u)
+// (Sec. 3.3, Eq. fine_correction), down to a 4^3 grid.
+//
+// Memory layout: every level is a dense N^3 float64 array in C order
+// (k fastest).  Index arithmetic uses N = 2^lg.
+#include "mgfr_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace mgfr {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what, const char *file, int line)
+{
+    return set_error(e == hipErrorOutOfMemory ? MGFR_ERR_OOM : MGFR_ERR_HIP, "%s failed: %s (%s:%d)", what,
+                     hipGetErrorString(e), file, line);
+}
+
+// ------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ size_t cidx(int i, int j, int k, int lg)
+{
+    return (((((size_t)i) << lg) + (size_t)j) << lg) + (size_t)k;
+}
+
+__device__ __forceinline__ double nanmax(double a, double b)
+{
+    return (a != a || a > b) ? a : b;
+}
+
+// Newton-Gauss-Seidel step for one cell from its value, its six neighbours and
+// its source: -(L_c - f_c) / (dL_c/du_c), optionally limited to |du| <= max_du.
+// With S1 = sum (u_n - u_c), S2 = sum e^{u_n}, S3 = sum e^{u_n} (u_n - u_c):
+//   flux sum          = (S3 + e^{u_c} S1) / 2
+//   d(flux sum)/du_c  = (e^{u_c} (S1 - 6) - S2) / 2
+__device__ __forceinline__ double ngs_step(double uc, double n0, double n1, double n2, double n3,
+                                           double n4, double n5, double f, const OpConst &k)
+{
+    double ec = exp(uc);
+    double d0 = n0 - uc, d1 = n1 - uc, d2 = n2 - uc, d3 = n3 - uc, d4 = n4 - uc, d5 = n5 - uc;
+    double e0 = exp(n0), e1 = exp(n1), e2 = exp(n2), e3 = exp(n3), e4 = exp(n4), e5 = exp(n5);
+    double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
+    double S2 = ((e0 + e1) + (e2 + e3)) + (e4 + e5);
+    double S3 = ((e0 * d0 + e1 * d1) + (e2 * d2 + e3 * d3)) + (e4 * d4 + e5 * d5);
+    double em = expm1(-k.q * uc);
+    double L = k.ih2 * 0.5 * (S3 + ec * S1) + k.bC * em;
+    double J = k.ih2 * 0.5 * (ec * (S1 - 6.0) - S2) - k.bC * k.q * (1.0 + em);
+    double du = -(L - f) / J;
+    if (k.max_du > 0.0) du = fmin(fmax(du, -k.max_du), k.max_du);
+    return du;
+}
+
+__device__ __forceinline__ double op_value(double uc, double n0, double n1, double n2, double n3,
+                                           double n4, double n5, const OpConst &k)
+{
+    double ec = exp(uc);
+    double d0 = n0 - uc, d1 = n1 - uc, d2 = n2 - uc, d3 = n3 - uc, d4 = n4 - uc, d5 = n5 - uc;
+    double e0 = exp(n0), e1 = exp(n1), e2 = exp(n2), e3 = exp(n3), e4 = exp(n4), e5 = exp(n5);
+    double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
+    double S3 = ((e0 * d0 + e1 * d1) + (e2 * d2 + e3 * d3)) + (e4 * d4 + e5 * d5);
+    return k.ih2 * 0.5 * (S3 + ec * S1) + k.bC * expm1(-k.q * uc);
+}
+
+// L_c at (i,j,k) of a periodic 2^lg mesh.
+__device__ __forceinline__ double op_at(const double *__restrict__ u, int i, int j, int k, int lg,
+                                        const OpConst &kc)
+{
+    const int m = (1 << lg) - 1;
+    double uc = u[cidx(i, j, k, lg)];
+    return op_value(uc, u[cidx((i + 1) & m, j, k, lg)], u[cidx((i - 1) & m, j, k, lg)],
+                    u[cidx(i, (j + 1) & m, k, lg)], u[cidx(i, (j - 1) & m, k, lg)],
+                    u[cidx(i, j, (k + 1) & m, lg)], u[cidx(i, j, (k - 1) & m, lg)], kc);
+}
+
+// Update one cell of colour `colour` given its flat index t over that colour's cells.
+__device__ __forceinline__ void sweep_cell(double *__restrict__ u, const double *__restrict__ f, size_t t,
+                                           int lg, int colour, const OpConst &kc)
+{
+    const int m = (1 << lg) - 1;
+    int mh = (int)(t & (size_t)((1 << (lg - 1)) - 1));
+    size_t row = t >> (lg - 1);
+    int j = (int)(row & m);
+    int i = (int)(row >> lg);
+    int k = 2 * mh + ((i + j + colour) & 1);
+    size_t c = cidx(i, j, k, lg);
+    double uc = u[c];
+    double du = ngs_step(uc, u[cidx((i + 1) & m, j, k, lg)], u[cidx((i - 1) & m, j, k, lg)],
+                         u[cidx(i, (j + 1) & m, k, lg)], u[cidx(i, (j - 1) & m, k, lg)],
+                         u[cidx(i, j, (k + 1) & m, lg)], u[cidx(i, j, (k - 1) & m, lg)], f[c], kc);
+    u[c] = uc + du;
+}
+
+// Residuals r = f - L(u) at the 8 daughters of coarse cell (I,J,K) and their
+// mean values of u and r.  The 2x2x2 block plus its 24 face neighbours are
+// loaded once and each is exponentiated once.
+struct BlockRes {
+    double r[8];
+    double umean, rmean;
+};
+
+__device__ __forceinline__ void block_residuals(const double *__restrict__ u, const double *__restrict__ f,
+                                                int I, int J, int K, int lg, const OpConst &kc, BlockRes &out)
+{
+    const int m = (1 << lg) - 1;
+    const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
+    double B[2][2][2], EB[2][2][2];
+    double Xm[2][2], Xp[2][2], Ym[2][2], Yp[2][2], Zm[2][2], Zp[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                B[a][b][c] = u[cidx(i0 + a, j0 + b, k0 + c, lg)];
+                EB[a][b][c] = exp(B[a][b][c]);
+            }
+            Xm[a][b] = u[cidx((i0 - 1) & m, j0 + a, k0 + b, lg)];
+            Xp[a][b] = u[cidx((i0 + 2) & m, j0 + a, k0 + b, lg)];
+            Ym[a][b] = u[cidx(i0 + a, (j0 - 1) & m, k0 + b, lg)];
+            Yp[a][b] = u[cidx(i0 + a, (j0 + 2) & m, k0 + b, lg)];
+            Zm[a][b] = u[cidx(i0 + a, j0 + b, (k0 - 1) & m, lg)];
+            Zp[a][b] = u[cidx(i0 + a, j0 + b, (k0 + 2) & m, lg)];
+        }
+    double su = 0.0, sr = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double uc = B[a][b][c], ec = EB[a][b][c];
+                double nx0 = a ? Xp[b][c] : B[1][b][c];       // +x
+                double nx1 = a ? B[0][b][c] : Xm[b][c];       // -x
+                double ny0 = b ? Yp[a][c] : B[a][1][c];
+                double ny1 = b ? B[a][0][c] : Ym[a][c];
+                double nz0 = c ? Zp[a][b] : B[a][b][1];
+                double nz1 = c ? B[a][b][0] : Zm[a][b];
+                double ex0 = a ? exp(nx0) : EB[1][b][c];
+                double ex1 = a ? EB[0][b][c] : exp(nx1);
+                double ey0 = b ? exp(ny0) : EB[a][1][c];
+                double ey1 = b ? EB[a][0][c] : exp(ny1);
+                double ez0 = c ? exp(nz0) : EB[a][b][1];
+                double ez1 = c ? EB[a][b][0] : exp(nz1);
+                double d0 = nx0 - uc, d1 = nx1 - uc, d2 = ny0 - uc, d3 = ny1 - uc, d4 = nz0 - uc, d5 = nz1 - uc;
+                double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
+                double S3 = ((ex0 * d0 + ex1 * d1) + (ey0 * d2 + ey1 * d3)) + (ez0 * d4 + ez1 * d5);
+                double L = kc.ih2 * 0.5 * (S3 + ec * S1) + kc.bC * expm1(-kc.q * uc);
+                double r = f[cidx(i0 + a, j0 + b, k0 + c, lg)] - L;
+                out.r[(a * 2 + b) * 2 + c] = r;
+                su += uc;
+                sr += r;
+            }
+    out.umean = su / 8.0;
+    out.rmean = sr / 8.0;
+}
+
+// Linear (mode 0) or injected (mode 1) correction at fine cell (i,j,k):
+// P(uc - ubar) with the central-difference gradient at the parent centre.
+__device__ __forceinline__ double prolong_value(const double *__restrict__ uc, const double *__restrict__ ub,
+                                                int i, int j, int k, int lgc, int mode)
+{
+    const int m = (1 << lgc) - 1;
+    int I = i >> 1, J = j >> 1, K = k >> 1;
+    size_t P = cidx(I, J, K, lgc);
+    double v = uc[P] - ub[P];
+    if (mode == 0) {
+        size_t xp = cidx((I + 1) & m, J, K, lgc), xm = cidx((I - 1) & m, J, K, lgc);
+        size_t yp = cidx(I, (J + 1) & m, K, lgc), ym = cidx(I, (J - 1) & m, K, lgc);
+        size_t zp = cidx(I, J, (K + 1) & m, lgc), zm = cidx(I, J, (K - 1) & m, lgc);
+        double gx = (uc[xp] - ub[xp]) - (uc[xm] - ub[xm]);
+        double gy = (uc[yp] - ub[yp]) - (uc[ym] - ub[ym]);
+        double gz = (uc[zp] - ub[zp]) - (uc[zm] - ub[zm]);
+        double sx = (i & 1) ? 0.125 : -0.125, sy = (j & 1) ? 0.125 : -0.125, sz = (k & 1) ? 0.125 : -0.125;
+        v += sx * gx;
+        v += sy * gy;
+        v += sz * gz;
+    }
+    return v;
+}
+
+// --------------------------------------------------------------- grid kernels
+
+__global__ __launch_bounds__(kBlock) void k_sweep_half(double *__restrict__ u, const double *__restrict__ f,
+                                                         int lg, int colour, OpConst kc)
+{
+    size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    sweep_cell(u, f, t, lg, colour, kc);
+}
+
+// rbar -> fc, R u -> ubar_c
+__global__ __launch_bounds__(kBlock) void k_residual_restrict(const double *__restrict__ u,
+                                                                const double *__restrict__ f, int lg,
+                                                                OpConst kc, double *__restrict__ ubar_c,
+                                                                double *__restrict__ f_c)
+{
+    const int lgc = lg - 1;
+    size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    int K = (int)(t & ((1u << lgc) - 1));
+    int J = (int)((t >> lgc) & ((1u << lgc) - 1));
+    int I = (int)(t >> (2 * lgc));
+    BlockRes br;
+    block_residuals(u, f, I, J, K, lg, kc, br);
+    ubar_c[t] = br.umean;
+    f_c[t] = br.rmean;
+}
+
+// f_c += L_c(ubar), u_c = ubar
+__global__ __launch_bounds__(kBlock) void k_coarse_rhs(const double *__restrict__ ubar, int lg, OpConst kc,
+                                                         double *__restrict__ fc, double *__restrict__ uc)
+{
+    size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int m = (1 << lg) - 1;
+    int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
+    fc[t] += op_at(ubar, i, j, k, lg, kc);
+    uc[t] = ubar[t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_prolong_add(double *__restrict__ u, const double *__restrict__ uc,
+                                                          const double *__restrict__ ub, int lg, int mode)
+{
+    size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int m = (1 << lg) - 1;
+    int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
+    u[t] += prolong_value(uc, ub, i, j, k, lg - 1, mode);
+}
+
+template <int BS>
+__device__ __forceinline__ void block_reduce_max_sum(double &mx, double &sm, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = nanmax(mx, __shfl_xor(mx, o, 64));
+        sm += __shfl_xor(sm, o, 64);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        sh[w] = mx;
+        sh[BS / 64 + w] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < BS / 64; ++i) {
+            mx = nanmax(mx, sh[i]);
+            sm += sh[BS / 64 + i];
+        }
+    }
+}
+
+// per-block max |r| and sum r^2 over the fine level (thread per 2x2x2 block)
+__global__ __launch_bounds__(kBlock) void k_residual_norm(const double *__restrict__ u,
+                                                            const double *__restrict__ f, int lg, OpConst kc,
+                                                            double *__restrict__ partial, int nparts)
+{
+    __shared__ double sh[2 * kBlock / 64];
+    const int lgc = lg - 1;
+    const size_t nblk = (size_t)1 << (3 * lgc);
+    double mx = 0.0, sm = 0.0;
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < nblk; t += (size_t)gridDim.x * kBlock) {
+        int K = (int)(t & ((1u << lgc) - 1));
+        int J = (int)((t >> lgc) & ((1u << lgc) - 1));
+        int I = (int)(t >> (2 * lgc));
+        BlockRes br;
+        block_residuals(u, f, I, J, K, lg, kc, br);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            mx = nanmax(mx, fabs(br.r[c]));
+            sm += br.r[c] * br.r[c];
+        }
+    }
+    block_reduce_max_sum<kBlock>(mx, sm, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = mx;
+        partial[nparts + blockIdx.x] = sm;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual_field(const double *__restrict__ u,
+                                                             const double *__restrict__ f, int lg, OpConst kc,
+                                                             double *__restrict__ r)
+{
+    size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int m = (1 << lg) - 1;
+    int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
+    r[t] = f[t] - op_at(u, i, j, k, lg, kc);
+}
+
+// final reduction of nparts partials -> out[0] = max, out[1] = sum
+__global__ __launch_bounds__(1024) void k_final_reduce(const double *__restrict__ partial, int nparts,
+                                                        double *__restrict__ out)
+{
+    __shared__ double sh[2 * 1024 / 64];
+    double mx = 0.0, sm = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 1024) {
+        mx = nanmax(mx, partial[i]);
+        sm += partial[nparts + i];
+    }
+    block_reduce_max_sum<1024>(mx, sm, sh);
+    if (threadIdx.x == 0) {
+        out[0] = mx;
+        out[1] = sm;
+    }
+}
+
+// f = s * delta with per-block max |f| partials
+__global__ __launch_bounds__(kBlock) void k_source(const double *__restrict__ delta, double s, size_t n,
+                                                     double *__restrict__ f, double *__restrict__ partial,
+                                                     int nparts)
+{
+    __shared__ double sh[2 * kBlock / 64];
+    double mx = 0.0, sm = 0.0;
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock) {
+        double v = s * delta[t];
+        f[t] = v;
+        mx = nanmax(mx, fabs(v));
+    }
+    block_reduce_max_sum<kBlock>(mx, sm, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = mx;
+        partial[nparts + blockIdx.x] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dfr(const double *__restrict__ u, double fbar, size_t n,
+                                                  double *__restrict__ dfr)
+{
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock)
+        dfr[t] = -fbar * expm1(u[t]);
+}
+
+// ------------------------------------------------------------- tail kernel
+// All levels with N <= kTailN inside one workgroup: the V-cycle from level l0
+// down to the 4^3 grid and back, with workgroup barriers between steps.
+
+struct TailArgs {
+    double *u[kMaxLevels];
+    double *f[kMaxLevels];
+    double *ub[kMaxLevels];
+    double ih2[kMaxLevels];
+    int lg[kMaxLevels];
+    int l0, nlev, pre, post, coarse, mode;
+    double bC, q, max_du;
+};
+
+__device__ void tail_sweeps(const TailArgs &A, int l, int sweeps)
+{
+    OpConst kc{A.ih2[l], A.bC, A.q, A.max_du};
+    const int lg = A.lg[l];
+    const size_t half = (size_t)1 << (3 * lg - 1);
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (size_t t = threadIdx.x; t < half; t += kTailThreads) sweep_cell(A.u[l], A.f[l], t, lg, colour, kc);
+            __syncthreads();
+        }
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs A)
+{
+    for (int l = A.l0; l < A.nlev - 1; ++l) {
+        tail_sweeps(A, l, A.pre);
+        OpConst kc{A.ih2[l], A.bC, A.q, A.max_du};
+        const int lg = A.lg[l], lgc = lg - 1;
+        const size_t nc = (size_t)1 << (3 * lgc);
+        for (size_t t = threadIdx.x; t < nc; t += kTailThreads) {
+            int K = (int)(t & ((1u << lgc) - 1));
+            int J = (int)((t >> lgc) & ((1u << lgc) - 1));
+            int I = (int)(t >> (2 * lgc));
+            BlockRes br;
+            block_residuals(A.u[l], A.f[l], I, J, K, lg, kc, br);
+            A.ub[l + 1][t] = br.umean;
+            A.f[l + 1][t] = br.rmean;
+        }
+        __syncthreads();
+        OpConst kcc{A.ih2[l + 1], A.bC, A.q, A.max_du};
+        const int mc = (1 << lgc) - 1;
+        for (size_t t = threadIdx.x; t < nc; t += kTailThreads) {
+            int k = (int)(t & mc), j = (int)((t >> lgc) & mc), i = (int)(t >> (2 * lgc));
+            A.f[l + 1][t] += op_at(A.ub[l + 1], i, j, k, lgc, kcc);
+            A.u[l + 1][t] = A.ub[l + 1][t];
+        }
+        __syncthreads();
+    }
+    tail_sweeps(A, A.nlev - 1, A.coarse);
+    for (int l = A.nlev - 2; l >= A.l0; --l) {
+        const int lg = A.lg[l];
+        const size_t n = (size_t)1 << (3 * lg);
+        const int m = (1 << lg) - 1;
+        for (size_t t = threadIdx.x; t < n; t += kTailThreads) {
+            int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
+            A.u[l][t] += prolong_value(A.u[l + 1], A.ub[l + 1], i, j, k, lg - 1, A.mode);
+        }
+        __syncthreads();
+        tail_sweeps(A, l, A.post);
+    }
+}
+
+// ------------------------------------------------------------ host launches
+
+static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+int launch_sweep64(mgfr_ctx *c, int l, double *u, const double *f, int sweeps, bool timed)
+{
+    Level &L = c->lev[l];
+    OpConst kc = level_const(c, l);
+    const size_t half = (size_t)1 << (3 * L.lg - 1);
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+            if (timed) {
+                Timer &T = c->sweep_timer;
+                if (T.used + 2 > (int)T.ev.size()) {
+                    for (int e = 0; e < 16; ++e) {
+                        hipEvent_t ev;
+                        MGFR_HIP(hipEventCreate(&ev));
+                        T.ev.push_back(ev);
+                    }
+                }
+                MGFR_HIP(hipEventRecord(T.ev[T.used], c->stream));
+                k_sweep_half<<<nblocks(half), kBlock, 0, c->stream>>>(u, f, L.lg, colour, kc);
+                MGFR_HIP(hipEventRecord(T.ev[T.used + 1], c->stream));
+                T.used += 2;
+            } else {
+                k_sweep_half<<<nblocks(half), kBlock, 0, c->stream>>>(u, f, L.lg, colour, kc);
+            }
+        }
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
+}
+
+static int launch_tail(mgfr_ctx *c, int l0)
+{
+    TailArgs A;
+    memset(&A, 0, sizeof A);
+    for (int l = 0; l < c->nlev; ++l) {
+        A.u[l] = c->lev[l].u;
+        A.f[l] = c->lev[l].f;
+        A.ub[l] = c->lev[l].ubar;
+        A.ih2[l] = 1.0 / (c->lev[l].h * c->lev[l].h);
+        A.lg[l] = c->lev[l].lg;
+    }
+    A.l0 = l0;
+    A.nlev = c->nlev;
+    A.pre = c->p.pre_smooth;
+    A.post = c->p.post_smooth;
+    A.coarse = c->p.coarse_sweeps;
+    A.mode = c->p.prolong;
+    A.bC = c->bC;
+    A.q = c->q;
+    A.max_du = c->p.max_du;
+    k_tail<<<1, kTailThreads, 0, c->stream>>>(A);
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
+}
+
+int vcycle64(mgfr_ctx *c, int l)
+{
+    Level &L = c->lev[l];
+    if (L.N <= kTailN) return launch_tail(c, l);
+    int rc;
+    if ((rc = launch_sweep64(c, l, L.u, L.f, c->p.pre_smooth, l == 0 && c->timing))) return rc;
+    Level &Lc = c->lev[l + 1];
+    const size_t nc = (size_t)1 << (3 * Lc.lg);
+    k_residual_restrict<<<nblocks(nc), kBlock, 0, c->stream>>>(L.u, L.f, L.lg, level_const(c, l), Lc.ubar, Lc.f);
+    k_coarse_rhs<<<nblocks(nc), kBlock, 0, c->stream>>>(Lc.ubar, Lc.lg, level_const(c, l + 1), Lc.f, Lc.u);
+    MGFR_HIP(hipGetLastError());
+    if ((rc = vcycle64(c, l + 1))) return rc;
+    const size_t n = (size_t)1 << (3 * L.lg);
+    k_prolong_add<<<nblocks(n), kBlock, 0, c->stream>>>(L.u, Lc.u, Lc.ubar, L.lg, c->p.prolong);
+    MGFR_HIP(hipGetLastError());
+    return launch_sweep64(c, l, L.u, L.f, c->p.post_smooth, l == 0 && c->timing);
+}
+
+int launch_residual_norm64(mgfr_ctx *c, int l, const double *u, const double *f, double *rmax, double *rsumsq)
+{
+    Level &L = c->lev[l];
+    const size_t nblk = (size_t)1 << (3 * (L.lg - 1));
+    unsigned g = (unsigned)std::min<size_t>(nblocks(nblk), (size_t)c->nparts);
+    k_residual_norm<<<g, kBlock, 0, c->stream>>>(u, f, L.lg, level_const(c, l), c->partial, (int)g);
+    k_final_reduce<<<1, 1024, 0, c->stream>>>(c->partial, (int)g, c->dscal);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipMemcpyAsync(c->hscal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    MGFR_HIP(hipStreamSynchronize(c->stream));
+    *rmax = c->hscal[0];
+    *rsumsq = c->hscal[1];
+    return MGFR_OK;
+}
+
+static int collect_sweep_time(mgfr_ctx *c, mgfr_stats *st)
+{
+    Timer &T = c->sweep_timer;
+    for (int e = 0; e + 1 < T.used; e += 2) {
+        float ms = 0;
+        MGFR_HIP(hipEventElapsedTime(&ms, T.ev[e], T.ev[e + 1]));
+        if (st) {
+            st->t_sweep_ms += ms;
+            st->n_sweep_launches += 1;
+        }
+    }
+    T.used = 0;
+    return MGFR_OK;
+}
+
+// ---------------------------------------------------------------- validation
+
+static int validate(const mgfr_params *p)
+{
+    if (!p) return set_error(MGFR_ERR_ARG, "params is NULL");
+    if (!(p->box > 0) || !std::isfinite(p->box)) return set_error(MGFR_ERR_ARG, "box must be > 0");
+    if (!(p->a > 0) || !std::isfinite(p->a)) return set_error(MGFR_ERR_ARG, "a must be > 0");
+    if (!(p->omega_m > 0)) return set_error(MGFR_ERR_ARG, "omega_m must be > 0");
+    if (!(p->omega_l >= 0)) return set_error(MGFR_ERR_ARG, "omega_l must be >= 0");
+    if (!(p->fr0_abs > 0) || !std::isfinite(p->fr0_abs)) return set_error(MGFR_ERR_ARG, "fr0_abs must be > 0");
+    if (p->n < 1) return set_error(MGFR_ERR_ARG, "n must be >= 1");
+    if (p->mesh < 8 || p->mesh > 2048 || (p->mesh & (p->mesh - 1)))
+        return set_error(MGFR_ERR_ARG, "mesh must be a power of two in [8, 2048], got %d", p->mesh);
+    if (p->refine_levels != 0) return set_error(MGFR_ERR_ARG, "refine_levels must be 0 for a uniform mesh");
+    if (!(p->tol > 0)) return set_error(MGFR_ERR_ARG, "tol must be > 0");
+    if (p->pre_smooth < 0 || p->post_smooth < 0) return set_error(MGFR_ERR_ARG, "smoothing counts must be >= 0");
+    if (p->coarse_sweeps < 1) return set_error(MGFR_ERR_ARG, "coarse_sweeps must be >= 1");
+    if (p->max_vcycles < 0) return set_error(MGFR_ERR_ARG, "max_vcycles must be >= 0");
+    if (p->prolong != MGFR_PROLONG_LINEAR && p->prolong != MGFR_PROLONG_INJECT)
+        return set_error(MGFR_ERR_ARG, "prolong must be 0 (linear) or 1 (injection)");
+    if (p->precision != MGFR_FP64 && p->precision != MGFR_MIXED)
+        return set_error(MGFR_ERR_ARG, "precision must be MGFR_FP64 or MGFR_MIXED");
+    if (p->nn_mode != MGFR_NN_NONE && p->nn_mode != MGFR_NN_COARSE)
+        return set_error(MGFR_ERR_ARG, "nn_mode must be MGFR_NN_NONE or MGFR_NN_COARSE");
+    return MGFR_OK;
+}
+
+static void background(const mgfr_params *p, double *fbar, double *beta, double *C)
+{
+    // Sec. 2: R_bar = 3 H0^2 (Omega_m a^-3 + 4 Omega_L); fbar_R(a) = fbar_R0 (R_bar0/R_bar(a))^(n+1)
+    double r = 4.0 * p->omega_l / p->omega_m;
+    double a3 = 1.0 / (p->a * p->a * p->a);
+    *fbar = p->fr0_abs * std::pow((1.0 + r) / (a3 + r), p->n + 1);
+    *C = p->omega_m * a3 + 4.0 * p->omega_l;
+    *beta = p->a * p->a / (kCOverH0 * kCOverH0) / *fbar;
+}
+
+}  // namespace mgfr
+
+using namespace mgfr;
+
+// ================================================================== C ABI
+
+extern "C" const char *mgfr_last_error(void) { return g_err.c_str(); }
+
+extern "C" int mgfr_background(const mgfr_params *p, double *fbar, double *beta, double *C)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    double a, b, c;
+    background(p, &a, &b, &c);
+    if (fbar) *fbar = a;
+    if (beta) *beta = b;
+    if (C) *C = c;
+    return MGFR_OK;
+}
+
+static void free_ctx(mgfr_ctx *c)
+{
+    if (!c) return;
+    nn_free(c);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        Level &L = c->lev[l];
+        if (l > 0) (void)hipFree(L.u);
+        (void)hipFree(L.f);
+        (void)hipFree(L.ubar);
+        (void)hipFree(L.e32);
+        (void)hipFree(L.r32);
+        (void)hipFree(L.u32);
+        (void)hipFree(L.ebar32);
+    }
+    (void)hipFree(c->partial);
+    (void)hipFree(c->dscal);
+    (void)hipFree(c->dflag);
+    (void)hipFree(c->r64);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+    for (hipEvent_t e : c->sweep_timer.ev) (void)hipEventDestroy(e);
+    if (c->ev_a) (void)hipEventDestroy(c->ev_a);
+    if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+    if (c->ev_c) (void)hipEventDestroy(c->ev_c);
+    delete c;
+}
+
+static int create_impl(const mgfr_params *p, void *stream, mgfr_ctx *c)
+{
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    MGFR_HIP(hipGetDevice(&c->device));
+    background(p, &c->fbar, &c->beta, &c->C);
+    c->bC = c->beta * c->C;
+    c->q = 1.0 / (p->n + 1);
+    int N = p->mesh, lg = 0;
+    while ((1 << lg) < N) ++lg;
+    c->nlev = 0;
+    for (int n = N, l = 0; n >= 4; n /= 2, ++l) {
+        Level &L = c->lev[l];
+        L.N = n;
+        L.lg = lg - l;
+        L.h = p->box / n;
+        size_t bytes = sizeof(double) * (size_t)n * n * n;
+        MGFR_HIP(hipMalloc(&L.f, bytes));
+        if (l > 0) {
+            MGFR_HIP(hipMalloc(&L.u, bytes));
+            MGFR_HIP(hipMalloc(&L.ubar, bytes));
+        }
+        c->nlev = l + 1;
+    }
+    c->nparts = 4096;
+    MGFR_HIP(hipMalloc(&c->partial, sizeof(double) * 2 * c->nparts));
+    MGFR_HIP(hipMalloc(&c->dscal, sizeof(double) * 8));
+    MGFR_HIP(hipMalloc(&c->dflag, sizeof(int) * 4));
+    MGFR_HIP(hipHostMalloc(&c->hscal, sizeof(double) * 8, hipHostMallocDefault));
+    MGFR_HIP(hipEventCreate(&c->ev_a));
+    MGFR_HIP(hipEventCreate(&c->ev_b));
+    MGFR_HIP(hipEventCreate(&c->ev_c));
+    if (p->precision == MGFR_MIXED) {
+        int rc = mixed_alloc(c);
+        if (rc) return rc;
+    }
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_create(const mgfr_params *p, void *stream, mgfr_ctx **out)
+{
+    if (!out) return set_error(MGFR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    mgfr_ctx *c = new (std::nothrow) mgfr_ctx();
+    if (!c) return set_error(MGFR_ERR_OOM, "host allocation failed");
+    rc = create_impl(p, stream, c);
+    if (rc) {
+        free_ctx(c);
+        return rc;
+    }
+    *out = c;
+    return MGFR_OK;
+}
+
+extern "C" void mgfr_destroy(mgfr_ctx *c) { free_ctx(c); }
+
+extern "C" int mgfr_set_stream(mgfr_ctx *c, void *stream)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    c->stream = (hipStream_t)stream;
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_set_timing(mgfr_ctx *c, int on)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    c->timing = on != 0;
+    return MGFR_OK;
+}
+
+static int check_ptr(const void *p, const char *name)
+{
+    if (!p) return set_error(MGFR_ERR_ARG, "%s is NULL", name);
+    return MGFR_OK;
+}
+
+// Form f on level 0 and return D = max|f| (bC if f == 0) on the host.
+static int prepare_source(mgfr_ctx *c, const double *delta, double *D)
+{
+    Level &L0 = c->lev[0];
+    size_t n = (size_t)L0.N * L0.N * L0.N;
+    double s = c->beta * c->p.omega_m / (c->p.a * c->p.a * c->p.a);
+    unsigned g = (unsigned)std::min<size_t>(nblocks(n), (size_t)c->nparts);
+    k_source<<<g, kBlock, 0, c->stream>>>(delta, s, n, L0.f, c->partial, (int)g);
+    k_final_reduce<<<1, 1024, 0, c->stream>>>(c->partial, (int)g, c->dscal + 2);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipMemcpyAsync(c->hscal + 2, c->dscal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    MGFR_HIP(hipStreamSynchronize(c->stream));
+    double d = c->hscal[2];
+    if (!std::isfinite(d)) return set_error(MGFR_ERR_NONFINITE, "delta contains NaN or Inf");
+    *D = d > 0 ? d : c->bC;
+    return MGFR_OK;
+}
+
+static int finish(mgfr_ctx *c, double *u, double *dfr, mgfr_stats *st, int status)
+{
+    if (dfr) {
+        size_t n = (size_t)c->lev[0].N * c->lev[0].N * c->lev[0].N;
+        unsigned g = (unsigned)std::min<size_t>(nblocks(n), 8192);
+        k_dfr<<<g, kBlock, 0, c->stream>>>(u, c->fbar, n, dfr);
+        MGFR_HIP(hipGetLastError());
+    }
+    MGFR_HIP(hipEventRecord(c->ev_b, c->stream));
+    MGFR_HIP(hipEventSynchronize(c->ev_b));
+    float ms = 0;
+    MGFR_HIP(hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+    if (st) {
+        st->t_solve_ms = ms;
+        st->status = status;
+    }
+    if (status == MGFR_ERR_NONFINITE) return set_error(status, "the iteration produced NaN or Inf");
+    return status;
+}
+
+static int solve_fp64(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
+{
+    Level &L0 = c->lev[0];
+    double rmax, rsq;
+    const double ncell = (double)L0.N * L0.N * L0.N;
+    int rc = launch_residual_norm64(c, 0, u, L0.f, &rmax, &rsq);
+    if (rc) return rc;
+    double res = rmax / D;
+    st->res0 = res;
+    int cyc = 0, status;
+    for (;;) {
+        if (!std::isfinite(res)) { status = MGFR_ERR_NONFINITE; break; }
+        if (res <= c->p.tol) { status = MGFR_OK; break; }
+        if (cyc >= c->p.max_vcycles) { status = MGFR_NOT_CONVERGED; break; }
+        if ((rc = vcycle64(c, 0))) return rc;
+        if ((rc = launch_residual_norm64(c, 0, u, L0.f, &rmax, &rsq))) return rc;
+        if (c->timing && (rc = collect_sweep_time(c, st))) return rc;
+        res = rmax / D;
+        if (cyc < MGFR_MAX_HIST) st->res_hist[cyc] = res;
+        ++cyc;
+    }
+    st->vcycles = cyc;
+    st->outer_iters = cyc;
+    st->res = res;
+    st->l2res = std::sqrt(rsq / ncell) / D;
+    return status;
+}
+
+extern "C" int mgfr_solve(mgfr_ctx *c, const double *delta, double *u, double *dfr, mgfr_stats *st_out)
+{
+    int rc;
+    if ((rc = check_ptr(c, "ctx")) || (rc = check_ptr(delta, "delta")) || (rc = check_ptr(u, "u"))) return rc;
+    mgfr_stats local;
+    mgfr_stats *st = st_out ? st_out : &local;
+    memset(st, 0, sizeof *st);
+    c->lev[0].u = u;
+    c->sweep_timer.used = 0;
+    MGFR_HIP(hipEventRecord(c->ev_a, c->stream));
+    double D;
+    if ((rc = prepare_source(c, delta, &D))) {
+        st->status = rc;
+        return rc;
+    }
+    st->scale = D;
+    if (c->p.nn_mode == MGFR_NN_COARSE) {
+        double tnn = 0;
+        if ((rc = nn_warm_start(c, delta, u, &tnn))) return rc;
+        st->t_nn_ms = tnn;
+    }
+    int status;
+    if (c->p.precision == MGFR_MIXED) {
+        status = solve_mixed(c, u, st, D);
+    } else {
+        status = solve_fp64(c, u, st, D);
+    }
+    if (status < 0 && status != MGFR_ERR_NONFINITE) return status;
+    return finish(c, u, dfr, st, status);
+}
+
+extern "C" int mgfr_ngs_sweep(mgfr_ctx *c, double *u, const double *f, int sweeps)
+{
+    int rc;
+    if ((rc = check_ptr(c, "ctx")) || (rc = check_ptr(u, "u")) || (rc = check_ptr(f, "f"))) return rc;
+    if (sweeps < 0) return set_error(MGFR_ERR_ARG, "sweeps must be >= 0");
+    Level &L0 = c->lev[0];
+    const size_t half = (size_t)1 << (3 * L0.lg - 1);
+    OpConst kc = level_const(c, 0);
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+            // N >= 8 gives N^3/2 >= 256 cells per colour: whole blocks only
+            k_sweep_half<<<nblocks(half), kBlock, 0, c->stream>>>(u, f, L0.lg, colour, kc);
+        }
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipStreamSynchronize(c->stream));
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_vcycle(mgfr_ctx *c, double *u, const double *f)
+{
+    int rc;
+    if ((rc = check_ptr(c, "ctx")) || (rc = check_ptr(u, "u")) || (rc = check_ptr(f, "f"))) return rc;
+    Level &L0 = c->lev[0];
+    size_t n = (size_t)L0.N * L0.N * L0.N;
+    MGFR_HIP(hipMemcpyAsync(L0.f, f, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    L0.u = u;
+    if ((rc = vcycle64(c, 0))) return rc;
+    MGFR_HIP(hipStreamSynchronize(c->stream));
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_residual(mgfr_ctx *c, const double *u, const double *f, double *r)
+{
+    int rc;
+    if ((rc = check_ptr(c, "ctx")) || (rc = check_ptr(u, "u")) || (rc = check_ptr(f, "f")) ||
+        (rc = check_ptr(r, "r")))
+        return rc;
+    Level &L0 = c->lev[0];
+    size_t n = (size_t)L0.N * L0.N * L0.N;
+    k_residual_field<<<nblocks(n), kBlock, 0, c->stream>>>(u, f, L0.lg, level_const(c, 0), r);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipStreamSynchronize(c->stream));
+    return MGFR_OK;
+}

@@ -1,0 +1,263 @@
+"""Thin ctypes binding of the HIP library ``libmgfr.so`` (C ABI in include/mgfr.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Arrays are torch tensors on the HIP device; the binding checks
+dtype, shape, contiguity and device, passes raw pointers and the current
+torch stream, and turns negative return codes into exceptions.  There is no
+CPU fallback: a missing library raises at import of the first call.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmgfr.so")
+
+MGFR_OK, MGFR_NOT_CONVERGED = 0, 1
+MGFR_ERR_ARG, MGFR_ERR_HIP, MGFR_ERR_NONFINITE, MGFR_ERR_OOM = -1, -2, -3, -4
+PROLONG_LINEAR, PROLONG_INJECT = 0, 1
+FP64, MIXED = 0, 1
+NN_NONE, NN_COARSE = 0, 1
+MAX_HIST = 256
+
+
+class MgfrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mgfr error {code}: {msg}")
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("box", C.c_double), ("a", C.c_double), ("omega_m", C.c_double),
+                ("omega_l", C.c_double), ("fr0_abs", C.c_double), ("n", C.c_int),
+                ("mesh", C.c_int), ("refine_levels", C.c_int), ("tol", C.c_double),
+                ("pre_smooth", C.c_int), ("post_smooth", C.c_int), ("coarse_sweeps", C.c_int),
+                ("max_vcycles", C.c_int), ("prolong", C.c_int), ("precision", C.c_int),
+                ("nn_mode", C.c_int), ("max_du", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("status", C.c_int), ("vcycles", C.c_int), ("outer_iters", C.c_int),
+                ("fell_back", C.c_int), ("res0", C.c_double), ("res", C.c_double),
+                ("scale", C.c_double), ("l2res", C.c_double), ("res_hist", C.c_double * MAX_HIST),
+                ("t_solve_ms", C.c_double), ("t_sweep_ms", C.c_double),
+                ("n_sweep_launches", C.c_int), ("t_nn_ms", C.c_double)]
+
+
+@dataclass
+class Params:
+    """Mirror of ``mgfr_params`` (defaults: the paper's model, V(2,2), tol 1e-8)."""
+    mesh: int = 32
+    box: float = 100.0
+    a: float = 1.0
+    omega_m: float = 0.3
+    omega_l: float = 0.7
+    fr0_abs: float = 1e-5
+    n: int = 1
+    refine_levels: int = 0
+    tol: float = 1e-8
+    pre_smooth: int = 2
+    post_smooth: int = 2
+    coarse_sweeps: int = 30
+    max_vcycles: int = 100
+    prolong: int = PROLONG_LINEAR
+    precision: int = FP64
+    nn_mode: int = NN_NONE
+    max_du: float = 2.0
+
+    def to_c(self) -> _Params:
+        return _Params(self.box, self.a, self.omega_m, self.omega_l, self.fr0_abs, self.n,
+                       self.mesh, self.refine_levels, self.tol, self.pre_smooth, self.post_smooth,
+                       self.coarse_sweeps, self.max_vcycles, self.prolong, self.precision,
+                       self.nn_mode, self.max_du)
+
+
+@dataclass
+class Stats:
+    status: int = 0
+    vcycles: int = 0
+    outer_iters: int = 0
+    fell_back: int = 0
+    res0: float = 0.0
+    res: float = 0.0
+    scale: float = 0.0
+    l2res: float = 0.0
+    res_hist: list = field(default_factory=list)
+    t_solve_ms: float = 0.0
+    t_sweep_ms: float = 0.0
+    n_sweep_launches: int = 0
+    t_nn_ms: float = 0.0
+
+    @classmethod
+    def from_c(cls, s: _Stats) -> "Stats":
+        n = min(max(s.vcycles, s.outer_iters), MAX_HIST)
+        return cls(s.status, s.vcycles, s.outer_iters, s.fell_back, s.res0, s.res, s.scale,
+                   s.l2res, list(s.res_hist[:n]), s.t_solve_ms, s.t_sweep_ms,
+                   s.n_sweep_launches, s.t_nn_ms)
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                              "or python paper_1305_2418_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.mgfr_last_error.restype = C.c_char_p
+        L.mgfr_background.argtypes = [C.POINTER(_Params), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.mgfr_create.argtypes = [C.POINTER(_Params), _VP, C.POINTER(_VP)]
+        L.mgfr_destroy.argtypes = [_VP]
+        L.mgfr_destroy.restype = None
+        L.mgfr_set_stream.argtypes = [_VP, _VP]
+        L.mgfr_set_timing.argtypes = [_VP, C.c_int]
+        L.mgfr_assign_density.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
+        L.mgfr_solve.argtypes = [_VP, _VP, _VP, _VP, C.POINTER(_Stats)]
+        L.mgfr_fifth_force.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
+        L.mgfr_ngs_sweep.argtypes = [_VP, _VP, _VP, C.c_int]
+        L.mgfr_vcycle.argtypes = [_VP, _VP, _VP]
+        L.mgfr_residual.argtypes = [_VP, _VP, _VP, _VP]
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names declared by include/mgfr.h (checked against the built library by the tests)."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(_PKG), "include", "mgfr.h")).read()
+    return sorted(set(re.findall(r"\b(mgfr_[a-z0-9_]+)\s*\(", hdr)))
+
+
+def _check(rc: int, allow_not_converged: bool = False) -> int:
+    if rc < 0 or (rc == MGFR_NOT_CONVERGED and not allow_not_converged):
+        msg = lib().mgfr_last_error().decode(errors="replace")
+        raise MgfrError(rc, msg)
+    return rc
+
+
+def _stream_ptr():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, shape, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a torch tensor on the HIP device")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def background(p: Params):
+    fb, beta, Cc = C.c_double(), C.c_double(), C.c_double()
+    pc = p.to_c()
+    _check(lib().mgfr_background(C.byref(pc), C.byref(fb), C.byref(beta), C.byref(Cc)))
+    return fb.value, beta.value, Cc.value
+
+
+class Solver:
+    """One mgfr context: the level hierarchy for an N^3 mesh on the current device."""
+
+    def __init__(self, params: Params, stream=None):
+        self.params = params
+        self._p = params.to_c()
+        h = _VP()
+        s = _stream_ptr() if stream is None else stream
+        _check(lib().mgfr_create(C.byref(self._p), s, C.byref(h)))
+        self._h = h
+        self.N = params.mesh
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgfr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(lib().mgfr_set_stream(self._h, _stream_ptr()))
+
+    @property
+    def shape(self):
+        return (self.N, self.N, self.N)
+
+    def set_timing(self, on: bool):
+        _check(lib().mgfr_set_timing(self._h, 1 if on else 0))
+
+    def assign_density(self, pos: torch.Tensor, mass: torch.Tensor | None = None,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+        self._sync_stream()
+        if pos.dim() != 2 or pos.shape[1] != 3:
+            raise ValueError("pos must be [np, 3]")
+        npart = pos.shape[0]
+        pp = _dev(pos, torch.float32, None, "pos")
+        mp = _dev(mass, torch.float64, (npart,), "mass", allow_none=True)
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=pos.device)
+        op = _dev(out, torch.float64, self.shape, "delta")
+        _check(lib().mgfr_assign_density(self._h, pp, mp, npart, op))
+        return out
+
+    def solve(self, delta: torch.Tensor, u: torch.Tensor | None = None, want_dfr: bool = True,
+              allow_not_converged: bool = False):
+        """Returns (u, dfr or None, Stats); u is updated in place if given."""
+        self._sync_stream()
+        dp = _dev(delta, torch.float64, self.shape, "delta")
+        if u is None:
+            u = torch.zeros(self.shape, dtype=torch.float64, device=delta.device)
+        up = _dev(u, torch.float64, self.shape, "u")
+        dfr = torch.empty_like(u) if want_dfr else None
+        st = _Stats()
+        rc = lib().mgfr_solve(self._h, dp, up, dfr.data_ptr() if want_dfr else None, C.byref(st))
+        _check(rc, allow_not_converged=allow_not_converged)
+        return u, dfr, Stats.from_c(st)
+
+    def fifth_force(self, u: torch.Tensor, pos: torch.Tensor, out: torch.Tensor | None = None):
+        self._sync_stream()
+        npart = pos.shape[0]
+        up = _dev(u, torch.float64, self.shape, "u")
+        pp = _dev(pos, torch.float32, (npart, 3), "pos")
+        if out is None:
+            out = torch.empty((npart, 3), dtype=torch.float32, device=pos.device)
+        ap = _dev(out, torch.float32, (npart, 3), "acc")
+        _check(lib().mgfr_fifth_force(self._h, up, pp, npart, ap))
+        return out
+
+    def ngs_sweep(self, u: torch.Tensor, f: torch.Tensor, sweeps: int = 1):
+        self._sync_stream()
+        _check(lib().mgfr_ngs_sweep(self._h, _dev(u, torch.float64, self.shape, "u"),
+                                    _dev(f, torch.float64, self.shape, "f"), sweeps))
+        return u
+
+    def vcycle(self, u: torch.Tensor, f: torch.Tensor):
+        self._sync_stream()
+        _check(lib().mgfr_vcycle(self._h, _dev(u, torch.float64, self.shape, "u"),
+                                 _dev(f, torch.float64, self.shape, "f")))
+        return u
+
+    def residual(self, u: torch.Tensor, f: torch.Tensor):
+        self._sync_stream()
+        r = torch.empty_like(u)
+        _check(lib().mgfr_residual(self._h, _dev(u, torch.float64, self.shape, "u"),
+                                   _dev(f, torch.float64, self.shape, "f"),
+                                   _dev(r, torch.float64, self.shape, "r")))
+        return r

@@ -1,0 +1,237 @@
+"""Parity of the HIP library against the FP64 CPU oracle (run on an MI355X).
+
+Inputs are seeded synthetic loads; the oracle and the library receive the same
+arrays.  Tolerances: rounding level for single steps, 1e-10 relative in
+delta f_R for whole FP64 solves at an identical schedule (same number of
+V-cycles), float32 rounding for the fifth force (its output type).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1305_2418_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _mg():
+    from paper_1305_2418_amd import mgfr
+    return mgfr
+
+
+def _load(N, rms, seed, halos=0, profile="plummer"):
+    pos = synth.clustered_load(N, 100.0, rms=rms, seed=seed, n_halos=halos, profile=profile)
+    return pos
+
+
+def _delta(N, rms, seed, halos=0):
+    pos = _load(N, rms, seed, halos).numpy()
+    return O.density_contrast(O.cic_assign(N, 100.0, pos))
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _params(mg, N, **kw):
+    return mg.Params(mesh=N, **kw)
+
+
+def _oparams(N, **kw):
+    return O.params(mesh=N, **kw)
+
+
+# --------------------------------------------------------------------- single steps
+
+@pytest.mark.parametrize("N", [16, 32, 64])
+def test_one_sweep_matches_oracle(N):
+    mg = _mg()
+    print(f"[case] one sweep N={N}", flush=True)
+    d = _delta(N, 5.0, 11, halos=10 if N >= 32 else 0)
+    p = _oparams(N, fr0_abs=1e-6)
+    fb, beta, C = O.background(p)
+    f = beta * 0.3 * d
+    rng = np.random.default_rng(N)
+    u0 = rng.normal(-1.0, 1.0, (N, N, N))
+    ref = O.ngs_sweep(u0, f, 100.0 / N, beta * C)
+    ref2 = O.ngs_sweep(ref, f, 100.0 / N, beta * C)
+    s = mg.Solver(_params(mg, N, fr0_abs=1e-6))
+    u = torch.tensor(u0, device=DEV)
+    ft = torch.tensor(f, device=DEV)
+    s.ngs_sweep(u, ft, 1)
+    assert _rel(u.cpu().numpy(), ref) < 1e-13
+    s.ngs_sweep(u, ft, 1)
+    assert _rel(u.cpu().numpy(), ref2) < 1e-13
+
+
+@pytest.mark.parametrize("N", [16, 64])
+def test_residual_matches_oracle(N):
+    mg = _mg()
+    print(f"[case] residual N={N}", flush=True)
+    rng = np.random.default_rng(3)
+    u0 = rng.normal(-2.0, 1.5, (N, N, N))
+    f = rng.normal(0, 1, (N, N, N))
+    p = _oparams(N, fr0_abs=1e-6)
+    fb, beta, C = O.background(p)
+    ref = f - O.apply_L(u0, 100.0 / N, beta * C)
+    s = mg.Solver(_params(mg, N, fr0_abs=1e-6))
+    r = s.residual(torch.tensor(u0, device=DEV), torch.tensor(f, device=DEV)).cpu().numpy()
+    assert _rel(r, ref) < 1e-13
+
+
+@pytest.mark.parametrize("N,prolong", [(16, 0), (32, 0), (64, 0), (64, 1), (128, 0)])
+def test_one_vcycle_matches_oracle(N, prolong):
+    mg = _mg()
+    print(f"[case] one V-cycle N={N} prolong={prolong}", flush=True)
+    d = _delta(N, 5.0, 12, halos=20)
+    p = _oparams(N, fr0_abs=1e-6, prolong=prolong)
+    fb, beta, C = O.background(p)
+    f = beta * 0.3 * d
+    u0 = np.zeros((N, N, N))
+    ref = O.vcycle_once(p, f, u0)
+    s = mg.Solver(_params(mg, N, fr0_abs=1e-6, prolong=prolong))
+    u = torch.zeros((N, N, N), dtype=torch.float64, device=DEV)
+    s.vcycle(u, torch.tensor(f, device=DEV))
+    assert _rel(u.cpu().numpy(), ref) < 1e-12
+
+
+# ---------------------------------------------------------------------- full solves
+
+SOLVE_CASES = [
+    # (N, rms, halos, fr0, a, seed)  -- config 1, then clustered, screened loads
+    (32, 1.0, 0, 1e-5, 1.0, 1),
+    (64, 5.0, 20, 1e-5, 1.0, 2),
+    (64, 5.0, 20, 1e-6, 1.0, 2),
+    (64, 5.0, 20, 1e-6, 0.5, 3),
+    (128, 5.0, 20, 1e-6, 1.0, 4),
+]
+
+
+@pytest.mark.parametrize("N,rms,halos,fr0,a,seed", SOLVE_CASES)
+def test_solve_matches_oracle(N, rms, halos, fr0, a, seed):
+    mg = _mg()
+    print(f"[case] solve N={N} fr0={fr0} a={a} seed={seed}", flush=True)
+    d = _delta(N, rms, seed, halos)
+    s_o, u_o, dfr_o, st_o = O.solve(_oparams(N, fr0_abs=fr0, a=a, max_vcycles=60), d)
+    assert s_o == 0
+    k = st_o.vcycles
+    # same schedule: exactly k V-cycles on both sides
+    s = mg.Solver(_params(mg, N, fr0_abs=fr0, a=a, max_vcycles=60))
+    u, dfr, st = s.solve(torch.tensor(d, device=DEV))
+    assert st.status == 0
+    assert abs(st.vcycles - k) <= 1
+    if st.vcycles != k:
+        s = mg.Solver(_params(mg, N, fr0_abs=fr0, a=a, max_vcycles=k, tol=1e-300))
+        u, dfr, st = s.solve(torch.tensor(d, device=DEV), allow_not_converged=True)
+    err = _rel(dfr.cpu().numpy(), dfr_o)
+    print(f"  vcycles={st.vcycles} oracle={k} res={st.res:.3e} oracle_res={st_o.res:.3e} rel dfr err={err:.2e}")
+    assert err < 1e-10
+    assert abs(st.res / st_o.res - 1) < 1e-3
+
+
+def test_solve_from_previous_solution_takes_no_cycles():
+    mg = _mg()
+    d = _delta(32, 1.0, 1)
+    s = mg.Solver(_params(mg, 32))
+    u, dfr, st = s.solve(torch.tensor(d, device=DEV))
+    u2, _, st2 = s.solve(torch.tensor(d, device=DEV), u=u.clone())
+    assert st2.vcycles == 0 and st2.status == 0 and torch.equal(u, u2)
+
+
+def test_uniform_density_on_gpu():
+    mg = _mg()
+    s = mg.Solver(_params(mg, 32))
+    u, dfr, st = s.solve(torch.zeros((32, 32, 32), dtype=torch.float64, device=DEV))
+    assert st.vcycles == 0 and float(u.abs().max()) == 0.0 and float(dfr.abs().max()) == 0.0
+
+
+def test_small_meshes_all_in_tail():
+    mg = _mg()
+    for N in (8, 16):
+        d = _delta(N, 1.0, 5)
+        s_o, u_o, dfr_o, st_o = O.solve(_oparams(N), d)
+        s = mg.Solver(_params(mg, N))
+        u, dfr, st = s.solve(torch.tensor(d, device=DEV))
+        assert st.vcycles == st_o.vcycles
+        assert _rel(dfr.cpu().numpy(), dfr_o) < 1e-10
+
+
+# ------------------------------------------------------------------ mass assignment
+
+@pytest.mark.parametrize("N,npart_side,halos", [(32, 32, 0), (64, 64, 20), (32, 50, 5)])
+def test_assign_matches_oracle(N, npart_side, halos):
+    mg = _mg()
+    print(f"[case] assign N={N} np={npart_side}^3", flush=True)
+    pos = _load(npart_side, 5.0, 21, halos)
+    ref = O.density_contrast(O.cic_assign(N, 100.0, pos.numpy()))
+    s = mg.Solver(_params(mg, N))
+    d = s.assign_density(pos.to(DEV)).cpu().numpy()
+    assert np.abs(d - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_assign_with_masses_and_wrapping():
+    mg = _mg()
+    rng = np.random.default_rng(22)
+    pos = rng.uniform(-150, 250, (5000, 3)).astype(np.float32)  # outside the box: wrapped
+    mass = rng.uniform(0.5, 2.0, 5000)
+    ref = O.density_contrast(O.cic_assign(32, 100.0, pos, mass))
+    s = mg.Solver(_params(mg, 32))
+    d = s.assign_density(torch.tensor(pos, device=DEV), torch.tensor(mass, device=DEV)).cpu().numpy()
+    assert np.abs(d - ref).max() < 1e-11
+
+
+def test_assign_rejects_nonfinite():
+    mg = _mg()
+    pos = torch.rand((1000, 3), device=DEV) * 100
+    pos[17, 1] = float("nan")
+    s = mg.Solver(_params(mg, 16))
+    with pytest.raises(mg.MgfrError) as ei:
+        s.assign_density(pos)
+    assert ei.value.code == mg.MGFR_ERR_NONFINITE
+
+
+# ----------------------------------------------------------------------- fifth force
+
+@pytest.mark.parametrize("N,a", [(32, 1.0), (64, 0.7)])
+def test_fifth_force_matches_oracle(N, a):
+    mg = _mg()
+    print(f"[case] fifth force N={N}", flush=True)
+    d = _delta(N, 5.0, 31, halos=10)
+    p = _oparams(N, fr0_abs=1e-5, a=a)
+    _, u_o, _, _ = O.solve(p, d)
+    pos = _load(N, 5.0, 32, 10)
+    ref = O.fifth_force(p, u_o, pos.numpy())
+    s = mg.Solver(_params(mg, N, fr0_abs=1e-5, a=a))
+    acc = s.fifth_force(torch.tensor(u_o, device=DEV), pos.to(DEV)).cpu().numpy().astype(np.float64)
+    scale = np.abs(ref).max()
+    # float32 output: |err| <= 2^-24 |a| per component plus a float64 gather floor
+    assert np.all(np.abs(acc - ref) <= 6.0e-8 * np.abs(ref) + 1e-10 * scale)
+
+
+# ----------------------------------------------------------------- error behaviour
+
+def test_nonfinite_delta_rejected_and_arguments_validated():
+    mg = _mg()
+    s = mg.Solver(_params(mg, 16))
+    d = torch.zeros((16, 16, 16), dtype=torch.float64, device=DEV)
+    d[3, 3, 3] = float("nan")
+    with pytest.raises(mg.MgfrError) as ei:
+        s.solve(d)
+    assert ei.value.code == mg.MGFR_ERR_NONFINITE
+    for bad in (dict(mesh=24), dict(a=0.0), dict(fr0_abs=-1e-5), dict(tol=0.0), dict(n=0)):
+        with pytest.raises(mg.MgfrError) as ei:
+            mg.Solver(mg.Params(**{**dict(mesh=16), **bad}))
+        assert ei.value.code == mg.MGFR_ERR_ARG
+
+
+def test_not_converged_status():
+    mg = _mg()
+    d = _delta(32, 1.0, 1)
+    s = mg.Solver(_params(mg, 32, max_vcycles=1))
+    u, dfr, st = s.solve(torch.tensor(d, device=DEV), allow_not_converged=True)
+    assert st.status == mg.MGFR_NOT_CONVERGED and st.vcycles == 1

@@ -118,9 +118,10 @@ def main():
     st_t = step(timing=True)
     torch.cuda.synchronize()
     sweep_ms = st_t.t_sweep_ms / max(1, st_t.n_sweep_launches)
-    # algorithmic bytes of one red or black half-sweep launch: read u (both colours),
-    # f of the updated colour, write u of the updated colour = 12 B per cell
-    alg_bytes = 12.0 * N ** 3
+    # algorithmic bytes of one full red-black sweep of the finest level: read u and f,
+    # write u = 24 B per cell (one fused launch at N >= 512, two per-colour launches below)
+    alg_bytes = 24.0 * N ** 3
+    kernel = "k_sweep_fused" if N >= 512 else "k_sweep_half (x2 per sweep)"
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "sweep_traffic.json")
@@ -158,7 +159,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep_half", "launch_ms": sweep_ms,
+                     "kernel": kernel, "launch_ms": sweep_ms,
                      "alg_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu_baseline:

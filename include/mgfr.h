@@ -122,6 +122,12 @@ int mgfr_set_stream(mgfr_ctx *ctx, void *stream);
  * or off (reported in mgfr_stats.t_sweep_ms). */
 int mgfr_set_timing(mgfr_ctx *ctx, int on);
 
+/* Smallest level size N at which a red-black sweep runs as one fused,
+ * out-of-place kernel (both colours per launch, LDS-staged tiles); smaller
+ * levels use one in-place kernel per colour.  Default 512; 0 = never;
+ * otherwise n >= 64.  Results agree to rounding either way. */
+int mgfr_set_fused_min_mesh(mgfr_ctx *ctx, int n);
+
 /* Cloud-in-cell assignment (Sec. 3.1) of np particles onto the N^3 mesh and
  * delta = m / m_bar - 1 with m_bar the mean cell mass of the assignment.
  * pos: float32 [np][3]; mass: float64 [np] or NULL for equal masses;

@@ -31,6 +31,7 @@ struct Level {
     int N = 0, lg = 0;
     double h = 0;
     double *u = nullptr, *f = nullptr, *ubar = nullptr;
+    double *alt = nullptr;  // second buffer of out-of-place sweeps (current iterate is u)
     // float32 mirrors for the mixed-precision inner cycle
     float *e32 = nullptr, *r32 = nullptr, *u32 = nullptr, *ebar32 = nullptr;
 };
@@ -49,6 +50,8 @@ struct mgfr_ctx {
     double fbar = 0, beta = 0, C = 0, bC = 0, q = 0;
     int nlev = 0;
     mgfr::Level lev[mgfr::kMaxLevels];
+    double *alt0 = nullptr;  // level-0 second buffer (owned)
+    int fused_min_n = 512;   // levels with N >= this use the fused out-of-place sweep (0: never)
     // reduction scratch
     double *partial = nullptr;  // [2 * nparts]
     int nparts = 0;

@@ -203,6 +203,175 @@ __device__ __forceinline__ double prolong_value(const double *__restrict__ uc, c
     return v;
 }
 
+// 1/x for finite non-zero x: hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double recip(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// Newton-Gauss-Seidel step from precomputed exponentials: ec = e^{u_c},
+// em = e^{-q u_c} - 1, neighbour values n* and their exponentials e*.
+__device__ __forceinline__ double ngs_step_e(double uc, double ec, double em, double n0, double e0, double n1,
+                                             double e1, double n2, double e2, double n3, double e3, double n4,
+                                             double e4, double n5, double e5, double f, const OpConst &k)
+{
+    double d0 = n0 - uc, d1 = n1 - uc, d2 = n2 - uc, d3 = n3 - uc, d4 = n4 - uc, d5 = n5 - uc;
+    double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
+    double S2 = ((e0 + e1) + (e2 + e3)) + (e4 + e5);
+    double S3 = ((e0 * d0 + e1 * d1) + (e2 * d2 + e3 * d3)) + (e4 * d4 + e5 * d5);
+    double L = k.ih2 * 0.5 * (S3 + ec * S1) + k.bC * em;
+    double J = k.ih2 * 0.5 * (ec * (S1 - 6.0) - S2) - k.bC * k.q * (1.0 + em);
+    double du = -(L - f) * recip(J);
+    if (k.max_du > 0.0) du = fmin(fmax(du, -k.max_du), k.max_du);
+    return du;
+}
+
+// e^{-q u} - 1 given e^{u}: for n = 1 (q = 1/2) this is rsqrt(e^u) - 1.
+template <bool N1>
+__device__ __forceinline__ double curv_em(double uc, double ec, double q)
+{
+    if constexpr (N1) return rsqrt(ec) - 1.0;
+    else return expm1(-q * uc);
+}
+
+// One full red-black sweep, out of place: uout = sweep(uin).
+//
+// A workgroup owns a (y, z) tile of (JL - 4) x FKI interior cells and marches
+// along x over `chunk` planes, staging a JL x 64 tile (halo 2) of each plane in
+// LDS.  Red cells are updated on the interior plus a one-cell ring (which needs
+// old black values two cells out), black cells on the interior; plane p+1 is
+// red-updated while plane p is black-updated.
+//
+// Lanes map to z columns and each thread owns one pair of consecutive y rows.
+// In every column exactly one row of the pair is red on plane p+1, and that
+// same row is black on plane p, so every lane does one red and one black
+// update per plane with straight-line code.  Each cell's e^u is computed once
+// when loaded and once more after its red update; for n = 1 the curvature term
+// reuses e^u through rsqrt.  Every cell of uin and f is read and every cell of
+// uout written once (24 B/cell) apart from the halo and the 4 warm-up planes of
+// each chunk; the next plane is prefetched one iteration ahead.
+constexpr int FKL = 64, FKI = 60;
+
+template <int JL>
+struct FusedShape {
+    static constexpr int JI = JL - 4;       // interior rows
+    static constexpr int THREADS = 32 * JL; // one thread per row pair and column
+};
+
+template <bool N1, int JL>
+__global__ __launch_bounds__(32 * JL) void k_sweep_fused(const double *__restrict__ uin,
+                                                           const double *__restrict__ f,
+                                                           double *__restrict__ uout, int lg, int chunk,
+                                                           OpConst kc)
+{
+    constexpr int JI = JL - 4;
+    __shared__ double sV[2][JL][FKL];
+    __shared__ double sE[2][JL][FKL];
+    const int N = 1 << lg, m = N - 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int k0 = blockIdx.x * FKI, j0 = blockIdx.y * JI, i0 = blockIdx.z * chunk;
+    const int kku = k0 - 2 + lane;
+    const int kg = kku & m;
+    const bool kin1 = lane >= 1 && lane <= FKL - 2;
+    const bool kint = lane >= 2 && lane <= FKL - 3 && kku < N;
+    const int ra = 2 * w, rb = ra + 1;  // the thread's two rows in the tile
+    const int jga = (j0 - 2 + ra) & m, jgb = (j0 - 2 + rb) & m;
+    const bool in1a = ra >= 1 && ra <= JL - 2, in1b = rb >= 1 && rb <= JL - 2;
+    const bool inta = ra >= 2 && ra <= JL - 3 && j0 - 2 + ra < N;
+    const bool intb = rb >= 2 && rb <= JL - 3 && j0 - 2 + rb < N;
+    const bool lda = in1a && kin1, ldb = in1b && kin1;  // f needed (red ring / black interior)
+    const int lm = lane > 0 ? lane - 1 : 0, lp = lane < FKL - 1 ? lane + 1 : FKL - 1;
+    auto at = [&](int i, int jg) { return (((((size_t)(i & m)) << lg) + (size_t)jg) << lg) + (size_t)kg; };
+
+    // plane p-1: red value (and e^u) in the row that is black on plane p
+    double V0s = 0.0, E0s = 0.0;
+    // plane p: red cells updated, black cells old
+    double V1a = uin[at(i0 - 2, jga)], V1b = uin[at(i0 - 2, jgb)];
+    // plane p+1: old values
+    double V2a = uin[at(i0 - 1, jga)], V2b = uin[at(i0 - 1, jgb)];
+    double F1s = 0.0;
+    double F2a = lda ? f[at(i0 - 1, jga)] : 0.0, F2b = ldb ? f[at(i0 - 1, jgb)] : 0.0;
+    double V4a = uin[at(i0, jga)], V4b = uin[at(i0, jgb)];
+    double F4a = lda ? f[at(i0, jga)] : 0.0, F4b = ldb ? f[at(i0, jgb)] : 0.0;
+    double E1a = exp(V1a), E1b = exp(V1b), E2a = exp(V2a), E2b = exp(V2b);
+    int xb = 0;
+    for (int p = i0 - 2; p < i0 + chunk; ++p) {
+        // plane p+2 (prefetched last iteration); prefetch plane p+3
+        const double V3a = V4a, V3b = V4b, F3a = F4a, F3b = F4b;
+        if (p + 1 < i0 + chunk) {
+            V4a = uin[at(p + 3, jga)];
+            V4b = uin[at(p + 3, jgb)];
+            F4a = lda ? f[at(p + 3, jga)] : 0.0;
+            F4b = ldb ? f[at(p + 3, jgb)] : 0.0;
+        }
+        const double E3a = exp(V3a), E3b = exp(V3b);
+        __syncthreads();  // the previous plane's readers of buffer xb are done
+        sV[xb][ra][lane] = V2a;
+        sV[xb][rb][lane] = V2b;
+        sE[xb][ra][lane] = E2a;
+        sE[xb][rb][lane] = E2b;
+        __syncthreads();
+        // red cell of plane p+1 in row r = ra + sel; the same row holds the black cell of plane p
+        const int sel = ((p + 1) + jga + kg) & 1;
+        const int r = ra + sel;
+        const int rc = r < 1 ? 1 : (r > JL - 2 ? JL - 2 : r);
+        {
+            const bool act = kin1 && (sel ? in1b : in1a);
+            const double uc = sel ? V2b : V2a, ec = sel ? E2b : E2a;
+            const double du = ngs_step_e(uc, ec, curv_em<N1>(uc, ec, kc.q), sel ? V1b : V1a, sel ? E1b : E1a,
+                                         sel ? V3b : V3a, sel ? E3b : E3a, sV[xb][rc - 1][lane],
+                                         sE[xb][rc - 1][lane], sV[xb][rc + 1][lane], sE[xb][rc + 1][lane],
+                                         sV[xb][rc][lm], sE[xb][rc][lm], sV[xb][rc][lp], sE[xb][rc][lp],
+                                         sel ? F2b : F2a, kc);
+            const double un = uc + du;
+            const double en = exp(un);
+            V2a = (act && !sel) ? un : V2a;
+            E2a = (act && !sel) ? en : E2a;
+            V2b = (act && sel) ? un : V2b;
+            E2b = (act && sel) ? en : E2b;
+            // only black positions of this buffer are read by other red updates
+            if (act) {
+                sV[xb][r][lane] = un;
+                sE[xb][r][lane] = en;
+            }
+        }
+        // black cell of plane p (buffer xb^1 holds plane p with its red cells updated)
+        if (p >= i0) {
+            const int yb = xb ^ 1;
+            const bool act = kint && (sel ? intb : inta);
+            const double uc = sel ? V1b : V1a, ec = sel ? E1b : E1a;
+            const double du = ngs_step_e(uc, ec, curv_em<N1>(uc, ec, kc.q), V0s, E0s, sel ? V2b : V2a,
+                                         sel ? E2b : E2a, sV[yb][rc - 1][lane], sE[yb][rc - 1][lane],
+                                         sV[yb][rc + 1][lane], sE[yb][rc + 1][lane], sV[yb][rc][lm],
+                                         sE[yb][rc][lm], sV[yb][rc][lp], sE[yb][rc][lp], F1s, kc);
+            const double un = uc + du;
+            V1a = (act && !sel) ? un : V1a;
+            V1b = (act && sel) ? un : V1b;
+            if (kint && inta) uout[at(p, jga)] = V1a;
+            if (kint && intb) uout[at(p, jgb)] = V1b;
+        }
+        // rotate: the red row of plane p is the black row of plane p+1
+        V0s = sel ? V1a : V1b;
+        E0s = sel ? E1a : E1b;
+        F1s = sel ? F2a : F2b;
+        V1a = V2a;
+        V1b = V2b;
+        E1a = E2a;
+        E1b = E2b;
+        V2a = V3a;
+        V2b = V3b;
+        E2a = E3a;
+        E2b = E3b;
+        F2a = F3a;
+        F2b = F3b;
+        xb ^= 1;
+    }
+}
+
 // --------------------------------------------------------------- grid kernels
 
 __global__ __launch_bounds__(kBlock) void k_sweep_half(double *__restrict__ u, const double *__restrict__ f,
@@ -421,30 +590,64 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs A)
 
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-int launch_sweep64(mgfr_ctx *c, int l, double *u, const double *f, int sweeps, bool timed)
+static int timer_slot(mgfr_ctx *c, int *slot)
 {
+    Timer &T = c->sweep_timer;
+    if (T.used + 2 > (int)T.ev.size()) {
+        for (int e = 0; e < 16; ++e) {
+            hipEvent_t ev;
+            MGFR_HIP(hipEventCreate(&ev));
+            T.ev.push_back(ev);
+        }
+    }
+    *slot = T.used;
+    T.used += 2;
+    return MGFR_OK;
+}
+
+#ifndef MGFR_FUSED_JL
+#define MGFR_FUSED_JL 16
+#endif
+
+static int fused_chunk(int N)
+{
+    int ch = N / 8;
+    return ch < 8 ? 8 : ch;
+}
+
+// `sweeps` red-black sweeps on level l.  Levels with N >= fused_min_n use the
+// out-of-place fused kernel and swap L.u / L.alt after each sweep; the others
+// update L.u in place with one kernel per colour.
+int launch_sweep64(mgfr_ctx *c, int l, double *u_unused, const double *f, int sweeps, bool timed)
+{
+    (void)u_unused;
     Level &L = c->lev[l];
     OpConst kc = level_const(c, l);
+    const bool fused = c->fused_min_n > 0 && L.N >= c->fused_min_n && L.alt != nullptr;
     const size_t half = (size_t)1 << (3 * L.lg - 1);
-    for (int s = 0; s < sweeps; ++s)
-        for (int colour = 0; colour < 2; ++colour) {
-            if (timed) {
-                Timer &T = c->sweep_timer;
-                if (T.used + 2 > (int)T.ev.size()) {
-                    for (int e = 0; e < 16; ++e) {
-                        hipEvent_t ev;
-                        MGFR_HIP(hipEventCreate(&ev));
-                        T.ev.push_back(ev);
-                    }
-                }
-                MGFR_HIP(hipEventRecord(T.ev[T.used], c->stream));
-                k_sweep_half<<<nblocks(half), kBlock, 0, c->stream>>>(u, f, L.lg, colour, kc);
-                MGFR_HIP(hipEventRecord(T.ev[T.used + 1], c->stream));
-                T.used += 2;
-            } else {
-                k_sweep_half<<<nblocks(half), kBlock, 0, c->stream>>>(u, f, L.lg, colour, kc);
-            }
+    for (int s = 0; s < sweeps; ++s) {
+        int slot = -1;
+        if (timed) {
+            int rc = timer_slot(c, &slot);
+            if (rc) return rc;
+            MGFR_HIP(hipEventRecord(c->sweep_timer.ev[slot], c->stream));
         }
+        if (fused) {
+            const int chunk = fused_chunk(L.N);
+            constexpr int JL = MGFR_FUSED_JL;
+            constexpr int JI = FusedShape<JL>::JI;
+            dim3 grid((unsigned)((L.N + FKI - 1) / FKI), (unsigned)((L.N + JI - 1) / JI), (unsigned)(L.N / chunk));
+            if (c->p.n == 1)
+                k_sweep_fused<true, JL><<<grid, FusedShape<JL>::THREADS, 0, c->stream>>>(L.u, f, L.alt, L.lg, chunk, kc);
+            else
+                k_sweep_fused<false, JL><<<grid, FusedShape<JL>::THREADS, 0, c->stream>>>(L.u, f, L.alt, L.lg, chunk, kc);
+            std::swap(L.u, L.alt);
+        } else {
+            for (int colour = 0; colour < 2; ++colour)
+                k_sweep_half<<<nblocks(half), kBlock, 0, c->stream>>>(L.u, f, L.lg, colour, kc);
+        }
+        if (timed) MGFR_HIP(hipEventRecord(c->sweep_timer.ev[slot + 1], c->stream));
+    }
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
 }
@@ -585,7 +788,10 @@ static void free_ctx(mgfr_ctx *c)
     nn_free(c);
     for (int l = 0; l < kMaxLevels; ++l) {
         Level &L = c->lev[l];
-        if (l > 0) (void)hipFree(L.u);
+        if (l > 0) {
+            (void)hipFree(L.u);
+            (void)hipFree(L.alt);
+        }
         (void)hipFree(L.f);
         (void)hipFree(L.ubar);
         (void)hipFree(L.e32);
@@ -593,6 +799,7 @@ static void free_ctx(mgfr_ctx *c)
         (void)hipFree(L.u32);
         (void)hipFree(L.ebar32);
     }
+    (void)hipFree(c->alt0);
     (void)hipFree(c->partial);
     (void)hipFree(c->dscal);
     (void)hipFree(c->dflag);
@@ -626,6 +833,10 @@ static int create_impl(const mgfr_params *p, void *stream, mgfr_ctx *c)
         if (l > 0) {
             MGFR_HIP(hipMalloc(&L.u, bytes));
             MGFR_HIP(hipMalloc(&L.ubar, bytes));
+        }
+        if (n >= 64) {  // second buffer for out-of-place fused sweeps
+            MGFR_HIP(hipMalloc(&L.alt, bytes));
+            if (l == 0) c->alt0 = L.alt;
         }
         c->nlev = l + 1;
     }
@@ -701,6 +912,20 @@ static int prepare_source(mgfr_ctx *c, const double *delta, double *D)
     return MGFR_OK;
 }
 
+// After out-of-place sweeps the current level-0 iterate may sit in the
+// context's buffer: copy it back into the caller's array.
+static int restore_level0(mgfr_ctx *c, double *user_u)
+{
+    Level &L0 = c->lev[0];
+    if (L0.u != user_u) {
+        size_t n = (size_t)L0.N * L0.N * L0.N;
+        MGFR_HIP(hipMemcpyAsync(user_u, L0.u, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        L0.alt = L0.u;
+        L0.u = user_u;
+    }
+    return MGFR_OK;
+}
+
 static int finish(mgfr_ctx *c, double *u, double *dfr, mgfr_stats *st, int status)
 {
     if (dfr) {
@@ -757,6 +982,7 @@ extern "C" int mgfr_solve(mgfr_ctx *c, const double *delta, double *u, double *d
     mgfr_stats *st = st_out ? st_out : &local;
     memset(st, 0, sizeof *st);
     c->lev[0].u = u;
+    c->lev[0].alt = c->alt0;
     c->sweep_timer.used = 0;
     MGFR_HIP(hipEventRecord(c->ev_a, c->stream));
     double D;
@@ -777,6 +1003,7 @@ extern "C" int mgfr_solve(mgfr_ctx *c, const double *delta, double *u, double *d
         status = solve_fp64(c, u, st, D);
     }
     if (status < 0 && status != MGFR_ERR_NONFINITE) return status;
+    if ((rc = restore_level0(c, u))) return rc;
     return finish(c, u, dfr, st, status);
 }
 
@@ -786,15 +1013,19 @@ extern "C" int mgfr_ngs_sweep(mgfr_ctx *c, double *u, const double *f, int sweep
     if ((rc = check_ptr(c, "ctx")) || (rc = check_ptr(u, "u")) || (rc = check_ptr(f, "f"))) return rc;
     if (sweeps < 0) return set_error(MGFR_ERR_ARG, "sweeps must be >= 0");
     Level &L0 = c->lev[0];
-    const size_t half = (size_t)1 << (3 * L0.lg - 1);
-    OpConst kc = level_const(c, 0);
-    for (int s = 0; s < sweeps; ++s)
-        for (int colour = 0; colour < 2; ++colour) {
-            // N >= 8 gives N^3/2 >= 256 cells per colour: whole blocks only
-            k_sweep_half<<<nblocks(half), kBlock, 0, c->stream>>>(u, f, L0.lg, colour, kc);
-        }
-    MGFR_HIP(hipGetLastError());
+    L0.u = u;
+    L0.alt = c->alt0;
+    if ((rc = launch_sweep64(c, 0, nullptr, f, sweeps, false))) return rc;
+    if ((rc = restore_level0(c, u))) return rc;
     MGFR_HIP(hipStreamSynchronize(c->stream));
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_set_fused_min_mesh(mgfr_ctx *c, int n)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (n != 0 && n < 64) return set_error(MGFR_ERR_ARG, "fused sweeps need levels of at least 64^3 (or 0 = off)");
+    c->fused_min_n = n;
     return MGFR_OK;
 }
 
@@ -806,7 +1037,9 @@ extern "C" int mgfr_vcycle(mgfr_ctx *c, double *u, const double *f)
     size_t n = (size_t)L0.N * L0.N * L0.N;
     MGFR_HIP(hipMemcpyAsync(L0.f, f, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     L0.u = u;
+    L0.alt = c->alt0;
     if ((rc = vcycle64(c, 0))) return rc;
+    if ((rc = restore_level0(c, u))) return rc;
     MGFR_HIP(hipStreamSynchronize(c->stream));
     return MGFR_OK;
 }

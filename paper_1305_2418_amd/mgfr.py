@@ -119,6 +119,7 @@ def lib() -> C.CDLL:
         L.mgfr_destroy.restype = None
         L.mgfr_set_stream.argtypes = [_VP, _VP]
         L.mgfr_set_timing.argtypes = [_VP, C.c_int]
+        L.mgfr_set_fused_min_mesh.argtypes = [_VP, C.c_int]
         L.mgfr_assign_density.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
         L.mgfr_solve.argtypes = [_VP, _VP, _VP, _VP, C.POINTER(_Stats)]
         L.mgfr_fifth_force.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
@@ -202,6 +203,9 @@ class Solver:
 
     def set_timing(self, on: bool):
         _check(lib().mgfr_set_timing(self._h, 1 if on else 0))
+
+    def set_fused_min_mesh(self, n: int):
+        _check(lib().mgfr_set_fused_min_mesh(self._h, int(n)))
 
     def assign_density(self, pos: torch.Tensor, mass: torch.Tensor | None = None,
                        out: torch.Tensor | None = None) -> torch.Tensor:

@@ -235,3 +235,49 @@ def test_not_converged_status():
     s = mg.Solver(_params(mg, 32, max_vcycles=1))
     u, dfr, st = s.solve(torch.tensor(d, device=DEV), allow_not_converged=True)
     assert st.status == mg.MGFR_NOT_CONVERGED and st.vcycles == 1
+
+
+# ------------------------------------------------------- fused out-of-place sweeps
+
+@pytest.mark.parametrize("N,n", [(64, 1), (128, 1), (64, 2)])
+def test_fused_sweep_matches_oracle(N, n):
+    mg = _mg()
+    print(f"[case] fused sweep N={N} n={n}", flush=True)
+    d = _delta(N, 5.0, 13, halos=20)
+    p = _oparams(N, fr0_abs=1e-6, n=n)
+    fb, beta, C = O.background(p)
+    f = beta * 0.3 * d
+    rng = np.random.default_rng(N + n)
+    u0 = rng.normal(-1.0, 1.0, (N, N, N))
+    ref = O.ngs_sweep(O.ngs_sweep(O.ngs_sweep(u0, f, 100.0 / N, beta * C, n), f, 100.0 / N, beta * C, n),
+                      f, 100.0 / N, beta * C, n)
+    s = mg.Solver(_params(mg, N, fr0_abs=1e-6, n=n))
+    s.set_fused_min_mesh(64)
+    u = torch.tensor(u0, device=DEV)
+    s.ngs_sweep(u, torch.tensor(f, device=DEV), 3)  # odd count: result copied back
+    assert _rel(u.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("N,pre,post,fr0", [(64, 2, 2, 1e-6), (128, 2, 2, 1e-6), (64, 1, 2, 1e-5), (256, 2, 2, 1e-6)])
+def test_fused_solve_matches_oracle(N, pre, post, fr0):
+    mg = _mg()
+    print(f"[case] fused solve N={N} pre={pre} post={post}", flush=True)
+    d = _delta(N, 5.0, 14, halos=20)
+    k = None
+    if N <= 128:
+        s_o, u_o, dfr_o, st_o = O.solve(_oparams(N, fr0_abs=fr0, pre_smooth=pre, post_smooth=post), d)
+        k = st_o.vcycles
+    s = mg.Solver(_params(mg, N, fr0_abs=fr0, pre_smooth=pre, post_smooth=post))
+    s.set_fused_min_mesh(64)
+    u, dfr, st = s.solve(torch.tensor(d, device=DEV))
+    assert st.status == 0
+    if k is not None:
+        assert abs(st.vcycles - k) <= 1
+        if st.vcycles == k:
+            assert _rel(dfr.cpu().numpy(), dfr_o) < 1e-10
+    # fused and per-colour kernels agree on the same schedule
+    s2 = mg.Solver(_params(mg, N, fr0_abs=fr0, pre_smooth=pre, post_smooth=post,
+                           max_vcycles=st.vcycles, tol=1e-300))
+    s2.set_fused_min_mesh(0)
+    u2, dfr2, st2 = s2.solve(torch.tensor(d, device=DEV), allow_not_converged=True)
+    assert _rel(dfr.cpu().numpy(), dfr2.cpu().numpy()) < 1e-10

@@ -34,6 +34,7 @@ struct Level {
     double *alt = nullptr;  // second buffer of out-of-place sweeps (current iterate is u)
     // float32 mirrors for the mixed-precision inner cycle
     float *e32 = nullptr, *r32 = nullptr, *u32 = nullptr, *ebar32 = nullptr;
+    float *alt32 = nullptr;  // second buffer of out-of-place float32 sweeps
 };
 
 struct Timer {
@@ -52,6 +53,7 @@ struct mgfr_ctx {
     mgfr::Level lev[mgfr::kMaxLevels];
     double *alt0 = nullptr;  // level-0 second buffer (owned)
     int fused_min_n = 512;   // levels with N >= this use the fused out-of-place sweep (0: never)
+    int fused32_min_n = 256; // the same for the float32 correction sweeps
     // reduction scratch
     double *partial = nullptr;  // [2 * nparts]
     int nparts = 0;
@@ -94,6 +96,8 @@ int launch_sweep64(mgfr_ctx *c, int l, double *u, const double *f, int sweeps, b
 int launch_residual_norm64(mgfr_ctx *c, int l, const double *u, const double *f, double *rmax,
                            double *rsumsq);
 int vcycle64(mgfr_ctx *c, int l);
+int solve_fp64_from(mgfr_ctx *c, double *u, mgfr_stats *st, double D);  // V-cycles from the current u
+int collect_timing(mgfr_ctx *c, mgfr_stats *st);
 
 // mixed precision (mgfr_mixed.hip)
 int mixed_alloc(mgfr_ctx *c);

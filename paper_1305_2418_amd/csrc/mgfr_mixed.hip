@@ -1,6 +1,803 @@
-// placeholder: mixed precision is added in its own step
+// Mixed-precision solve: float64 defect correction around float32 FAS V-cycles.
+//
+// Outer loop (float64, finest level only):
+//   r = f - L(u)                      residual of the float64 iterate
+//   stop when max|r| / D <= tol       (Sec. 3.3 step 8)
+//   solve N_u(e) = r approximately    one float32 FAS V-cycle, e = 0 initially
+//   u <- u + e
+// where N_u(e) = L(u + e) - L(u) is evaluated without cancellation:
+//   N_c = (1/h^2) sum_nb [ (w_n X_n + w_c X_c)/2 (u_n - u_c)
+//                          + (w_n (1 + X_n) + w_c (1 + X_c))/2 (e_n - e_c) ]
+//         + bC s_c expm1(-q e_c)
+// with w = e^u, s = e^{-q u}, X = expm1(e).  The float32 unknown is the small
+// correction, so float32 keeps its relative precision and the float64
+// residual can still reach 1e-8.  The inner cycle is the same FAS V-cycle as
+// the float64 solve (Sec. 3.3): restriction by daughter means of e and of the
+// linearisation point u, coarse source N_2h(R e) + R(r - N(e)), correction
+// e += P(e_2h - R e), red-black Newton-Gauss-Seidel on e.  In exact
+// arithmetic one such cycle from e = 0 reproduces one float64 V-cycle, so the
+// float64 residual follows the float64 solve's history to rounding.  If it
+// grows for three consecutive outer iterations (the float64 solve itself shows
+// two-step transients from a cold start in deep screening) or turns
+// non-finite, the solve restarts as the plain float64 solve from u = 0.
 #include "mgfr_internal.h"
+#include "mgfr_ops.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
 namespace mgfr {
-int mixed_alloc(mgfr_ctx *c) { (void)c; return set_error(MGFR_ERR_ARG, "mixed precision is not available"); }
-int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D) { (void)c; (void)u; (void)st; (void)D; return set_error(MGFR_ERR_ARG, "mixed precision is not available"); }
+
+namespace {
+
+struct MxConst {
+    float ih2, bC, q, max_du;
+};
+
+#ifndef MGFR_FUSED32_JL
+#define MGFR_FUSED32_JL 16
+#endif
+
+__device__ __forceinline__ size_t ix(int i, int j, int k, int lg)
+{
+    return (((((size_t)i) << lg) + (size_t)j) << lg) + (size_t)k;
 }
+
+__device__ __forceinline__ double nanmax_d(double a, double b) { return (a != a || a > b) ? a : b; }
+
+// e^x for the float32 correction cycle: the hardware base-2 exponential of
+// x log2(e) (relative error a few float32 ulps times |x log2 e|, which only
+// perturbs the linearisation point the float64 outer loop corrects anyway).
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
+// e^x - 1 without cancellation: Taylor series to x^6 for |x| < 1/4 (truncation
+// below 2e-8 relative), fexp(x) - 1 otherwise (at most ~5 ulp of cancellation).
+__device__ __forceinline__ float fexpm1(float x)
+{
+    const float p = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
+    return fabsf(x) < 0.25f ? p : fexp(x) - 1.0f;
+}
+
+// Newton step on e at one cell from precomputed per-cell quantities:
+//   centre: e, X = expm1(e), u, w = e^u; neighbours likewise.
+__device__ __forceinline__ float mx_step(float ec, float Xc, float uc, float wc, const float en[6],
+                                         const float Xn[6], const float un[6], const float wn[6], float r,
+                                         const MxConst &k)
+{
+    float Su = 0.f, Se = 0.f, A = 0.f, B = 0.f, SW = 0.f;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const float du = un[t] - uc, de = en[t] - ec;
+        const float Wn = wn[t] + wn[t] * Xn[t];
+        Su += du;
+        Se += de;
+        A += wn[t] * Xn[t] * du;
+        B += Wn * de;
+        SW += Wn;
+    }
+    const float wXc = wc * Xc, Wc = wc + wXc;
+    const float flux = 0.5f * ((A + wXc * Su) + (B + Wc * Se));
+    const float dflux = 0.5f * (Wc * (Su + Se - 6.0f) - SW);
+    const float sc = fexp(-k.q * uc);
+    const float cm = fexpm1(-k.q * ec);
+    const float N = k.ih2 * flux + k.bC * sc * cm;
+    const float J = k.ih2 * dflux - k.q * k.bC * sc * (1.0f + cm);
+    float d = -(N - r) / J;
+    if (k.max_du > 0.f) d = fminf(fmaxf(d, -k.max_du), k.max_du);
+    return d;
+}
+
+__device__ __forceinline__ float mx_value(float ec, float Xc, float uc, float wc, const float en[6],
+                                          const float Xn[6], const float un[6], const float wn[6],
+                                          const MxConst &k)
+{
+    float Su = 0.f, Se = 0.f, A = 0.f, B = 0.f;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const float du = un[t] - uc, de = en[t] - ec;
+        Su += du;
+        Se += de;
+        A += wn[t] * Xn[t] * du;
+        B += (wn[t] + wn[t] * Xn[t]) * de;
+    }
+    const float wXc = wc * Xc, Wc = wc + wXc;
+    const float flux = 0.5f * ((A + wXc * Su) + (B + Wc * Se));
+    return k.ih2 * flux + k.bC * fexp(-k.q * uc) * fexpm1(-k.q * ec);
+}
+
+// gather the cell and its six periodic neighbours and their exponentials
+struct MxCell {
+    float ec, Xc, uc, wc;
+    float en[6], Xn[6], un[6], wn[6];
+};
+
+__device__ __forceinline__ void mx_gather(const float *__restrict__ e, const float *__restrict__ u, int i, int j,
+                                          int k, int lg, MxCell &c)
+{
+    const int m = (1 << lg) - 1;
+    const size_t idx[6] = {ix((i + 1) & m, j, k, lg), ix((i - 1) & m, j, k, lg), ix(i, (j + 1) & m, k, lg),
+                           ix(i, (j - 1) & m, k, lg), ix(i, j, (k + 1) & m, lg), ix(i, j, (k - 1) & m, lg)};
+    const size_t cc = ix(i, j, k, lg);
+    c.ec = e[cc];
+    c.uc = u[cc];
+    c.Xc = fexpm1(c.ec);
+    c.wc = fexp(c.uc);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        c.en[t] = e[idx[t]];
+        c.un[t] = u[idx[t]];
+        c.Xn[t] = fexpm1(c.en[t]);
+        c.wn[t] = fexp(c.un[t]);
+    }
+}
+
+__device__ __forceinline__ void mx_sweep_cell(float *__restrict__ e, const float *__restrict__ u,
+                                              const float *__restrict__ r, size_t t, int lg, int colour,
+                                              const MxConst &kc)
+{
+    const int m = (1 << lg) - 1;
+    const int mh = (int)(t & (size_t)((1 << (lg - 1)) - 1));
+    const size_t row = t >> (lg - 1);
+    const int j = (int)(row & m), i = (int)(row >> lg);
+    const int k = 2 * mh + ((i + j + colour) & 1);
+    MxCell c;
+    mx_gather(e, u, i, j, k, lg, c);
+    const size_t cc = ix(i, j, k, lg);
+    e[cc] = c.ec + mx_step(c.ec, c.Xc, c.uc, c.wc, c.en, c.Xn, c.un, c.wn, r[cc], kc);
+}
+
+__device__ __forceinline__ float mx_value_at(const float *__restrict__ e, const float *__restrict__ u, int i, int j,
+                                             int k, int lg, const MxConst &kc)
+{
+    MxCell c;
+    mx_gather(e, u, i, j, k, lg, c);
+    return mx_value(c.ec, c.Xc, c.uc, c.wc, c.en, c.Xn, c.un, c.wn, kc);
+}
+
+// Daughter means of e, u and of the residual r - N(e) for coarse cell (I,J,K):
+// the 2x2x2 block and its 24 face neighbours are loaded and exponentiated once.
+__device__ __forceinline__ void mx_restrict_block(const float *__restrict__ e, const float *__restrict__ u,
+                                                  const float *__restrict__ r, int I, int J, int K, int lg,
+                                                  const MxConst &kc, float &em, float &um, float &rm)
+{
+    const int m = (1 << lg) - 1;
+    const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
+    // index 0..7: block cell (a,b,c) -> a*4+b*2+c; faces: [face][p][q]
+    float Be[8], Bu[8], BX[8], Bw[8];
+    float Fe[6][4], Fu[6][4], FX[6][4], Fw[6][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const size_t cc = ix(i0 + a, j0 + b, k0 + c, lg);
+                Be[a * 4 + b * 2 + c] = e[cc];
+                Bu[a * 4 + b * 2 + c] = u[cc];
+            }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const size_t f0 = ix((i0 + 2) & m, j0 + p, k0 + q, lg), f1 = ix((i0 - 1) & m, j0 + p, k0 + q, lg);
+            const size_t f2 = ix(i0 + p, (j0 + 2) & m, k0 + q, lg), f3 = ix(i0 + p, (j0 - 1) & m, k0 + q, lg);
+            const size_t f4 = ix(i0 + p, j0 + q, (k0 + 2) & m, lg), f5 = ix(i0 + p, j0 + q, (k0 - 1) & m, lg);
+            const size_t fi[6] = {f0, f1, f2, f3, f4, f5};
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                Fe[f][p * 2 + q] = e[fi[f]];
+                Fu[f][p * 2 + q] = u[fi[f]];
+            }
+        }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        BX[t] = fexpm1(Be[t]);
+        Bw[t] = fexp(Bu[t]);
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            FX[f][t] = fexpm1(Fe[f][t]);
+            Fw[f][t] = fexp(Fu[f][t]);
+        }
+    float se = 0.f, su = 0.f, sr = 0.f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int t = a * 4 + b * 2 + c;
+                // neighbours +x, -x, +y, -y, +z, -z: inside the block or on a face
+                const int nx0 = (a ^ 1) * 4 + b * 2 + c;
+                const int ny0 = a * 4 + (b ^ 1) * 2 + c;
+                const int nz0 = a * 4 + b * 2 + (c ^ 1);
+                float en[6], Xn[6], un[6], wn[6];
+#define MX_NB(slot, inblock, bi, face, fi)                                                  \
+    if (inblock) { en[slot] = Be[bi]; Xn[slot] = BX[bi]; un[slot] = Bu[bi]; wn[slot] = Bw[bi]; } \
+    else { en[slot] = Fe[face][fi]; Xn[slot] = FX[face][fi]; un[slot] = Fu[face][fi]; wn[slot] = Fw[face][fi]; }
+                MX_NB(0, a == 0, nx0, 0, b * 2 + c)
+                MX_NB(1, a == 1, nx0, 1, b * 2 + c)
+                MX_NB(2, b == 0, ny0, 2, a * 2 + c)
+                MX_NB(3, b == 1, ny0, 3, a * 2 + c)
+                MX_NB(4, c == 0, nz0, 4, a * 2 + b)
+                MX_NB(5, c == 1, nz0, 5, a * 2 + b)
+#undef MX_NB
+                const float N = mx_value(Be[t], BX[t], Bu[t], Bw[t], en, Xn, un, wn, kc);
+                se += Be[t];
+                su += Bu[t];
+                sr += r[ix(i0 + a, j0 + b, k0 + c, lg)] - N;
+            }
+    em = 0.125f * se;
+    um = 0.125f * su;
+    rm = 0.125f * sr;
+}
+
+// daughter means of e, u and of the residual r - N(e) for coarse cell (I,J,K)
+__device__ __forceinline__ void mx_restrict_cell(const float *__restrict__ e, const float *__restrict__ u,
+                                                 const float *__restrict__ r, int I, int J, int K, int lg,
+                                                 const MxConst &kc, float &em, float &um, float &rm)
+{
+    float se = 0.f, su = 0.f, sr = 0.f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+                const size_t cc = ix(i, j, k, lg);
+                se += e[cc];
+                su += u[cc];
+                sr += r[cc] - mx_value_at(e, u, i, j, k, lg, kc);
+            }
+    em = 0.125f * se;
+    um = 0.125f * su;
+    rm = 0.125f * sr;
+}
+
+__device__ __forceinline__ float mx_prolong(const float *__restrict__ ec, const float *__restrict__ eb, int i,
+                                            int j, int k, int lgc, int mode)
+{
+    const int m = (1 << lgc) - 1;
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const size_t P = ix(I, J, K, lgc);
+    float v = ec[P] - eb[P];
+    if (mode == 0) {
+        const size_t xp = ix((I + 1) & m, J, K, lgc), xm = ix((I - 1) & m, J, K, lgc);
+        const size_t yp = ix(I, (J + 1) & m, K, lgc), ym = ix(I, (J - 1) & m, K, lgc);
+        const size_t zp = ix(I, J, (K + 1) & m, lgc), zm = ix(I, J, (K - 1) & m, lgc);
+        const float gx = (ec[xp] - eb[xp]) - (ec[xm] - eb[xm]);
+        const float gy = (ec[yp] - eb[yp]) - (ec[ym] - eb[ym]);
+        const float gz = (ec[zp] - eb[zp]) - (ec[zm] - eb[zm]);
+        v += ((i & 1) ? 0.125f : -0.125f) * gx;
+        v += ((j & 1) ? 0.125f : -0.125f) * gy;
+        v += ((k & 1) ? 0.125f : -0.125f) * gz;
+    }
+    return v;
+}
+
+// Newton step on e from neighbour quantities passed individually (fused kernel).
+__device__ __forceinline__ float mx_step6(float ec, float Xc, float uc, float wc, float sc, float r,
+                                          float e0, float X0, float u0, float w0, float e1, float X1, float u1,
+                                          float w1, float e2, float X2, float u2, float w2, float e3, float X3,
+                                          float u3, float w3, float e4, float X4, float u4, float w4, float e5,
+                                          float X5, float u5, float w5, const MxConst &k)
+{
+    const float en[6] = {e0, e1, e2, e3, e4, e5}, Xn[6] = {X0, X1, X2, X3, X4, X5};
+    const float un[6] = {u0, u1, u2, u3, u4, u5}, wn[6] = {w0, w1, w2, w3, w4, w5};
+    float Su = 0.f, Se = 0.f, A = 0.f, B = 0.f, SW = 0.f;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const float du = un[t] - uc, de = en[t] - ec;
+        const float Wn = wn[t] + wn[t] * Xn[t];
+        Su += du;
+        Se += de;
+        A += wn[t] * Xn[t] * du;
+        B += Wn * de;
+        SW += Wn;
+    }
+    const float wXc = wc * Xc, Wc = wc + wXc;
+    const float flux = 0.5f * ((A + wXc * Su) + (B + Wc * Se));
+    const float dflux = 0.5f * (Wc * (Su + Se - 6.0f) - SW);
+    const float cm = fexpm1(-k.q * ec);
+    const float N = k.ih2 * flux + k.bC * sc * cm;
+    const float J = k.ih2 * dflux - k.q * k.bC * sc * (1.0f + cm);
+    float d = -(N - r) * __builtin_amdgcn_rcpf(J);
+    if (k.max_du > 0.f) d = fminf(fmaxf(d, -k.max_du), k.max_du);
+    return d;
+}
+
+// e^{-q u} from u and w = e^u: rsqrt(w) for n = 1
+template <bool N1>
+__device__ __forceinline__ float mx_s(float u, float w, float q)
+{
+    if constexpr (N1) return __builtin_amdgcn_rsqf(w);
+    else return fexp(-q * u);
+}
+
+// One full red-black sweep of the float32 correction e, out of place
+// (eout = sweep(ein)); same tiling and row-pair scheme as the float64 fused
+// sweep.  Each staged cell carries e, X = expm1(e), the linearisation point u
+// and w = e^u, computed once when the plane is loaded; X is refreshed after a
+// red update.  Traffic: read e, u, r and write e, 16 B/cell.
+constexpr int MKL = 64, MKI = 60;
+
+template <bool N1, int JL>
+__global__ __launch_bounds__(32 * JL) void k_mx_sweep_fused(const float *__restrict__ ein,
+                                                              const float *__restrict__ u,
+                                                              const float *__restrict__ r,
+                                                              float *__restrict__ eout, int lg, int chunk,
+                                                              MxConst kc)
+{
+    constexpr int JI = JL - 4;
+    __shared__ float sEv[2][JL][MKL], sX[2][JL][MKL], sU[2][JL][MKL], sW[2][JL][MKL];
+    const int N = 1 << lg, m = N - 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int k0 = blockIdx.x * MKI, j0 = blockIdx.y * JI, i0 = blockIdx.z * chunk;
+    const int kku = k0 - 2 + lane;
+    const int kg = kku & m;
+    const bool kin1 = lane >= 1 && lane <= MKL - 2;
+    const bool kint = lane >= 2 && lane <= MKL - 3 && kku < N;
+    const int ra = 2 * w, rb = ra + 1;
+    const int jga = (j0 - 2 + ra) & m, jgb = (j0 - 2 + rb) & m;
+    const bool in1a = ra >= 1 && ra <= JL - 2, in1b = rb >= 1 && rb <= JL - 2;
+    const bool inta = ra >= 2 && ra <= JL - 3 && j0 - 2 + ra < N;
+    const bool intb = rb >= 2 && rb <= JL - 3 && j0 - 2 + rb < N;
+    const bool lda = in1a && kin1, ldb = in1b && kin1;
+    const int lm = lane > 0 ? lane - 1 : 0, lp = lane < MKL - 1 ? lane + 1 : MKL - 1;
+    auto at = [&](int i, int jg) { return (((((size_t)(i & m)) << lg) + (size_t)jg) << lg) + (size_t)kg; };
+
+    // plane p-1 (red row of plane p-1 = black row of plane p)
+    float e0s = 0.f, X0s = 0.f, u0s = 0.f, w0s = 0.f;
+    // planes p (red updated, black old) and p+1 (old)
+    float e1a = ein[at(i0 - 2, jga)], e1b = ein[at(i0 - 2, jgb)];
+    float u1a = u[at(i0 - 2, jga)], u1b = u[at(i0 - 2, jgb)];
+    float e2a = ein[at(i0 - 1, jga)], e2b = ein[at(i0 - 1, jgb)];
+    float u2a = u[at(i0 - 1, jga)], u2b = u[at(i0 - 1, jgb)];
+    float r1s = 0.f;
+    float r2a = lda ? r[at(i0 - 1, jga)] : 0.f, r2b = ldb ? r[at(i0 - 1, jgb)] : 0.f;
+    float e4a = ein[at(i0, jga)], e4b = ein[at(i0, jgb)];
+    float u4a = u[at(i0, jga)], u4b = u[at(i0, jgb)];
+    float r4a = lda ? r[at(i0, jga)] : 0.f, r4b = ldb ? r[at(i0, jgb)] : 0.f;
+    float X1a = fexpm1(e1a), X1b = fexpm1(e1b), w1a = fexp(u1a), w1b = fexp(u1b);
+    float X2a = fexpm1(e2a), X2b = fexpm1(e2b), w2a = fexp(u2a), w2b = fexp(u2b);
+    int xb = 0;
+    for (int p = i0 - 2; p < i0 + chunk; ++p) {
+        const float e3a = e4a, e3b = e4b, u3a = u4a, u3b = u4b, r3a = r4a, r3b = r4b;
+        if (p + 1 < i0 + chunk) {
+            e4a = ein[at(p + 3, jga)];
+            e4b = ein[at(p + 3, jgb)];
+            u4a = u[at(p + 3, jga)];
+            u4b = u[at(p + 3, jgb)];
+            r4a = lda ? r[at(p + 3, jga)] : 0.f;
+            r4b = ldb ? r[at(p + 3, jgb)] : 0.f;
+        }
+        const float X3a = fexpm1(e3a), X3b = fexpm1(e3b), w3a = fexp(u3a), w3b = fexp(u3b);
+        __syncthreads();
+        sEv[xb][ra][lane] = e2a;
+        sEv[xb][rb][lane] = e2b;
+        sX[xb][ra][lane] = X2a;
+        sX[xb][rb][lane] = X2b;
+        sU[xb][ra][lane] = u2a;
+        sU[xb][rb][lane] = u2b;
+        sW[xb][ra][lane] = w2a;
+        sW[xb][rb][lane] = w2b;
+        __syncthreads();
+        const int sel = ((p + 1) + jga + kg) & 1;
+        const int rr = ra + sel;
+        const int rc = rr < 1 ? 1 : (rr > JL - 2 ? JL - 2 : rr);
+        {
+            const bool act = kin1 && (sel ? in1b : in1a);
+            const float ec = sel ? e2b : e2a, Xc = sel ? X2b : X2a, uc = sel ? u2b : u2a, wc = sel ? w2b : w2a;
+            const float d = mx_step6(
+                ec, Xc, uc, wc, mx_s<N1>(uc, wc, kc.q), sel ? r2b : r2a, sel ? e1b : e1a, sel ? X1b : X1a,
+                sel ? u1b : u1a, sel ? w1b : w1a, sel ? e3b : e3a, sel ? X3b : X3a, sel ? u3b : u3a,
+                sel ? w3b : w3a, sEv[xb][rc - 1][lane], sX[xb][rc - 1][lane], sU[xb][rc - 1][lane],
+                sW[xb][rc - 1][lane], sEv[xb][rc + 1][lane], sX[xb][rc + 1][lane], sU[xb][rc + 1][lane],
+                sW[xb][rc + 1][lane], sEv[xb][rc][lm], sX[xb][rc][lm], sU[xb][rc][lm], sW[xb][rc][lm],
+                sEv[xb][rc][lp], sX[xb][rc][lp], sU[xb][rc][lp], sW[xb][rc][lp], kc);
+            const float en = ec + d;
+            const float Xn = fexpm1(en);
+            e2a = (act && !sel) ? en : e2a;
+            X2a = (act && !sel) ? Xn : X2a;
+            e2b = (act && sel) ? en : e2b;
+            X2b = (act && sel) ? Xn : X2b;
+            if (act) {
+                sEv[xb][rr][lane] = en;
+                sX[xb][rr][lane] = Xn;
+            }
+        }
+        if (p >= i0) {
+            const int yb = xb ^ 1;
+            const bool act = kint && (sel ? intb : inta);
+            const float ec = sel ? e1b : e1a, Xc = sel ? X1b : X1a, uc = sel ? u1b : u1a, wc = sel ? w1b : w1a;
+            const float d = mx_step6(
+                ec, Xc, uc, wc, mx_s<N1>(uc, wc, kc.q), r1s, e0s, X0s, u0s, w0s, sel ? e2b : e2a,
+                sel ? X2b : X2a, sel ? u2b : u2a, sel ? w2b : w2a, sEv[yb][rc - 1][lane], sX[yb][rc - 1][lane],
+                sU[yb][rc - 1][lane], sW[yb][rc - 1][lane], sEv[yb][rc + 1][lane], sX[yb][rc + 1][lane],
+                sU[yb][rc + 1][lane], sW[yb][rc + 1][lane], sEv[yb][rc][lm], sX[yb][rc][lm], sU[yb][rc][lm],
+                sW[yb][rc][lm], sEv[yb][rc][lp], sX[yb][rc][lp], sU[yb][rc][lp], sW[yb][rc][lp], kc);
+            const float en = ec + d;
+            e1a = (act && !sel) ? en : e1a;
+            e1b = (act && sel) ? en : e1b;
+            if (kint && inta) eout[at(p, jga)] = e1a;
+            if (kint && intb) eout[at(p, jgb)] = e1b;
+        }
+        e0s = sel ? e1a : e1b;
+        X0s = sel ? X1a : X1b;
+        u0s = sel ? u1a : u1b;
+        w0s = sel ? w1a : w1b;
+        r1s = sel ? r2a : r2b;
+        e1a = e2a; e1b = e2b; X1a = X2a; X1b = X2b; u1a = u2a; u1b = u2b; w1a = w2a; w1b = w2b;
+        e2a = e3a; e2b = e3b; X2a = X3a; X2b = X3b; u2a = u3a; u2b = u3b; w2a = w3a; w2b = w3b;
+        r2a = r3a; r2b = r3b;
+        xb ^= 1;
+    }
+}
+
+// ------------------------------------------------------------------- kernels
+
+__global__ __launch_bounds__(kBlock) void k_mx_sweep_half(float *__restrict__ e, const float *__restrict__ u,
+                                                            const float *__restrict__ r, int lg, int colour,
+                                                            MxConst kc)
+{
+    mx_sweep_cell(e, u, r, (size_t)blockIdx.x * kBlock + threadIdx.x, lg, colour, kc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mx_residual_restrict(const float *__restrict__ e,
+                                                                   const float *__restrict__ u,
+                                                                   const float *__restrict__ r, int lg, MxConst kc,
+                                                                   float *__restrict__ eb_c, float *__restrict__ u_c,
+                                                                   float *__restrict__ r_c)
+{
+    const int lgc = lg - 1;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)), I = (int)(t >> (2 * lgc));
+    float em, um, rm;
+    mx_restrict_block(e, u, r, I, J, K, lg, kc, em, um, rm);
+    eb_c[t] = em;
+    u_c[t] = um;
+    r_c[t] = rm;
+}
+
+// r_c += N_c(eb); e_c = eb
+__global__ __launch_bounds__(kBlock) void k_mx_coarse_rhs(const float *__restrict__ eb, const float *__restrict__ u,
+                                                            int lg, MxConst kc, float *__restrict__ rc,
+                                                            float *__restrict__ ec)
+{
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int m = (1 << lg) - 1;
+    const int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
+    rc[t] += mx_value_at(eb, u, i, j, k, lg, kc);
+    ec[t] = eb[t];
+}
+
+// one thread per coarse cell: its 8 daughters of the 2^lg mesh
+__global__ __launch_bounds__(kBlock) void k_mx_prolong_add(float *__restrict__ e, const float *__restrict__ ec,
+                                                             const float *__restrict__ eb, int lg, int mode)
+{
+    const int lgc = lg - 1;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)), I = (int)(t >> (2 * lgc));
+    prolong_block(e, ec, eb, I, J, K, lgc, mode);
+}
+
+struct MxTail {
+    float *e[kMaxLevels];
+    float *u[kMaxLevels];
+    float *r[kMaxLevels];
+    float *eb[kMaxLevels];
+    float ih2[kMaxLevels];
+    int lg[kMaxLevels];
+    int l0, nlev, pre, post, coarse, mode;
+    float bC, q, max_du;
+};
+
+__device__ void mx_tail_sweeps(const MxTail &A, int l, int sweeps)
+{
+    const MxConst kc{A.ih2[l], A.bC, A.q, A.max_du};
+    const int lg = A.lg[l];
+    const size_t half = (size_t)1 << (3 * lg - 1);
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (size_t t = threadIdx.x; t < half; t += kTailThreads) mx_sweep_cell(A.e[l], A.u[l], A.r[l], t, lg, colour, kc);
+            __syncthreads();
+        }
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_mx_tail(MxTail A)
+{
+    for (int l = A.l0; l < A.nlev - 1; ++l) {
+        mx_tail_sweeps(A, l, A.pre);
+        const MxConst kc{A.ih2[l], A.bC, A.q, A.max_du};
+        const int lg = A.lg[l], lgc = lg - 1;
+        const size_t nc = (size_t)1 << (3 * lgc);
+        for (size_t t = threadIdx.x; t < nc; t += kTailThreads) {
+            const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)),
+                      I = (int)(t >> (2 * lgc));
+            float em, um, rm;
+            mx_restrict_cell(A.e[l], A.u[l], A.r[l], I, J, K, lg, kc, em, um, rm);
+            A.eb[l + 1][t] = em;
+            A.u[l + 1][t] = um;
+            A.r[l + 1][t] = rm;
+        }
+        __syncthreads();
+        const MxConst kcc{A.ih2[l + 1], A.bC, A.q, A.max_du};
+        const int mc = (1 << lgc) - 1;
+        for (size_t t = threadIdx.x; t < nc; t += kTailThreads) {
+            const int k = (int)(t & mc), j = (int)((t >> lgc) & mc), i = (int)(t >> (2 * lgc));
+            A.r[l + 1][t] += mx_value_at(A.eb[l + 1], A.u[l + 1], i, j, k, lgc, kcc);
+        }
+        __syncthreads();
+        for (size_t t = threadIdx.x; t < nc; t += kTailThreads) A.e[l + 1][t] = A.eb[l + 1][t];
+        __syncthreads();
+    }
+    mx_tail_sweeps(A, A.nlev - 1, A.coarse);
+    for (int l = A.nlev - 2; l >= A.l0; --l) {
+        const int lg = A.lg[l];
+        const size_t n = (size_t)1 << (3 * lg);
+        const int m = (1 << lg) - 1;
+        for (size_t t = threadIdx.x; t < n; t += kTailThreads) {
+            const int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
+            A.e[l][t] += mx_prolong(A.e[l + 1], A.eb[l + 1], i, j, k, lg - 1, A.mode);
+        }
+        __syncthreads();
+        mx_tail_sweeps(A, l, A.post);
+    }
+}
+
+// float64 residual of u on the finest level, its float32 copies for the inner
+// cycle, and per-block max / sum of squares (thread per 2x2x2 block)
+__global__ __launch_bounds__(kBlock) void k_mx_outer_residual(const double *__restrict__ u,
+                                                                const double *__restrict__ f, int lg, OpConst kc,
+                                                                float *__restrict__ r32, float *__restrict__ u32,
+                                                                float *__restrict__ e32,
+                                                                double *__restrict__ partial, int nparts)
+{
+    __shared__ double sh[2 * kBlock / 64];
+    const int lgc = lg - 1;
+    const size_t nblk = (size_t)1 << (3 * lgc);
+    double mx = 0.0, sm = 0.0;
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < nblk; t += (size_t)gridDim.x * kBlock) {
+        const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)),
+                  I = (int)(t >> (2 * lgc));
+        BlockRes br;
+        block_residuals(u, f, I, J, K, lg, kc, br);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const size_t cc = ix(2 * I + a, 2 * J + b, 2 * K + c, lg);
+                    const double r = br.r[(a * 2 + b) * 2 + c];
+                    r32[cc] = (float)r;
+                    u32[cc] = (float)u[cc];
+                    e32[cc] = 0.0f;
+                    mx = nanmax_d(mx, fabs(r));
+                    sm += r * r;
+                }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = nanmax_d(mx, __shfl_xor(mx, o, 64));
+        sm += __shfl_xor(sm, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = mx;
+        sh[kBlock / 64 + w] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            mx = nanmax_d(mx, sh[i]);
+            sm += sh[kBlock / 64 + i];
+        }
+        partial[blockIdx.x] = mx;
+        partial[nparts + blockIdx.x] = sm;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mx_update(double *__restrict__ u, const float *__restrict__ e, size_t n)
+{
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock)
+        u[t] += (double)e[t];
+}
+
+__global__ __launch_bounds__(1024) void k_mx_final(const double *__restrict__ partial, int nparts,
+                                                    double *__restrict__ out)
+{
+    __shared__ double sh[32];
+    double mx = 0.0, sm = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 1024) {
+        mx = nanmax_d(mx, partial[i]);
+        sm += partial[nparts + i];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = nanmax_d(mx, __shfl_xor(mx, o, 64));
+        sm += __shfl_xor(sm, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = mx;
+        sh[16 + (threadIdx.x >> 6)] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 16; ++i) {
+            mx = nanmax_d(mx, sh[i]);
+            sm += sh[16 + i];
+        }
+        out[0] = mx;
+        out[1] = sm;
+    }
+}
+
+inline unsigned nb(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+MxConst mx_const(const mgfr_ctx *c, int l)
+{
+    return MxConst{(float)(1.0 / (c->lev[l].h * c->lev[l].h)), (float)c->bC, (float)c->q, (float)c->p.max_du};
+}
+
+int mx_launch_sweeps(mgfr_ctx *c, int l, int sweeps, bool timed)
+{
+    Level &L = c->lev[l];
+    const MxConst kc = mx_const(c, l);
+    const size_t half = (size_t)1 << (3 * L.lg - 1);
+    for (int s = 0; s < sweeps; ++s) {
+        int slot = -1;
+        if (timed) {
+            Timer &T = c->sweep_timer;
+            if (T.used + 2 > (int)T.ev.size())
+                for (int q = 0; q < 16; ++q) {
+                    hipEvent_t ev;
+                    MGFR_HIP(hipEventCreate(&ev));
+                    T.ev.push_back(ev);
+                }
+            slot = T.used;
+            T.used += 2;
+            MGFR_HIP(hipEventRecord(T.ev[slot], c->stream));
+        }
+        const bool fused = c->fused32_min_n > 0 && L.N >= c->fused32_min_n && L.alt32 != nullptr;
+        if (fused) {
+            constexpr int JL = MGFR_FUSED32_JL;
+            const int chunk = L.N / 8 < 8 ? 8 : L.N / 8;
+            dim3 grid((unsigned)((L.N + MKI - 1) / MKI), (unsigned)((L.N + JL - 5) / (JL - 4)), (unsigned)(L.N / chunk));
+            if (c->p.n == 1)
+                k_mx_sweep_fused<true, JL><<<grid, 32 * JL, 0, c->stream>>>(L.e32, L.u32, L.r32, L.alt32, L.lg, chunk, kc);
+            else
+                k_mx_sweep_fused<false, JL><<<grid, 32 * JL, 0, c->stream>>>(L.e32, L.u32, L.r32, L.alt32, L.lg, chunk, kc);
+            std::swap(L.e32, L.alt32);
+        } else {
+            for (int colour = 0; colour < 2; ++colour)
+                k_mx_sweep_half<<<nb(half), kBlock, 0, c->stream>>>(L.e32, L.u32, L.r32, L.lg, colour, kc);
+        }
+        if (timed) MGFR_HIP(hipEventRecord(c->sweep_timer.ev[slot + 1], c->stream));
+    }
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
+}
+
+int mx_launch_tail(mgfr_ctx *c, int l0)
+{
+    MxTail A;
+    memset(&A, 0, sizeof A);
+    for (int l = 0; l < c->nlev; ++l) {
+        A.e[l] = c->lev[l].e32;
+        A.u[l] = c->lev[l].u32;
+        A.r[l] = c->lev[l].r32;
+        A.eb[l] = c->lev[l].ebar32;
+        A.ih2[l] = (float)(1.0 / (c->lev[l].h * c->lev[l].h));
+        A.lg[l] = c->lev[l].lg;
+    }
+    A.l0 = l0;
+    A.nlev = c->nlev;
+    A.pre = c->p.pre_smooth;
+    A.post = c->p.post_smooth;
+    A.coarse = c->p.coarse_sweeps;
+    A.mode = c->p.prolong;
+    A.bC = (float)c->bC;
+    A.q = (float)c->q;
+    A.max_du = (float)c->p.max_du;
+    k_mx_tail<<<1, kTailThreads, 0, c->stream>>>(A);
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
+}
+
+int mx_vcycle(mgfr_ctx *c, int l)
+{
+    Level &L = c->lev[l];
+    if (L.N <= kTailN) return mx_launch_tail(c, l);
+    int rc;
+    if ((rc = mx_launch_sweeps(c, l, c->p.pre_smooth, l == 0 && c->timing))) return rc;
+    Level &Lc = c->lev[l + 1];
+    const size_t nc = (size_t)1 << (3 * Lc.lg);
+    k_mx_residual_restrict<<<nb(nc), kBlock, 0, c->stream>>>(L.e32, L.u32, L.r32, L.lg, mx_const(c, l), Lc.ebar32,
+                                                             Lc.u32, Lc.r32);
+    k_mx_coarse_rhs<<<nb(nc), kBlock, 0, c->stream>>>(Lc.ebar32, Lc.u32, Lc.lg, mx_const(c, l + 1), Lc.r32, Lc.e32);
+    MGFR_HIP(hipGetLastError());
+    if ((rc = mx_vcycle(c, l + 1))) return rc;
+    k_mx_prolong_add<<<nb(nc), kBlock, 0, c->stream>>>(L.e32, Lc.e32, Lc.ebar32, L.lg, c->p.prolong);
+    MGFR_HIP(hipGetLastError());
+    return mx_launch_sweeps(c, l, c->p.post_smooth, l == 0 && c->timing);
+}
+
+}  // namespace
+
+int mixed_alloc(mgfr_ctx *c)
+{
+    for (int l = 0; l < c->nlev; ++l) {
+        Level &L = c->lev[l];
+        const size_t bytes = sizeof(float) * (size_t)L.N * L.N * L.N;
+        MGFR_HIP(hipMalloc(&L.e32, bytes));
+        if (L.N >= 64) MGFR_HIP(hipMalloc(&L.alt32, bytes));
+        MGFR_HIP(hipMalloc(&L.r32, bytes));
+        MGFR_HIP(hipMalloc(&L.u32, bytes));
+        if (l > 0) MGFR_HIP(hipMalloc(&L.ebar32, bytes));
+    }
+    return MGFR_OK;
+}
+
+// Float64 residual of the level-0 iterate (also prepares the float32 inner
+// problem); returns max|r| and sum r^2 on the host.
+static int outer_residual(mgfr_ctx *c, double *rmax, double *rsq)
+{
+    Level &L0 = c->lev[0];
+    const size_t nblk = (size_t)1 << (3 * (L0.lg - 1));
+    const unsigned g = (unsigned)std::min<size_t>(nb(nblk), (size_t)c->nparts);
+    k_mx_outer_residual<<<g, kBlock, 0, c->stream>>>(L0.u, L0.f, L0.lg, level_const(c, 0), L0.r32, L0.u32, L0.e32,
+                                                      c->partial, (int)g);
+    k_mx_final<<<1, 1024, 0, c->stream>>>(c->partial, (int)g, c->dscal);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipMemcpyAsync(c->hscal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    MGFR_HIP(hipStreamSynchronize(c->stream));
+    *rmax = c->hscal[0];
+    *rsq = c->hscal[1];
+    return MGFR_OK;
+}
+
+int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
+{
+    Level &L0 = c->lev[0];
+    const size_t n = (size_t)L0.N * L0.N * L0.N;
+    const double ncell = (double)n;
+    double rmax, rsq;
+    int rc = outer_residual(c, &rmax, &rsq);
+    if (rc) return rc;
+    double res = rmax / D, prev = res;
+    st->res0 = res;
+    int it = 0, grow = 0, status;
+    for (;;) {
+        if (!std::isfinite(res) || grow >= 3) {
+            // fall back: plain float64 solve from u = 0
+            MGFR_HIP(hipMemsetAsync(u, 0, n * sizeof(double), c->stream));
+            st->fell_back = 1;
+            const int outer = it;
+            status = solve_fp64_from(c, u, st, D);
+            st->outer_iters = outer + st->vcycles;
+            return status;
+        }
+        if (res <= c->p.tol) { status = MGFR_OK; break; }
+        if (it >= c->p.max_vcycles) { status = MGFR_NOT_CONVERGED; break; }
+        if ((rc = mx_vcycle(c, 0))) return rc;
+        k_mx_update<<<(unsigned)std::min<size_t>(nb(n), 8192), kBlock, 0, c->stream>>>(u, L0.e32, n);
+        MGFR_HIP(hipGetLastError());
+        if ((rc = outer_residual(c, &rmax, &rsq))) return rc;
+        if (c->timing && (rc = collect_timing(c, st))) return rc;
+        prev = res;
+        res = rmax / D;
+        grow = (res > prev) ? grow + 1 : 0;
+        if (it < MGFR_MAX_HIST) st->res_hist[it] = res;
+        ++it;
+    }
+    st->vcycles = it;
+    st->outer_iters = it;
+    st->res = res;
+    st->l2res = std::sqrt(rsq / ncell) / D;
+    return status;
+}
+
+}  // namespace mgfr

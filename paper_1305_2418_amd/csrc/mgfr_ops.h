@@ -1,0 +1,144 @@
+// Device helpers shared by the float64 and mixed-precision kernels.
+#pragma once
+
+#include "mgfr_internal.h"
+
+namespace mgfr {
+
+__device__ __forceinline__ size_t cidx(int i, int j, int k, int lg)
+{
+    return (((((size_t)i) << lg) + (size_t)j) << lg) + (size_t)k;
+}
+
+__device__ __forceinline__ double nanmax(double a, double b)
+{
+    return (a != a || a > b) ? a : b;
+}
+
+// Residuals r = f - L(u) at the 8 daughters of coarse cell (I,J,K) and their
+// mean values of u and r.  The 2x2x2 block plus its 24 face neighbours are
+// loaded once and each is exponentiated once.
+struct BlockRes {
+    double r[8];
+    double umean, rmean;
+};
+
+__device__ __forceinline__ void block_residuals(const double *__restrict__ u, const double *__restrict__ f,
+                                                int I, int J, int K, int lg, const OpConst &kc, BlockRes &out)
+{
+    const int m = (1 << lg) - 1;
+    const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
+    double B[2][2][2], EB[2][2][2];
+    double Xm[2][2], Xp[2][2], Ym[2][2], Yp[2][2], Zm[2][2], Zp[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                B[a][b][c] = u[cidx(i0 + a, j0 + b, k0 + c, lg)];
+                EB[a][b][c] = exp(B[a][b][c]);
+            }
+            Xm[a][b] = u[cidx((i0 - 1) & m, j0 + a, k0 + b, lg)];
+            Xp[a][b] = u[cidx((i0 + 2) & m, j0 + a, k0 + b, lg)];
+            Ym[a][b] = u[cidx(i0 + a, (j0 - 1) & m, k0 + b, lg)];
+            Yp[a][b] = u[cidx(i0 + a, (j0 + 2) & m, k0 + b, lg)];
+            Zm[a][b] = u[cidx(i0 + a, j0 + b, (k0 - 1) & m, lg)];
+            Zp[a][b] = u[cidx(i0 + a, j0 + b, (k0 + 2) & m, lg)];
+        }
+    double su = 0.0, sr = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double uc = B[a][b][c], ec = EB[a][b][c];
+                double nx0 = a ? Xp[b][c] : B[1][b][c];       // +x
+                double nx1 = a ? B[0][b][c] : Xm[b][c];       // -x
+                double ny0 = b ? Yp[a][c] : B[a][1][c];
+                double ny1 = b ? B[a][0][c] : Ym[a][c];
+                double nz0 = c ? Zp[a][b] : B[a][b][1];
+                double nz1 = c ? B[a][b][0] : Zm[a][b];
+                double ex0 = a ? exp(nx0) : EB[1][b][c];
+                double ex1 = a ? EB[0][b][c] : exp(nx1);
+                double ey0 = b ? exp(ny0) : EB[a][1][c];
+                double ey1 = b ? EB[a][0][c] : exp(ny1);
+                double ez0 = c ? exp(nz0) : EB[a][b][1];
+                double ez1 = c ? EB[a][b][0] : exp(nz1);
+                double d0 = nx0 - uc, d1 = nx1 - uc, d2 = ny0 - uc, d3 = ny1 - uc, d4 = nz0 - uc, d5 = nz1 - uc;
+                double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
+                double S3 = ((ex0 * d0 + ex1 * d1) + (ey0 * d2 + ey1 * d3)) + (ez0 * d4 + ez1 * d5);
+                double L = kc.ih2 * 0.5 * (S3 + ec * S1) + kc.bC * expm1(-kc.q * uc);
+                double r = f[cidx(i0 + a, j0 + b, k0 + c, lg)] - L;
+                out.r[(a * 2 + b) * 2 + c] = r;
+                su += uc;
+                sr += r;
+            }
+    out.umean = su / 8.0;
+    out.rmean = sr / 8.0;
+}
+
+// Linear (mode 0) or injected (mode 1) correction at fine cell (i,j,k):
+// P(uc - ubar) with the central-difference gradient at the parent centre.
+__device__ __forceinline__ double prolong_value(const double *__restrict__ uc, const double *__restrict__ ub,
+                                                int i, int j, int k, int lgc, int mode)
+{
+    const int m = (1 << lgc) - 1;
+    int I = i >> 1, J = j >> 1, K = k >> 1;
+    size_t P = cidx(I, J, K, lgc);
+    double v = uc[P] - ub[P];
+    if (mode == 0) {
+        size_t xp = cidx((I + 1) & m, J, K, lgc), xm = cidx((I - 1) & m, J, K, lgc);
+        size_t yp = cidx(I, (J + 1) & m, K, lgc), ym = cidx(I, (J - 1) & m, K, lgc);
+        size_t zp = cidx(I, J, (K + 1) & m, lgc), zm = cidx(I, J, (K - 1) & m, lgc);
+        double gx = (uc[xp] - ub[xp]) - (uc[xm] - ub[xm]);
+        double gy = (uc[yp] - ub[yp]) - (uc[ym] - ub[ym]);
+        double gz = (uc[zp] - ub[zp]) - (uc[zm] - ub[zm]);
+        double sx = (i & 1) ? 0.125 : -0.125, sy = (j & 1) ? 0.125 : -0.125, sz = (k & 1) ? 0.125 : -0.125;
+        v += sx * gx;
+        v += sy * gy;
+        v += sz * gz;
+    }
+    return v;
+}
+
+
+// Correction u += P(uc - ub) for the 8 daughters of coarse cell (I,J,K) of a
+// 2^lgc mesh: the parent value and gradient are formed once (same arithmetic
+// order as prolong_value).
+template <typename T>
+__device__ __forceinline__ void prolong_block(T *__restrict__ u, const T *__restrict__ uc, const T *__restrict__ ub,
+                                              int I, int J, int K, int lgc, int mode)
+{
+    const int m = (1 << lgc) - 1;
+    const size_t P = cidx(I, J, K, lgc);
+    const T v0 = uc[P] - ub[P];
+    T gx = 0, gy = 0, gz = 0;
+    if (mode == 0) {
+        const size_t xp = cidx((I + 1) & m, J, K, lgc), xm = cidx((I - 1) & m, J, K, lgc);
+        const size_t yp = cidx(I, (J + 1) & m, K, lgc), ym = cidx(I, (J - 1) & m, K, lgc);
+        const size_t zp = cidx(I, J, (K + 1) & m, lgc), zm = cidx(I, J, (K - 1) & m, lgc);
+        gx = (uc[xp] - ub[xp]) - (uc[xm] - ub[xm]);
+        gy = (uc[yp] - ub[yp]) - (uc[ym] - ub[ym]);
+        gz = (uc[zp] - ub[zp]) - (uc[zm] - ub[zm]);
+    }
+    const int lg = lgc + 1;
+    const T eighth = (T)0.125;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                T v = v0;
+                if (mode == 0) {
+                    v += (a ? eighth : -eighth) * gx;
+                    v += (b ? eighth : -eighth) * gy;
+                    v += (c ? eighth : -eighth) * gz;
+                }
+                u[cidx(2 * I + a, 2 * J + b, 2 * K + c, lg)] += v;
+            }
+}
+
+}  // namespace mgfr

@@ -12,6 +12,7 @@
 // Memory layout: every level is a dense N^3 float64 array in C order
 // (k fastest).  Index arithmetic uses N = 2^lg.
 #include "mgfr_internal.h"
+#include "mgfr_ops.h"
 
 #include <algorithm>
 #include <cmath>
@@ -42,16 +43,6 @@ int hip_fail(hipError_t e, const char *what, const char *file, int line)
 }
 
 // ------------------------------------------------------------ device helpers
-
-__device__ __forceinline__ size_t cidx(int i, int j, int k, int lg)
-{
-    return (((((size_t)i) << lg) + (size_t)j) << lg) + (size_t)k;
-}
-
-__device__ __forceinline__ double nanmax(double a, double b)
-{
-    return (a != a || a > b) ? a : b;
-}
 
 // Newton-Gauss-Seidel step for one cell from its value, its six neighbours and
 // its source: -(L_c - f_c) / (dL_c/du_c), optionally limited to |du| <= max_du.
@@ -113,94 +104,6 @@ __device__ __forceinline__ void sweep_cell(double *__restrict__ u, const double 
                          u[cidx(i, (j + 1) & m, k, lg)], u[cidx(i, (j - 1) & m, k, lg)],
                          u[cidx(i, j, (k + 1) & m, lg)], u[cidx(i, j, (k - 1) & m, lg)], f[c], kc);
     u[c] = uc + du;
-}
-
-// Residuals r = f - L(u) at the 8 daughters of coarse cell (I,J,K) and their
-// mean values of u and r.  The 2x2x2 block plus its 24 face neighbours are
-// loaded once and each is exponentiated once.
-struct BlockRes {
-    double r[8];
-    double umean, rmean;
-};
-
-__device__ __forceinline__ void block_residuals(const double *__restrict__ u, const double *__restrict__ f,
-                                                int I, int J, int K, int lg, const OpConst &kc, BlockRes &out)
-{
-    const int m = (1 << lg) - 1;
-    const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
-    double B[2][2][2], EB[2][2][2];
-    double Xm[2][2], Xp[2][2], Ym[2][2], Yp[2][2], Zm[2][2], Zp[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                B[a][b][c] = u[cidx(i0 + a, j0 + b, k0 + c, lg)];
-                EB[a][b][c] = exp(B[a][b][c]);
-            }
-            Xm[a][b] = u[cidx((i0 - 1) & m, j0 + a, k0 + b, lg)];
-            Xp[a][b] = u[cidx((i0 + 2) & m, j0 + a, k0 + b, lg)];
-            Ym[a][b] = u[cidx(i0 + a, (j0 - 1) & m, k0 + b, lg)];
-            Yp[a][b] = u[cidx(i0 + a, (j0 + 2) & m, k0 + b, lg)];
-            Zm[a][b] = u[cidx(i0 + a, j0 + b, (k0 - 1) & m, lg)];
-            Zp[a][b] = u[cidx(i0 + a, j0 + b, (k0 + 2) & m, lg)];
-        }
-    double su = 0.0, sr = 0.0;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                double uc = B[a][b][c], ec = EB[a][b][c];
-                double nx0 = a ? Xp[b][c] : B[1][b][c];       // +x
-                double nx1 = a ? B[0][b][c] : Xm[b][c];       // -x
-                double ny0 = b ? Yp[a][c] : B[a][1][c];
-                double ny1 = b ? B[a][0][c] : Ym[a][c];
-                double nz0 = c ? Zp[a][b] : B[a][b][1];
-                double nz1 = c ? B[a][b][0] : Zm[a][b];
-                double ex0 = a ? exp(nx0) : EB[1][b][c];
-                double ex1 = a ? EB[0][b][c] : exp(nx1);
-                double ey0 = b ? exp(ny0) : EB[a][1][c];
-                double ey1 = b ? EB[a][0][c] : exp(ny1);
-                double ez0 = c ? exp(nz0) : EB[a][b][1];
-                double ez1 = c ? EB[a][b][0] : exp(nz1);
-                double d0 = nx0 - uc, d1 = nx1 - uc, d2 = ny0 - uc, d3 = ny1 - uc, d4 = nz0 - uc, d5 = nz1 - uc;
-                double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
-                double S3 = ((ex0 * d0 + ex1 * d1) + (ey0 * d2 + ey1 * d3)) + (ez0 * d4 + ez1 * d5);
-                double L = kc.ih2 * 0.5 * (S3 + ec * S1) + kc.bC * expm1(-kc.q * uc);
-                double r = f[cidx(i0 + a, j0 + b, k0 + c, lg)] - L;
-                out.r[(a * 2 + b) * 2 + c] = r;
-                su += uc;
-                sr += r;
-            }
-    out.umean = su / 8.0;
-    out.rmean = sr / 8.0;
-}
-
-// Linear (mode 0) or injected (mode 1) correction at fine cell (i,j,k):
-// P(uc - ubar) with the central-difference gradient at the parent centre.
-__device__ __forceinline__ double prolong_value(const double *__restrict__ uc, const double *__restrict__ ub,
-                                                int i, int j, int k, int lgc, int mode)
-{
-    const int m = (1 << lgc) - 1;
-    int I = i >> 1, J = j >> 1, K = k >> 1;
-    size_t P = cidx(I, J, K, lgc);
-    double v = uc[P] - ub[P];
-    if (mode == 0) {
-        size_t xp = cidx((I + 1) & m, J, K, lgc), xm = cidx((I - 1) & m, J, K, lgc);
-        size_t yp = cidx(I, (J + 1) & m, K, lgc), ym = cidx(I, (J - 1) & m, K, lgc);
-        size_t zp = cidx(I, J, (K + 1) & m, lgc), zm = cidx(I, J, (K - 1) & m, lgc);
-        double gx = (uc[xp] - ub[xp]) - (uc[xm] - ub[xm]);
-        double gy = (uc[yp] - ub[yp]) - (uc[ym] - ub[ym]);
-        double gz = (uc[zp] - ub[zp]) - (uc[zm] - ub[zm]);
-        double sx = (i & 1) ? 0.125 : -0.125, sy = (j & 1) ? 0.125 : -0.125, sz = (k & 1) ? 0.125 : -0.125;
-        v += sx * gx;
-        v += sy * gy;
-        v += sz * gz;
-    }
-    return v;
 }
 
 // 1/x for finite non-zero x: hardware reciprocal refined by two Newton steps.
@@ -409,13 +312,14 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rhs(const double *__restrict_
     uc[t] = ubar[t];
 }
 
+// one thread per coarse cell: its 8 daughters of the 2^lg mesh
 __global__ __launch_bounds__(kBlock) void k_prolong_add(double *__restrict__ u, const double *__restrict__ uc,
                                                           const double *__restrict__ ub, int lg, int mode)
 {
-    size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    const int m = (1 << lg) - 1;
-    int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
-    u[t] += prolong_value(uc, ub, i, j, k, lg - 1, mode);
+    const int lgc = lg - 1;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)), I = (int)(t >> (2 * lgc));
+    prolong_block(u, uc, ub, I, J, K, lgc, mode);
 }
 
 template <int BS>
@@ -689,8 +593,7 @@ int vcycle64(mgfr_ctx *c, int l)
     k_coarse_rhs<<<nblocks(nc), kBlock, 0, c->stream>>>(Lc.ubar, Lc.lg, level_const(c, l + 1), Lc.f, Lc.u);
     MGFR_HIP(hipGetLastError());
     if ((rc = vcycle64(c, l + 1))) return rc;
-    const size_t n = (size_t)1 << (3 * L.lg);
-    k_prolong_add<<<nblocks(n), kBlock, 0, c->stream>>>(L.u, Lc.u, Lc.ubar, L.lg, c->p.prolong);
+    k_prolong_add<<<nblocks(nc), kBlock, 0, c->stream>>>(L.u, Lc.u, Lc.ubar, L.lg, c->p.prolong);
     MGFR_HIP(hipGetLastError());
     return launch_sweep64(c, l, L.u, L.f, c->p.post_smooth, l == 0 && c->timing);
 }
@@ -710,7 +613,7 @@ int launch_residual_norm64(mgfr_ctx *c, int l, const double *u, const double *f,
     return MGFR_OK;
 }
 
-static int collect_sweep_time(mgfr_ctx *c, mgfr_stats *st)
+int collect_timing(mgfr_ctx *c, mgfr_stats *st)
 {
     Timer &T = c->sweep_timer;
     for (int e = 0; e + 1 < T.used; e += 2) {
@@ -798,6 +701,7 @@ static void free_ctx(mgfr_ctx *c)
         (void)hipFree(L.r32);
         (void)hipFree(L.u32);
         (void)hipFree(L.ebar32);
+        (void)hipFree(L.alt32);
     }
     (void)hipFree(c->alt0);
     (void)hipFree(c->partial);
@@ -946,7 +850,7 @@ static int finish(mgfr_ctx *c, double *u, double *dfr, mgfr_stats *st, int statu
     return status;
 }
 
-static int solve_fp64(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
+int mgfr::solve_fp64_from(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
 {
     Level &L0 = c->lev[0];
     double rmax, rsq;
@@ -962,7 +866,7 @@ static int solve_fp64(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
         if (cyc >= c->p.max_vcycles) { status = MGFR_NOT_CONVERGED; break; }
         if ((rc = vcycle64(c, 0))) return rc;
         if ((rc = launch_residual_norm64(c, 0, u, L0.f, &rmax, &rsq))) return rc;
-        if (c->timing && (rc = collect_sweep_time(c, st))) return rc;
+        if (c->timing && (rc = collect_timing(c, st))) return rc;
         res = rmax / D;
         if (cyc < MGFR_MAX_HIST) st->res_hist[cyc] = res;
         ++cyc;
@@ -1000,7 +904,7 @@ extern "C" int mgfr_solve(mgfr_ctx *c, const double *delta, double *u, double *d
     if (c->p.precision == MGFR_MIXED) {
         status = solve_mixed(c, u, st, D);
     } else {
-        status = solve_fp64(c, u, st, D);
+        status = solve_fp64_from(c, u, st, D);
     }
     if (status < 0 && status != MGFR_ERR_NONFINITE) return status;
     if ((rc = restore_level0(c, u))) return rc;
@@ -1026,6 +930,7 @@ extern "C" int mgfr_set_fused_min_mesh(mgfr_ctx *c, int n)
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
     if (n != 0 && n < 64) return set_error(MGFR_ERR_ARG, "fused sweeps need levels of at least 64^3 (or 0 = off)");
     c->fused_min_n = n;
+    c->fused32_min_n = n;
     return MGFR_OK;
 }
 

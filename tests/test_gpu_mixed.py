@@ -1,0 +1,71 @@
+"""Mixed-precision solve (float32 correction cycles inside a float64 defect
+correction) against the FP64 CPU oracle: it must reach the same relative
+residual tolerance and agree with the oracle's solution to 1e-6 relative in
+delta f_R."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1305_2418_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _delta(N, rms, seed, halos):
+    pos = synth.clustered_load(N, 100.0, rms=rms, seed=seed, n_halos=halos).numpy()
+    return O.density_contrast(O.cic_assign(N, 100.0, pos))
+
+
+CASES = [(32, 1.0, 0, 1e-5, 1.0, 1), (64, 5.0, 20, 1e-5, 1.0, 2), (64, 5.0, 20, 1e-6, 1.0, 2),
+         (64, 5.0, 20, 1e-6, 0.5, 3), (128, 5.0, 20, 1e-6, 1.0, 4)]
+
+
+@pytest.mark.parametrize("N,rms,halos,fr0,a,seed", CASES)
+def test_mixed_solve_matches_fp64_oracle(N, rms, halos, fr0, a, seed):
+    from paper_1305_2418_amd import mgfr
+    print(f"[case] mixed N={N} fr0={fr0} a={a}", flush=True)
+    d = _delta(N, rms, seed, halos)
+    # reference: the oracle iterated well below the tolerance
+    s_o, u_o, dfr_o, st_o = O.solve(O.params(mesh=N, fr0_abs=fr0, a=a, tol=1e-11, max_vcycles=100), d)
+    assert s_o == 0
+    s = mgfr.Solver(mgfr.Params(mesh=N, fr0_abs=fr0, a=a, precision=mgfr.MIXED))
+    u, dfr, st = s.solve(torch.tensor(d, device=DEV))
+    assert st.status == 0 and st.fell_back == 0 and st.res <= 1e-8
+    err = np.abs(dfr.cpu().numpy() - dfr_o).max() / np.abs(dfr_o).max()
+    print(f"  outer iterations {st.outer_iters}, res {st.res:.2e}, rel dfr err {err:.2e}")
+    assert err < 1e-6
+    # its float64 residual agrees with the oracle's evaluation of the same u
+    fb, beta, C = O.background(O.params(mesh=N, fr0_abs=fr0, a=a))
+    f = beta * 0.3 / a ** 3 * d
+    r = O.residual_max(u.cpu().numpy(), f, 100.0 / N, beta * C) / np.abs(f).max()
+    assert r <= 1e-8 and abs(r / st.res - 1) < 1e-3
+
+
+def test_mixed_falls_back_to_fp64_on_bad_guess():
+    from paper_1305_2418_amd import mgfr
+    d = _delta(32, 1.0, 1, 0)
+    s = mgfr.Solver(mgfr.Params(mesh=32, precision=mgfr.MIXED))
+    u0 = torch.zeros((32, 32, 32), dtype=torch.float64, device=DEV)
+    u0[5, 5, 5] = float("nan")
+    u, dfr, st = s.solve(torch.tensor(d, device=DEV), u=u0)
+    assert st.fell_back == 1 and st.status == 0 and st.res <= 1e-8
+    s_o, u_o, dfr_o, st_o = O.solve(O.params(mesh=32), d)
+    assert np.abs(dfr.cpu().numpy() - dfr_o).max() / np.abs(dfr_o).max() < 1e-6
+
+
+@pytest.mark.parametrize("N,fr0,a", [(64, 1e-6, 1.0), (128, 1e-6, 0.5), (128, 1e-5, 1.0)])
+def test_mixed_fused_sweeps_match_fp64_oracle(N, fr0, a):
+    """Same as above with the fused float32 sweep forced on for every level >= 64^3."""
+    from paper_1305_2418_amd import mgfr
+    print(f"[case] mixed fused N={N} fr0={fr0} a={a}", flush=True)
+    d = _delta(N, 5.0, 7, 20)
+    s_o, u_o, dfr_o, st_o = O.solve(O.params(mesh=N, fr0_abs=fr0, a=a, tol=1e-11, max_vcycles=100), d)
+    s = mgfr.Solver(mgfr.Params(mesh=N, fr0_abs=fr0, a=a, precision=mgfr.MIXED))
+    s.set_fused_min_mesh(64)
+    u, dfr, st = s.solve(torch.tensor(d, device=DEV))
+    assert st.status == 0 and st.fell_back == 0 and st.res <= 1e-8
+    err = np.abs(dfr.cpu().numpy() - dfr_o).max() / np.abs(dfr_o).max()
+    print(f"  outer iterations {st.outer_iters} (oracle {st_o.vcycles} to 1e-11), rel dfr err {err:.2e}")
+    assert err < 1e-6

@@ -162,6 +162,65 @@ int mgfr_ngs_sweep(mgfr_ctx *ctx, double *u, const double *f, int sweeps);
 int mgfr_vcycle(mgfr_ctx *ctx, double *u, const double *f);
 int mgfr_residual(mgfr_ctx *ctx, const double *u, const double *f, double *r);
 
+/* ---------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method).  A 3-level 3D U-Net
+ * (16/32/64 channels, 3^3 periodic convolutions, bfloat16 weights and
+ * activations, float32 accumulation) maps delta on a periodic S^3 mesh, with
+ * the scale factor and |f_R0| as constant input channels, to u on that mesh.
+ * With nn_mode = MGFR_NN_COARSE, mgfr_solve restricts delta to the N/4 mesh
+ * (means of 4^3 cells), predicts u there, prolongs it twice with the linear
+ * reconstruction of Sec. 3.3 and uses the result as the initial guess; the
+ * multigrid iteration then runs to the same tolerance as without it.
+ * The network object owns its weights, Adam moments and activation
+ * workspace (allocated in mgfr_net_create); the solver context only borrows
+ * it.  Arrays are device pointers unless stated; bf16 tensors are
+ * channels-last [B][S][S][S][C] with voxel index ((b S + z) S + y) S + x.
+ * --------------------------------------------------------------------- */
+typedef struct mgfr_net mgfr_net;
+
+/* He-normal weights from `seed`, zero biases; workspace for up to
+ * max_voxels = B * S^3 voxels per call (a multiple of 4096). */
+int mgfr_net_create(int seed, int64_t max_voxels, void *stream, mgfr_net **out);
+void mgfr_net_destroy(mgfr_net *net);
+int mgfr_net_set_stream(mgfr_net *net, void *stream);
+/* Number of float32 parameters (conv weights [27][Cout][Cin] then biases, layer by layer, then the head). */
+int64_t mgfr_net_num_params(const mgfr_net *net);
+/* Copy the float32 master parameters to / from a HOST buffer of mgfr_net_num_params floats;
+ * set_params also resets the Adam state. */
+int mgfr_net_get_params(mgfr_net *net, float *host);
+int mgfr_net_set_params(mgfr_net *net, const float *host);
+/* u = network(delta) for B volumes of side S (power of two, 32 <= S <= 1024).
+ * delta, u: float64 [B][S^3]; cond: HOST float64 [B][2] = (a, |f_R0|) per volume. */
+int mgfr_net_predict(mgfr_net *net, const double *delta, int B, int S, const double *cond, double *u);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error
+ * between the network output and u_target / 5; *loss (host, nullable) gets the loss
+ * before the step.  Returns MGFR_ERR_NONFINITE if the loss is not finite. */
+int mgfr_net_train_step(mgfr_net *net, const double *delta, const double *u_target, int B, int S,
+                        const double *cond, float lr, float *loss);
+/* Loss and its gradient with respect to every parameter (HOST float32 [num_params]),
+ * without updating the weights. */
+int mgfr_net_grads(mgfr_net *net, const double *delta, const double *u_target, int B, int S,
+                   const double *cond, float *loss, float *grad_host);
+/* Attach (or detach with NULL) the network used by nn_mode = MGFR_NN_COARSE. */
+int mgfr_set_net(mgfr_ctx *ctx, mgfr_net *net);
+
+/* Single convolution layers on bf16 tensors (the network's building blocks),
+ * on `stream`, no synchronisation:
+ *   fwd:         y[v][o] = act(sum_{t,c} x[v+off(t)][c] w[t][o][c] + bias[o]), periodic;
+ *                w bf16 [27][Cout][Cin], bias float32 [Cout] or NULL, relu 0/1;
+ *                y bf16 and/or y32 float32 outputs [V][Cout] (either may be NULL).
+ *                Cin % 8 == 0, Cout % 16 == 0, both <= 96, S >= 8 a power of two.
+ *   bwd_data:    dx[v][c] = sum_{t,o} dz[v-off(t)][o] w[t][o][c]; wt_work: bf16 scratch
+ *                of 27*Cin*Cout elements (caller-owned); Cin % 16 == 0.
+ *   bwd_weight:  dw[t][o][c] += sum_v dz[v][o] x[v+off(t)][c] (float32, accumulated with
+ *                atomics, so summation order varies); db[o] += sum_v dz[v][o] if db != NULL. */
+int mgfr_conv3d_fwd(const void *x, int B, int S, int Cin, const void *w, const float *bias, int Cout,
+                    int relu, void *y, float *y32, void *stream);
+int mgfr_conv3d_bwd_data(const void *dz, int B, int S, int Cout, const void *w, int Cin, void *wt_work,
+                         void *dx, void *stream);
+int mgfr_conv3d_bwd_weight(const void *x, const void *dz, int B, int S, int Cin, int Cout, float *dw,
+                           float *db, void *stream);
+
 /* Last error message of this host thread ("" if none). */
 const char *mgfr_last_error(void);
 

@@ -126,6 +126,22 @@ def lib() -> C.CDLL:
         L.mgfr_ngs_sweep.argtypes = [_VP, _VP, _VP, C.c_int]
         L.mgfr_vcycle.argtypes = [_VP, _VP, _VP]
         L.mgfr_residual.argtypes = [_VP, _VP, _VP, _VP]
+        L.mgfr_net_create.argtypes = [C.c_int, C.c_int64, _VP, C.POINTER(_VP)]
+        L.mgfr_net_destroy.argtypes = [_VP]
+        L.mgfr_net_destroy.restype = None
+        L.mgfr_net_set_stream.argtypes = [_VP, _VP]
+        L.mgfr_net_num_params.argtypes = [_VP]
+        L.mgfr_net_num_params.restype = C.c_int64
+        L.mgfr_net_get_params.argtypes = [_VP, _VP]
+        L.mgfr_net_set_params.argtypes = [_VP, _VP]
+        L.mgfr_net_predict.argtypes = [_VP, _VP, C.c_int, C.c_int, _VP, _VP]
+        L.mgfr_net_train_step.argtypes = [_VP, _VP, _VP, C.c_int, C.c_int, _VP, C.c_float,
+                                          C.POINTER(C.c_float)]
+        L.mgfr_net_grads.argtypes = [_VP, _VP, _VP, C.c_int, C.c_int, _VP, C.POINTER(C.c_float), _VP]
+        L.mgfr_set_net.argtypes = [_VP, _VP]
+        L.mgfr_conv3d_fwd.argtypes = [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, C.c_int, C.c_int, _VP, _VP, _VP]
+        L.mgfr_conv3d_bwd_data.argtypes = [_VP, C.c_int, C.c_int, C.c_int, _VP, C.c_int, _VP, _VP, _VP]
+        L.mgfr_conv3d_bwd_weight.argtypes = [_VP, _VP, C.c_int, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]
         _lib = L
     return _lib
 
@@ -246,6 +262,10 @@ class Solver:
         _check(lib().mgfr_fifth_force(self._h, up, pp, npart, ap))
         return out
 
+    def set_net(self, net):
+        _check(lib().mgfr_set_net(self._h, None if net is None else net._h))
+        self._net = net
+
     def ngs_sweep(self, u: torch.Tensor, f: torch.Tensor, sweeps: int = 1):
         self._sync_stream()
         _check(lib().mgfr_ngs_sweep(self._h, _dev(u, torch.float64, self.shape, "u"),
@@ -265,3 +285,121 @@ class Solver:
                                    _dev(f, torch.float64, self.shape, "f"),
                                    _dev(r, torch.float64, self.shape, "r")))
         return r
+
+
+def _cond_array(cond):
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(cond, dtype=np.float64).reshape(-1, 2))
+    return arr, arr.ctypes.data_as(C.c_void_p)
+
+
+class Net:
+    """The learned warm-start network (weights, Adam state, workspace on the device)."""
+
+    def __init__(self, seed: int = 0, max_voxels: int = 128 ** 3, stream=None):
+        h = _VP()
+        s = _stream_ptr() if stream is None else stream
+        _check(lib().mgfr_net_create(int(seed), int(max_voxels), s, C.byref(h)))
+        self._h = h
+        self.max_voxels = max_voxels
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgfr_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync(self):
+        _check(lib().mgfr_net_set_stream(self._h, _stream_ptr()))
+
+    @property
+    def num_params(self) -> int:
+        return int(lib().mgfr_net_num_params(self._h))
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(lib().mgfr_net_get_params(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.num_params:
+            raise ValueError("wrong parameter count")
+        _check(lib().mgfr_net_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+
+    def predict(self, delta: torch.Tensor, cond) -> torch.Tensor:
+        self._sync()
+        B, S = delta.shape[0], delta.shape[1]
+        _dev(delta, torch.float64, (B, S, S, S), "delta")
+        u = torch.empty_like(delta)
+        arr, cp = _cond_array(cond)
+        if arr.shape[0] != B:
+            raise ValueError("cond must have one (a, |f_R0|) row per volume")
+        _check(lib().mgfr_net_predict(self._h, delta.data_ptr(), B, S, cp, u.data_ptr()))
+        return u
+
+    def train_step(self, delta: torch.Tensor, u_target: torch.Tensor, cond, lr: float) -> float:
+        self._sync()
+        B, S = delta.shape[0], delta.shape[1]
+        _dev(delta, torch.float64, (B, S, S, S), "delta")
+        _dev(u_target, torch.float64, (B, S, S, S), "u_target")
+        arr, cp = _cond_array(cond)
+        loss = C.c_float()
+        _check(lib().mgfr_net_train_step(self._h, delta.data_ptr(), u_target.data_ptr(), B, S, cp,
+                                         float(lr), C.byref(loss)))
+        return loss.value
+
+    def grads(self, delta: torch.Tensor, u_target: torch.Tensor, cond):
+        import numpy as np
+        self._sync()
+        B, S = delta.shape[0], delta.shape[1]
+        arr, cp = _cond_array(cond)
+        g = np.empty(self.num_params, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().mgfr_net_grads(self._h, delta.data_ptr(), u_target.data_ptr(), B, S, cp, C.byref(loss),
+                                    g.ctypes.data_as(C.c_void_p)))
+        return loss.value, g
+
+
+def conv3d_fwd(x: torch.Tensor, w: torch.Tensor, bias=None, relu=False, out32=False):
+    """x bf16 [B,S,S,S,Cin], w bf16 [27,Cout,Cin] -> bf16 (or float32) [B,S,S,S,Cout]."""
+    B, S, Cin = x.shape[0], x.shape[1], x.shape[-1]
+    Cout = w.shape[1]
+    _dev(x, torch.bfloat16, None, "x")
+    _dev(w, torch.bfloat16, (27, Cout, Cin), "w")
+    if bias is not None:
+        _dev(bias, torch.float32, (Cout,), "bias")
+    y = torch.empty((B, S, S, S, Cout), dtype=torch.float32 if out32 else torch.bfloat16, device=x.device)
+    _check(lib().mgfr_conv3d_fwd(x.data_ptr(), B, S, Cin, w.data_ptr(),
+                                 None if bias is None else bias.data_ptr(), Cout, 1 if relu else 0,
+                                 None if out32 else y.data_ptr(), y.data_ptr() if out32 else None,
+                                 _stream_ptr()))
+    return y
+
+
+def conv3d_bwd_data(dz: torch.Tensor, w: torch.Tensor):
+    B, S, Cout = dz.shape[0], dz.shape[1], dz.shape[-1]
+    Cin = w.shape[2]
+    _dev(dz, torch.bfloat16, None, "dz")
+    _dev(w, torch.bfloat16, (27, Cout, Cin), "w")
+    work = torch.empty_like(w)
+    dx = torch.empty((B, S, S, S, Cin), dtype=torch.bfloat16, device=dz.device)
+    _check(lib().mgfr_conv3d_bwd_data(dz.data_ptr(), B, S, Cout, w.data_ptr(), Cin, work.data_ptr(),
+                                      dx.data_ptr(), _stream_ptr()))
+    return dx
+
+
+def conv3d_bwd_weight(x: torch.Tensor, dz: torch.Tensor):
+    B, S, Cin, Cout = x.shape[0], x.shape[1], x.shape[-1], dz.shape[-1]
+    dw = torch.zeros((27, Cout, Cin), dtype=torch.float32, device=x.device)
+    db = torch.zeros((Cout,), dtype=torch.float32, device=x.device)
+    _check(lib().mgfr_conv3d_bwd_weight(x.data_ptr(), dz.data_ptr(), B, S, Cin, Cout, dw.data_ptr(),
+                                        db.data_ptr(), _stream_ptr()))
+    return dw, db

@@ -70,7 +70,7 @@ typedef struct mgfr_params {
     double omega_l;  /* vacuum density parameter, >= 0 */
     double fr0_abs;  /* |fbar_R0| > 0 (the paper's fbar_R0 is negative) */
     int n;           /* Hu-Sawicki exponent n >= 1 (the paper runs n = 1) */
-    int mesh;        /* N: cells per side, a power of two, 8 <= N <= 2048 */
+    int mesh;        /* N: cells per side, a power of two, 8 <= N <= 1024 (the 1024^3 solve needs ~60 GB) */
     int refine_levels; /* must be 0 for the uniform-mesh context */
     double tol;      /* accept when max|f - L(u)| / D <= tol, D = max|f| (Sec. 3.3 step 8); > 0 */
     int pre_smooth;  /* red-black sweeps before restriction, >= 0 */

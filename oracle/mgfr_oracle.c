@@ -427,3 +427,416 @@ void or_fifth_force(const or_params *p, const double *u, int64_t np, const float
     free(fr);
     free(g);
 }
+
+/* ------------------------------------------------- sampled checks (large meshes) */
+
+/* Residual f - L(u) at `count` listed cells (flat C-order indices). */
+void or_residual_at(int N, double h, double bC, int n, const double *u, const double *f, int64_t count,
+                    const int64_t *cells, double *out)
+{
+    double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
+    for (int64_t s = 0; s < count; ++s) {
+        int64_t c = cells[s];
+        int k = (int)(c % N), j = (int)((c / N) % N), i = (int)(c / ((int64_t)N * N));
+        out[s] = f[c] - op_cell(u, N, i, j, k, ih2, bC, q, NULL);
+    }
+}
+
+/* Cloud-in-cell mass of `count` listed cells, scanning every particle
+ * (same weights as or_cic_assign; `mark` is caller scratch of N^3 bytes). */
+void or_cic_cells(int N, double box, int64_t np, const float *pos, const double *mass, int64_t count,
+                  const int64_t *cells, unsigned char *mark, double *out)
+{
+    double h = box / N;
+    size_t n3 = (size_t)N * N * N;
+    memset(mark, 0, n3);
+    for (int64_t s = 0; s < count; ++s) { mark[cells[s]] = 1; out[s] = 0.0; }
+    for (int64_t p = 0; p < np; ++p) {
+        long i0[3];
+        double t[3];
+        for (int d = 0; d < 3; ++d) {
+            double xi = (double)pos[3 * p + d] / h - 0.5;
+            double fl = floor(xi);
+            t[d] = xi - fl;
+            i0[d] = (long)fl;
+        }
+        double mp = mass ? mass[p] : 1.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    size_t cell = ((size_t)wrapi(i0[0] + a, N) * N + wrapi(i0[1] + b, N)) * N + wrapi(i0[2] + c, N);
+                    if (!mark[cell]) continue;
+                    double w = (a ? t[0] : 1.0 - t[0]) * (b ? t[1] : 1.0 - t[1]) * (c ? t[2] : 1.0 - t[2]);
+                    for (int64_t s = 0; s < count; ++s)
+                        if ((size_t)cells[s] == cell) out[s] += w * mp;
+                }
+    }
+}
+
+/* Fifth force (as or_fifth_force) at `np` particles, f_R evaluated on the fly. */
+void or_fifth_force_at(const or_params *p, const double *u, int64_t np, const float *pos, double *acc)
+{
+    int N = p->mesh;
+    double h = p->box / N;
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    double pref = OR_C_KMS * OR_C_KMS / (2.0 * p->a);
+#define FR(i, j, k) (-fb * exp(u[((size_t)wrapi(i, N) * N + wrapi(j, N)) * N + wrapi(k, N)]))
+    for (int64_t q = 0; q < np; ++q) {
+        long i0[3];
+        double t[3];
+        for (int d = 0; d < 3; ++d) {
+            double xi = (double)pos[3 * q + d] / h - 0.5;
+            double fl = floor(xi);
+            t[d] = xi - fl;
+            i0[d] = (long)fl;
+        }
+        double s[3] = {0, 0, 0};
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    double w = (a ? t[0] : 1.0 - t[0]) * (b ? t[1] : 1.0 - t[1]) * (c ? t[2] : 1.0 - t[2]);
+                    long i = i0[0] + a, j = i0[1] + b, k = i0[2] + c;
+                    s[0] += w * (FR(i + 1, j, k) - FR(i - 1, j, k)) / (2 * h);
+                    s[1] += w * (FR(i, j + 1, k) - FR(i, j - 1, k)) / (2 * h);
+                    s[2] += w * (FR(i, j, k + 1) - FR(i, j, k - 1)) / (2 * h);
+                }
+        for (int d = 0; d < 3; ++d) acc[3 * q + d] = pref * s[d];
+    }
+#undef FR
+}
+
+/* ------------------------------------------------------------- refined levels
+ *
+ * Block-structured adaptive refinement with the paper's one-way interface
+ * (Sec. 3.3, steps 9-12).  Level l has N_l = N_0 2^l cells per side.  A cell
+ * of level l-1 holding more than 8 particles (nearest-grid-point count) is
+ * refined: its children and those of the aligned 4^3 group of level-(l-1)
+ * cells around it form an 8^3 block of level l.  Level-2 blocks also refine
+ * every level-1 block within two level-1 cells of them, so that the ghost
+ * cells of level 2 and the parents they are prolonged from lie on level 1.
+ * Each level is solved after its parent: the initial guess and the ghost layer
+ * around the union of blocks come from the linear prolongation of the parent
+ * solution (fixed during the level solve), and the level is solved by FAS
+ * V-cycles whose coarse grids are the union of blocks at 1/2, 1/4 and 1/8
+ * resolution (one cell per block at the coarsest; every coarse cell is fully
+ * covered, so the paper's mask is 1 on all of them); coarse cells outside the
+ * union hold the parent solution at that resolution (restricted from the base
+ * below the base resolution) and are never updated.
+ *
+ * Dense storage: every level is an N_l^3 array with a mask; this oracle only
+ * needs small meshes.                                                         */
+
+#define OR_AMR_MAXL 3
+
+typedef struct {
+    int N;            /* side at this resolution */
+    double h;
+    unsigned char *mask; /* 1 = unknown of the level solve */
+    double *u, *f, *fr;  /* fr: frozen values outside the mask */
+    double *ubar, *r;
+} or_sub;
+
+static size_t cube(int n) { return (size_t)n * n * n; }
+
+#define SIDX(S, i, j, k) ((((size_t)wrapi(i, (S)->N)) * (S)->N + wrapi(j, (S)->N)) * (S)->N + wrapi(k, (S)->N))
+
+static double sval(const or_sub *S, long i, long j, long k)
+{
+    size_t c = SIDX(S, i, j, k);
+    return S->mask[c] ? S->u[c] : S->fr[c];
+}
+
+/* L and dL/du at a masked cell, neighbours from the unknowns or the frozen values */
+static double sub_op(const or_sub *S, int i, int j, int k, double bC, double q, double *J)
+{
+    double ih2 = 1.0 / (S->h * S->h);
+    double uc = S->u[SIDX(S, i, j, k)];
+    double nb[6] = {sval(S, i + 1, j, k), sval(S, i - 1, j, k), sval(S, i, j + 1, k),
+                    sval(S, i, j - 1, k), sval(S, i, j, k + 1), sval(S, i, j, k - 1)};
+    double ec = exp(uc), lap = 0.0, dlap = 0.0;
+    for (int s = 0; s < 6; ++s) {
+        double en = exp(nb[s]);
+        lap += 0.5 * (en + ec) * (nb[s] - uc);
+        dlap += 0.5 * (ec * (nb[s] - uc - 1.0) - en);
+    }
+    double em = expm1(-q * uc);
+    if (J) *J = ih2 * dlap - bC * q * (1.0 + em);
+    return ih2 * lap + bC * em;
+}
+
+static void sub_sweep(or_sub *S, double bC, double q, double max_du)
+{
+    int N = S->N;
+    for (int colour = 0; colour < 2; ++colour)
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                for (int k = 0; k < N; ++k) {
+                    size_t c = ((size_t)i * N + j) * N + k;
+                    if (!S->mask[c] || ((i + j + k) & 1) != colour) continue;
+                    double J;
+                    double L = sub_op(S, i, j, k, bC, q, &J);
+                    double du = -(L - S->f[c]) / J;
+                    if (max_du > 0.0) du = fmin(fmax(du, -max_du), max_du);
+                    S->u[c] += du;
+                }
+}
+
+static double sub_resmax(or_sub *S, double bC, double q)
+{
+    int N = S->N;
+    double mx = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) {
+                size_t c = ((size_t)i * N + j) * N + k;
+                if (!S->mask[c]) continue;
+                double r = fabs(S->f[c] - sub_op(S, i, j, k, bC, q, NULL));
+                if (!(r <= mx)) mx = r;
+            }
+    return mx;
+}
+
+static void amr_vcycle(or_sub *Sv, int m, int nsub, const or_params *p, double bC, double q)
+{
+    or_sub *S = &Sv[m];
+    if (m == nsub - 1) {
+        for (int s = 0; s < p->coarse_sweeps; ++s) sub_sweep(S, bC, q, p->max_du);
+        return;
+    }
+    for (int s = 0; s < p->pre_smooth; ++s) sub_sweep(S, bC, q, p->max_du);
+    int N = S->N;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) {
+                size_t c = ((size_t)i * N + j) * N + k;
+                S->r[c] = S->mask[c] ? S->f[c] - sub_op(S, i, j, k, bC, q, NULL) : 0.0;
+            }
+    or_sub *C = &Sv[m + 1];
+    int Nc = C->N;
+    for (int I = 0; I < Nc; ++I)
+        for (int Jx = 0; Jx < Nc; ++Jx)
+            for (int K = 0; K < Nc; ++K) {
+                size_t cc = ((size_t)I * Nc + Jx) * Nc + K;
+                if (!C->mask[cc]) continue;
+                double su = 0.0, sr = 0.0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b)
+                        for (int d = 0; d < 2; ++d) {
+                            size_t fc = (((size_t)(2 * I + a)) * N + (2 * Jx + b)) * N + (2 * K + d);
+                            su += S->u[fc];
+                            sr += S->r[fc];
+                        }
+                C->ubar[cc] = su / 8.0;
+                C->f[cc] = sr / 8.0;
+            }
+    for (size_t cc = 0; cc < cube(Nc); ++cc) if (C->mask[cc]) C->u[cc] = C->ubar[cc];
+    for (int I = 0; I < Nc; ++I)
+        for (int Jx = 0; Jx < Nc; ++Jx)
+            for (int K = 0; K < Nc; ++K) {
+                size_t cc = ((size_t)I * Nc + Jx) * Nc + K;
+                if (C->mask[cc]) C->f[cc] += sub_op(C, I, Jx, K, bC, q, NULL);
+            }
+    amr_vcycle(Sv, m + 1, nsub, p, bC, q);
+    /* correction u += P(e), e = u_c - ubar on the coarse unknowns and 0 elsewhere */
+#define EC(a, b, c) (C->mask[SIDX(C, a, b, c)] ? C->u[SIDX(C, a, b, c)] - C->ubar[SIDX(C, a, b, c)] : 0.0)
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) {
+                size_t c = ((size_t)i * N + j) * N + k;
+                if (!S->mask[c]) continue;
+                int I = i / 2, Jx = j / 2, K = k / 2;
+                double v = EC(I, Jx, K);
+                if (p->prolong == 0) {
+                    double si = (i & 1) ? 1.0 : -1.0, sj = (j & 1) ? 1.0 : -1.0, sk = (k & 1) ? 1.0 : -1.0;
+                    v += si * (EC(I + 1, Jx, K) - EC(I - 1, Jx, K)) / 8.0;
+                    v += sj * (EC(I, Jx + 1, K) - EC(I, Jx - 1, K)) / 8.0;
+                    v += sk * (EC(I, Jx, K + 1) - EC(I, Jx, K - 1)) / 8.0;
+                }
+                S->u[c] += v;
+            }
+#undef EC
+    for (int s = 0; s < p->post_smooth; ++s) sub_sweep(S, bC, q, p->max_du);
+}
+
+/* linear prolongation of a full field (values, not corrections) to cell (i,j,k) of a
+ * mesh of side 2N from the side-N field P (periodic) */
+static double prolong_field_at(const double *P, int N, long i, long j, long k)
+{
+    long I = i / 2, J = j / 2, K = k / 2;
+    if (i < 0) I = (i - 1) / 2;
+    if (j < 0) J = (j - 1) / 2;
+    if (k < 0) K = (k - 1) / 2;
+#define PV(a, b, c) P[((size_t)wrapi(a, N) * N + wrapi(b, N)) * N + wrapi(c, N)]
+    double v = PV(I, J, K);
+    double si = (wrapi(i, 2 * N) & 1) ? 1.0 : -1.0, sj = (wrapi(j, 2 * N) & 1) ? 1.0 : -1.0,
+           sk = (wrapi(k, 2 * N) & 1) ? 1.0 : -1.0;
+    v += si * (PV(I + 1, J, K) - PV(I - 1, J, K)) / 8.0;
+    v += sj * (PV(I, J + 1, K) - PV(I, J - 1, K)) / 8.0;
+    v += sk * (PV(I, J, K + 1) - PV(I, J, K - 1)) / 8.0;
+#undef PV
+    return v;
+}
+
+/* Solve the base mesh and `nref` (0..2) refined levels for np unit-mass particles.
+ * u[l], mask[l]: caller arrays of (N_0 2^l)^3 elements; u[l] holds the level-l
+ * solution on mask[l] cells (u[0] everywhere).  st[l]: per-level statistics.
+ * Returns the worst status. */
+int or_amr_solve(const or_params *p, int nref, int64_t np, const float *pos, double **u, unsigned char **mask,
+                 or_stats *st)
+{
+    int N0 = p->mesh;
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    double bC = beta * C, q = 1.0 / (p->n + 1);
+    double srcs = beta * p->omega_m / (p->a * p->a * p->a);
+    /* base level */
+    double *m0 = malloc(cube(N0) * sizeof(double)), *d0 = malloc(cube(N0) * sizeof(double));
+    or_cic_assign(N0, p->box, np, pos, NULL, m0);
+    or_delta(N0, m0, d0);
+    memset(u[0], 0, cube(N0) * sizeof(double));
+    int worst = or_solve(p, d0, u[0], NULL, &st[0]);
+    memset(mask[0], 1, cube(N0));
+    free(m0);
+    free(d0);
+    if (nref <= 0) return worst;
+    /* flags and blocks: blk[l][b] over (N_l/8)^3 blocks */
+    unsigned char *blk[OR_AMR_MAXL] = {0};
+    for (int l = 1; l <= nref; ++l) {
+        int nb = (N0 << l) / 8;
+        blk[l] = calloc(cube(nb), 1);
+    }
+    {   /* level 1 from base counts */
+        int *cnt = calloc(cube(N0), sizeof(int));
+        double h = p->box / N0;
+        for (int64_t i = 0; i < np; ++i) {
+            long c[3];
+            for (int d = 0; d < 3; ++d) c[d] = wrapi((long)floor((double)pos[3 * i + d] / h), N0);
+            cnt[((size_t)c[0] * N0 + c[1]) * N0 + c[2]]++;
+        }
+        int nb = N0 / 4;
+        for (int i = 0; i < N0; ++i)
+            for (int j = 0; j < N0; ++j)
+                for (int k = 0; k < N0; ++k)
+                    if (cnt[((size_t)i * N0 + j) * N0 + k] > 8) blk[1][((size_t)(i / 4) * nb + j / 4) * nb + k / 4] = 1;
+        free(cnt);
+    }
+    if (nref >= 2) {  /* level 2 from level-1 counts inside level-1 blocks */
+        int N1 = 2 * N0, nb1 = N1 / 8, nb2 = N1 / 4;
+        int *cnt = calloc(cube(N1), sizeof(int));
+        double h = p->box / N1;
+        for (int64_t i = 0; i < np; ++i) {
+            long c[3];
+            for (int d = 0; d < 3; ++d) c[d] = wrapi((long)floor((double)pos[3 * i + d] / h), N1);
+            if (blk[1][((size_t)(c[0] / 8) * nb1 + c[1] / 8) * nb1 + c[2] / 8]) cnt[((size_t)c[0] * N1 + c[1]) * N1 + c[2]]++;
+        }
+        for (int i = 0; i < N1; ++i)
+            for (int j = 0; j < N1; ++j)
+                for (int k = 0; k < N1; ++k)
+                    if (cnt[((size_t)i * N1 + j) * N1 + k] > 8) blk[2][((size_t)(i / 4) * nb2 + j / 4) * nb2 + k / 4] = 1;
+        free(cnt);
+        /* proper nesting: level-1 blocks within two level-1 cells of every level-2 block */
+        for (int bi = 0; bi < nb2; ++bi)
+            for (int bj = 0; bj < nb2; ++bj)
+                for (int bk = 0; bk < nb2; ++bk) {
+                    if (!blk[2][((size_t)bi * nb2 + bj) * nb2 + bk]) continue;
+                    for (long ci = 4L * bi - 2; ci < 4L * bi + 6; ++ci)
+                        for (long cj = 4L * bj - 2; cj < 4L * bj + 6; ++cj)
+                            for (long ck = 4L * bk - 2; ck < 4L * bk + 6; ++ck)
+                                blk[1][((size_t)(wrapi(ci, N1) / 8) * nb1 + wrapi(cj, N1) / 8) * nb1 + wrapi(ck, N1) / 8] = 1;
+                }
+    }
+    for (int l = 1; l <= nref; ++l) {
+        int N = N0 << l, nb = N / 8;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                for (int k = 0; k < N; ++k)
+                    mask[l][((size_t)i * N + j) * N + k] = blk[l][((size_t)(i / 8) * nb + j / 8) * nb + k / 8];
+    }
+    /* level solves, coarse to fine */
+    for (int l = 1; l <= nref; ++l) {
+        int N = N0 << l;
+        or_sub Sv[4];
+        int nsub = 4;
+        for (int m = 0; m < nsub; ++m) {
+            int Nm = N >> m;
+            or_sub *S = &Sv[m];
+            S->N = Nm;
+            S->h = p->box / Nm;
+            S->mask = calloc(cube(Nm), 1);
+            S->u = calloc(cube(Nm), sizeof(double));
+            S->f = calloc(cube(Nm), sizeof(double));
+            S->fr = calloc(cube(Nm), sizeof(double));
+            S->ubar = calloc(cube(Nm), sizeof(double));
+            S->r = calloc(cube(Nm), sizeof(double));
+            for (int i = 0; i < Nm; ++i)
+                for (int j = 0; j < Nm; ++j)
+                    for (int k = 0; k < Nm; ++k)
+                        S->mask[((size_t)i * Nm + j) * Nm + k] =
+                            mask[l][(((size_t)(i << m)) * N + (j << m)) * N + (k << m)];
+            /* frozen values: the solution at resolution level l - m */
+            int lp = l - m;
+            for (int i = 0; i < Nm; ++i)
+                for (int j = 0; j < Nm; ++j)
+                    for (int k = 0; k < Nm; ++k) {
+                        size_t c = ((size_t)i * Nm + j) * Nm + k;
+                        double v;
+                        if (m == 0) {
+                            v = prolong_field_at(u[l - 1], N / 2, i, j, k);
+                        } else if (lp >= 1) {
+                            v = u[lp][c];
+                        } else if (lp == 0) {
+                            v = u[0][c];
+                        } else {
+                            int f = 1 << (-lp);
+                            double s = 0.0;
+                            for (int a = 0; a < f; ++a)
+                                for (int b = 0; b < f; ++b)
+                                    for (int d = 0; d < f; ++d)
+                                        s += u[0][(((size_t)(i * f + a)) * N0 + (j * f + b)) * N0 + (k * f + d)];
+                            v = s / (f * f * f);
+                        }
+                        S->fr[c] = v;
+                    }
+        }
+        /* unknowns, source and initial guess on level l */
+        or_sub *S0 = &Sv[0];
+        double *ml = malloc(cube(N) * sizeof(double));
+        or_cic_assign(N, p->box, np, pos, NULL, ml);
+        double mbar = (double)np / (double)cube(N);
+        double D = 0.0;
+        for (size_t c = 0; c < cube(N); ++c) {
+            if (!S0->mask[c]) continue;
+            S0->f[c] = srcs * (ml[c] / mbar - 1.0);
+            S0->u[c] = S0->fr[c];
+            if (fabs(S0->f[c]) > D) D = fabs(S0->f[c]);
+        }
+        free(ml);
+        if (D == 0.0) D = bC;
+        or_stats *s = &st[l];
+        memset(s, 0, sizeof *s);
+        s->scale = D;
+        double res = sub_resmax(S0, bC, q) / D;
+        s->res0 = res;
+        int cyc = 0, status;
+        for (;;) {
+            if (!isfinite(res)) { status = -3; break; }
+            if (res <= p->tol) { status = 0; break; }
+            if (cyc >= p->max_vcycles) { status = 1; break; }
+            amr_vcycle(Sv, 0, nsub, p, bC, q);
+            res = sub_resmax(S0, bC, q) / D;
+            if (cyc < OR_MAX_HIST) s->res_hist[cyc] = res;
+            ++cyc;
+        }
+        s->vcycles = cyc;
+        s->res = res;
+        s->status = status;
+        if (status != 0 && (worst == 0 || status < 0)) worst = status;
+        for (size_t c = 0; c < cube(N); ++c) u[l][c] = S0->mask[c] ? S0->u[c] : 0.0;
+        for (int m = 0; m < nsub; ++m) {
+            free(Sv[m].mask); free(Sv[m].u); free(Sv[m].f); free(Sv[m].fr); free(Sv[m].ubar); free(Sv[m].r);
+        }
+    }
+    for (int l = 1; l <= nref; ++l) free(blk[l]);
+    return worst;
+}

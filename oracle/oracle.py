@@ -69,6 +69,13 @@ def lib():
         L.or_solve.restype = C.c_int
         L.or_vcycle_once.argtypes = [C.POINTER(Params), dp, dp]
         L.or_fifth_force.argtypes = [C.POINTER(Params), dp, C.c_int64, fp, dp]
+        ip = C.POINTER(C.c_int64)
+        L.or_residual_at.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp, C.c_int64, ip, dp]
+        L.or_cic_cells.argtypes = [C.c_int, C.c_double, C.c_int64, fp, dp, C.c_int64, ip, C.c_void_p, dp]
+        L.or_fifth_force_at.argtypes = [C.POINTER(Params), dp, C.c_int64, fp, dp]
+        L.or_amr_solve.argtypes = [C.POINTER(Params), C.c_int, C.c_int64, fp, C.POINTER(dp),
+                                   C.POINTER(C.c_void_p), C.POINTER(Stats)]
+        L.or_amr_solve.restype = C.c_int
         _lib = L
     return _lib
 
@@ -188,3 +195,50 @@ def fifth_force(p, u, pos):
     acc = np.empty((pos.shape[0], 3), np.float64)
     lib().or_fifth_force(C.byref(p), _d(u), pos.shape[0], _f(pos), _d(acc))
     return acc
+
+
+def _i64(a):
+    assert a.dtype == np.int64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def residual_at(u, f, h, bC, cells, n=1):
+    """f - L(u) at the flat cell indices ``cells`` (arrays may be any C-contiguous N^3 float64)."""
+    u = np.ascontiguousarray(u, np.float64)
+    f = np.ascontiguousarray(f, np.float64)
+    cells = np.ascontiguousarray(cells, np.int64)
+    out = np.empty(cells.size, np.float64)
+    lib().or_residual_at(u.shape[0], h, bC, n, _d(u), _d(f), cells.size, _i64(cells), _d(out))
+    return out
+
+
+def cic_cells(N, box, pos, cells, mass=None):
+    pos = np.ascontiguousarray(pos, np.float32)
+    cells = np.ascontiguousarray(cells, np.int64)
+    mark = np.empty(N ** 3, np.uint8)
+    out = np.empty(cells.size, np.float64)
+    mp = None if mass is None else _d(np.ascontiguousarray(mass, np.float64))
+    lib().or_cic_cells(N, box, pos.shape[0], _f(pos), mp, cells.size, _i64(cells),
+                       mark.ctypes.data_as(C.c_void_p), _d(out))
+    return out
+
+
+def fifth_force_at(p, u, pos):
+    pos = np.ascontiguousarray(pos, np.float32)
+    u = np.ascontiguousarray(u, np.float64)
+    acc = np.empty((pos.shape[0], 3), np.float64)
+    lib().or_fifth_force_at(C.byref(p), _d(u), pos.shape[0], _f(pos), _d(acc))
+    return acc
+
+
+def amr_solve(p, nref, pos):
+    """Base solve plus ``nref`` refined levels; returns (status, [u_l], [mask_l], [stats_l])."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    N0 = p.mesh
+    us = [np.zeros((N0 << l,) * 3, np.float64) for l in range(nref + 1)]
+    ms = [np.zeros((N0 << l,) * 3, np.uint8) for l in range(nref + 1)]
+    up = (C.POINTER(C.c_double) * (nref + 1))(*[_d(a) for a in us])
+    mp = (C.c_void_p * (nref + 1))(*[a.ctypes.data_as(C.c_void_p) for a in ms])
+    st = (Stats * (nref + 1))()
+    s = lib().or_amr_solve(C.byref(p), nref, pos.shape[0], _f(pos), up, mp, st)
+    return s, us, ms, list(st)

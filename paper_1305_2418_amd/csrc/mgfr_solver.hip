@@ -639,8 +639,8 @@ static int validate(const mgfr_params *p)
     if (!(p->omega_l >= 0)) return set_error(MGFR_ERR_ARG, "omega_l must be >= 0");
     if (!(p->fr0_abs > 0) || !std::isfinite(p->fr0_abs)) return set_error(MGFR_ERR_ARG, "fr0_abs must be > 0");
     if (p->n < 1) return set_error(MGFR_ERR_ARG, "n must be >= 1");
-    if (p->mesh < 8 || p->mesh > 2048 || (p->mesh & (p->mesh - 1)))
-        return set_error(MGFR_ERR_ARG, "mesh must be a power of two in [8, 2048], got %d", p->mesh);
+    if (p->mesh < 8 || p->mesh > 1024 || (p->mesh & (p->mesh - 1)))
+        return set_error(MGFR_ERR_ARG, "mesh must be a power of two in [8, 1024], got %d", p->mesh);
     if (p->refine_levels != 0) return set_error(MGFR_ERR_ARG, "refine_levels must be 0 for a uniform mesh");
     if (!(p->tol > 0)) return set_error(MGFR_ERR_ARG, "tol must be > 0");
     if (p->pre_smooth < 0 || p->post_smooth < 0) return set_error(MGFR_ERR_ARG, "smoothing counts must be >= 0");

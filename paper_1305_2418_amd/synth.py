@@ -118,7 +118,7 @@ def nfw_radii(m: int, r200: float, conc: float, g: torch.Generator) -> torch.Ten
 def add_halos(pos: torch.Tensor, box: float, n_halos: int, m_lo: float, m_hi: float,
               omega_m: float, seed: int, profile: str = "plummer",
               conc=(5.0, 10.0)) -> torch.Tensor:
-    """Relocate random lattice particles into ``n_halos`` halos (in place on a CPU copy).
+    """Relocate random lattice particles into ``n_halos`` halos (on a copy, on pos's device).
 
     Halo masses are log-uniform in [m_lo, m_hi] (M_sun/h); the particle mass is
     Omega_m rho_crit L^3 / N_p; r200 = (3 M / (4 pi 200 rho_crit))^(1/3).
@@ -135,7 +135,7 @@ def add_halos(pos: torch.Tensor, box: float, n_halos: int, m_lo: float, m_hi: fl
     order = torch.randperm(npart, generator=g)
     centres = torch.rand((n_halos, 3), generator=g, dtype=torch.float64) * box
     cs = torch.empty(n_halos, dtype=torch.float64).uniform_(conc[0], conc[1], generator=g)
-    out = pos.detach().to("cpu", torch.float64).clone()
+    out = pos.detach().to(torch.float64).clone()
     start = 0
     for h in range(n_halos):
         c = counts[h]
@@ -148,7 +148,8 @@ def add_halos(pos: torch.Tensor, box: float, n_halos: int, m_lo: float, m_hi: fl
             r = nfw_radii(c, r200, cs[h].item(), g)
         else:
             raise ValueError(profile)
-        out[idx] = centres[h] + r.unsqueeze(1) * _directions(c, g)
+        # drawn on the CPU generator, placed on the positions' device
+        out[idx.to(out.device)] = (centres[h] + r.unsqueeze(1) * _directions(c, g)).to(out.device)
     return torch.remainder(out, box)
 
 
@@ -168,7 +169,7 @@ def clustered_load(n: int, box: float = 100.0, rms: float = 1.0, seed: int = 1,
     pos = zeldovich(n, box, rms, seed, device=device)
     if n_halos:
         pos = add_halos(pos, box, n_halos, m_lo, m_hi, omega_m, seed, profile)
-    return to_f32(pos, box)
+    return to_f32(pos, box).cpu() if str(device) == "cpu" else to_f32(pos, box)
 
 
 # -- simple density fields (delta on an N^3 mesh, C order, float64 numpy) -------------
@@ -200,3 +201,25 @@ def cosine_delta(N: int, eps: float, mode=(1, 0, 0)) -> np.ndarray:
     ph = (2 * np.pi * mode[0] * idx[:, None, None] + 2 * np.pi * mode[1] * idx[None, :, None]
           + 2 * np.pi * mode[2] * idx[None, None, :])
     return eps * np.cos(ph)
+
+
+def spheres_delta(N: int, box: float, n_spheres: int, seed: int, width=(1.0, 4.0), peak=(1e2, 1e4),
+                  device="cpu") -> torch.Tensor:
+    """Sum of periodic Gaussian overdensities peak * exp(-r^2/w^2) at seeded random centres,
+    mean removed, float64 [N, N, N] on ``device`` (for meshes too large for particle loads)."""
+    g = _gen(seed)
+    cen = torch.rand((n_spheres, 3), generator=g, dtype=torch.float64) * box
+    w = torch.empty(n_spheres, dtype=torch.float64).uniform_(width[0], width[1], generator=g)
+    pk = torch.exp(torch.empty(n_spheres, dtype=torch.float64).uniform_(math.log(peak[0]), math.log(peak[1]),
+                                                                          generator=g))
+    x = (torch.arange(N, dtype=torch.float64, device=device) + 0.5) * (box / N)
+    d = torch.zeros((N, N, N), dtype=torch.float64, device=device)
+    for s in range(n_spheres):
+        comp = []
+        for ax in range(3):
+            dx = torch.abs(x - cen[s, ax].item())
+            dx = torch.minimum(dx, box - dx)
+            comp.append(torch.exp(-(dx * dx) / (w[s].item() ** 2)))
+        d += pk[s].item() * comp[0].view(N, 1, 1) * comp[1].view(1, N, 1) * comp[2].view(1, 1, N)
+    d -= d.mean()
+    return d

@@ -485,3 +485,23 @@ def test_assignment_gather_adjointness():
         # weight of particle p on cell c, from single-particle assignments
         wp = np.array([O.cic_assign(N, box, pos[i:i + 1])[c] for i in range(50)])
         assert (m * G).sum() == pytest.approx((w * wp).sum(), rel=1e-13)
+
+
+def test_sampled_oracle_routines_agree_with_full_ones():
+    """The sampled residual, CIC and force routines (used at full size) reproduce the
+    whole-mesh routines at the sampled cells / particles."""
+    N, box = 16, 100.0
+    pos = synth.clustered_load(16, box, rms=3.0, seed=9, n_halos=3).numpy()
+    mass = np.random.default_rng(11).uniform(0.5, 2.0, pos.shape[0])
+    m = O.cic_assign(N, box, pos, mass)
+    cells = np.array([0, 17, 300, 4095, 2222], np.int64)
+    assert np.allclose(O.cic_cells(N, box, pos, cells, mass), m.reshape(-1)[cells], rtol=1e-13)
+    p = O.params(mesh=N, fr0_abs=1e-6)
+    fb, beta, C, bC = bc_of(p)
+    d = O.density_contrast(m)
+    s, u, _, _ = O.solve(O.params(mesh=N, fr0_abs=1e-6, max_vcycles=2, tol=1e-30), d)
+    f = beta * 0.3 * d
+    r_full = f - O.apply_L(u, box / N, bC)
+    assert np.allclose(O.residual_at(u, f, box / N, bC, cells), r_full.reshape(-1)[cells], rtol=1e-13, atol=1e-15)
+    sub = pos[::97]
+    assert np.allclose(O.fifth_force_at(p, u, sub), O.fifth_force(p, u, sub), rtol=1e-12)

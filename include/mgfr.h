@@ -221,6 +221,37 @@ int mgfr_conv3d_bwd_data(const void *dz, int B, int S, int Cout, const void *w, 
 int mgfr_conv3d_bwd_weight(const void *x, const void *dz, int B, int S, int Cin, int Cout, float *dw,
                            float *db, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Adaptive refinement (Sec. 3.3 steps 9-12, one-way interface) on a
+ * block-structured mesh.  The base mesh N0 = p->mesh is solved by the
+ * uniform solver (p->precision applies there); refinement levels
+ * l = 1..p->refine_levels (1 or 2) have N0 2^l cells per side and consist of
+ * 8^3-cell blocks: a cell of level l-1 holding more than 8 particles
+ * (nearest-grid-point count, unit masses) refines the aligned 4^3 group of
+ * cells around it.  Level-2 blocks also refine the level-1 blocks within two
+ * level-1 cells of them.  Each level starts from, and keeps as fixed ghost
+ * values around its blocks, the linear prolongation of its parent's
+ * solution, and is solved by float64 FAS V-cycles over its blocks at
+ * 1/1, 1/2, 1/4 and 1/8 resolution (coarse cells outside the blocks hold the
+ * solution at that resolution).  The object owns all level storage, sized at
+ * creation for at most max_blocks blocks per level.
+ * --------------------------------------------------------------------- */
+typedef struct mgfr_amr mgfr_amr;
+
+/* p->refine_levels in {1, 2}; 32 <= p->mesh <= 512; 1 <= max_blocks <= 2^22. */
+int mgfr_amr_create(const mgfr_params *p, int64_t max_blocks, void *stream, mgfr_amr **out);
+void mgfr_amr_destroy(mgfr_amr *amr);
+/* pos: float32 [np][3] (unit masses); u0: float64 [N0^3] output (base solution) or
+ * NULL; st: HOST array of refine_levels + 1 stats (level 0 = base) or NULL.
+ * Returns the worst level status (MGFR_NOT_CONVERGED if a level hit
+ * max_vcycles); MGFR_ERR_ARG if a level needs more than max_blocks blocks. */
+int mgfr_amr_solve(mgfr_amr *amr, const float *pos, int64_t np, double *u0, mgfr_stats *st);
+/* Blocks of level l (1..refine_levels) after the last solve, -1 on error. */
+int64_t mgfr_amr_num_blocks(const mgfr_amr *amr, int level);
+/* origins: HOST int32 [nblocks][3] block origins in level cells (multiples of 8);
+ * u: device float64 [nblocks][8][8][8] level solution (either may be NULL). */
+int mgfr_amr_get_level(mgfr_amr *amr, int level, int32_t *origins, double *u);
+
 /* Last error message of this host thread ("" if none). */
 const char *mgfr_last_error(void);
 

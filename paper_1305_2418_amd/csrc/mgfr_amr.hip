@@ -1,0 +1,782 @@
+// Block-structured refined levels with the one-way interface of Sec. 3.3
+// (steps 9-12).  The base mesh (N0^3) is solved by the uniform solver; level
+// l = 1, 2 has N_l = N0 2^l cells per side and consists of 8^3-cell blocks:
+// a cell of level l-1 holding more than 8 particles (nearest-grid-point
+// count) refines the aligned 4^3 group of level-(l-1) cells around it into
+// one level-l block.  Level-2 blocks also refine every level-1 block within
+// two level-1 cells of them (proper nesting: the ghost cells of level 2 and
+// the parents they are prolonged from lie on level 1).
+//
+// A level is solved after its parent.  Its initial guess and the ghost layer
+// around the union of its blocks are the linear prolongation (Sec. 3.3) of the
+// parent solution; ghosts stay fixed.  The level's FAS V-cycles use the union
+// of blocks at 1/2, 1/4 and 1/8 resolution as coarse grids (block-aligned, so
+// every coarse cell is fully covered and the paper's mask is 1 on all of
+// them); coarse cells outside the union hold the solution of the level at
+// that resolution (restricted from the base below the base resolution) and
+// are never updated, and the correction is zero there.
+//
+// Storage: each block keeps, per sublevel m (side b = 8 >> m), a padded
+// (b+2)^3 array; ghost faces towards a neighbouring block are refreshed by a
+// halo exchange after every update, the others hold the frozen values.
+#include "mgfr_internal.h"
+#include "mgfr_ops.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+namespace mgfr {
+namespace {
+
+constexpr int kSub = 4;  // sublevels 8^3, 4^3, 2^3, 1^3 per block
+constexpr int kMaxRef = 2;
+
+__host__ __device__ inline int sub_b(int m) { return 8 >> m; }
+__host__ __device__ inline int sub_p(int m) { return (8 >> m) + 2; }
+__host__ __device__ inline int sub_vol(int m) { return sub_p(m) * sub_p(m) * sub_p(m); }
+
+struct LevelDev {
+    int lg;                  // N_l = 2^lg
+    int nb;                  // blocks
+    int mlg;                 // block-map side 2^mlg (= N_l / 8)
+    const int *map;          // block id or -1 for every 8^3 block position
+    const int *org;          // [nb][3] block origin in level cells
+    const int *nbr;          // [nb][6] face neighbours (-x,+x,-y,+y,-z,+z) or -1
+    double *u[kSub], *f[kSub], *ub[kSub], *E[kSub];
+};
+
+struct Composite {  // solutions available for frozen / ghost values
+    const double *u0;
+    int lg0;
+    LevelDev lev[kMaxRef + 1];  // lev[1], lev[2] valid when solved
+    int nsolved;                // levels 1..nsolved hold solutions
+};
+
+__device__ __forceinline__ int wrapn(int i, int n) { return i & (n - 1); }
+
+__device__ __forceinline__ size_t pidx(int m, int x, int y, int z)
+{
+    const int p = sub_p(m);
+    return ((size_t)(x + 1) * p + (y + 1)) * p + (z + 1);
+}
+
+// solution of level lr at one of its cells (lr <= nsolved; lr < 0: base means)
+__device__ double comp_at(const Composite &C, int lr, int i, int j, int k)
+{
+    if (lr >= 1) {
+        const LevelDev &L = C.lev[lr];
+        const int N = 1 << L.lg;
+        i = wrapn(i, N);
+        j = wrapn(j, N);
+        k = wrapn(k, N);
+        const int M = 1 << L.mlg;
+        const int b = L.map[((size_t)(i >> 3) * M + (j >> 3)) * M + (k >> 3)];
+        if (b >= 0) return L.u[0][(size_t)b * sub_vol(0) + pidx(0, i & 7, j & 7, k & 7)];
+        // outside the level: excluded by proper nesting; make a violation loud
+        return __builtin_nan("");
+    }
+    const int N0 = 1 << C.lg0;
+    if (lr == 0) return C.u0[cidx(wrapn(i, N0), wrapn(j, N0), wrapn(k, N0), C.lg0)];
+    const int f = 1 << (-lr), Nr = N0 >> (-lr);
+    i = wrapn(i, Nr);
+    j = wrapn(j, Nr);
+    k = wrapn(k, Nr);
+    double s = 0.0;
+    for (int a = 0; a < f; ++a)
+        for (int b = 0; b < f; ++b)
+            for (int c = 0; c < f; ++c) s += C.u0[cidx(i * f + a, j * f + b, k * f + c, C.lg0)];
+    return s / (double)(f * f * f);
+}
+
+// linear prolongation of the level-(l-1) solution to cell (i,j,k) of level l
+__device__ double prolong_parent(const Composite &C, int l, int i, int j, int k)
+{
+    const int lp = l - 1;
+    const int I = i >> 1, J = j >> 1, K = k >> 1;  // arithmetic shift: floor for negatives
+    double v = comp_at(C, lp, I, J, K);
+    v += ((i & 1) ? 0.125 : -0.125) * (comp_at(C, lp, I + 1, J, K) - comp_at(C, lp, I - 1, J, K));
+    v += ((j & 1) ? 0.125 : -0.125) * (comp_at(C, lp, I, J + 1, K) - comp_at(C, lp, I, J - 1, K));
+    v += ((k & 1) ? 0.125 : -0.125) * (comp_at(C, lp, I, J, K + 1) - comp_at(C, lp, I, J, K - 1));
+    return v;
+}
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_ngp_count(const float *__restrict__ pos, int64_t np, int lg, double h, int *__restrict__ cnt)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int N = 1 << lg;
+    int c[3];
+    for (int d = 0; d < 3; ++d) {
+        const double x = (double)pos[3 * p + d] / h;
+        if (!(fabs(x) < 4.0e18)) return;
+        c[d] = (int)((long long)floor(x) & (N - 1));
+    }
+    atomicAdd(&cnt[cidx(c[0], c[1], c[2], lg)], 1);
+}
+
+// nearest-grid-point counts at level-l resolution, into the level's blocks
+__global__ void k_ngp_count_blocks(const float *__restrict__ pos, int64_t np, LevelDev L, double h,
+                                   int *__restrict__ cnt)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int N = 1 << L.lg, M = 1 << L.mlg;
+    int c[3];
+    for (int d = 0; d < 3; ++d) {
+        const double x = (double)pos[3 * p + d] / h;
+        if (!(fabs(x) < 4.0e18)) return;
+        c[d] = (int)((long long)floor(x) & (N - 1));
+    }
+    const int b = L.map[((size_t)(c[0] >> 3) * M + (c[1] >> 3)) * M + (c[2] >> 3)];
+    if (b >= 0) atomicAdd(&cnt[(size_t)b * 512 + ((c[0] & 7) * 8 + (c[1] & 7)) * 8 + (c[2] & 7)], 1);
+}
+
+// cloud-in-cell masses of all particles onto the level's block cells (f[0] interior)
+__global__ void k_amr_cic(const float *__restrict__ pos, int64_t np, LevelDev L, double h)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int N = 1 << L.lg, M = 1 << L.mlg;
+    int i0[3];
+    double t[3];
+    for (int d = 0; d < 3; ++d) {
+        const double xi = (double)pos[3 * p + d] / h - 0.5;
+        if (!(fabs(xi) < 4.0e18)) return;
+        const double fl = floor(xi);
+        t[d] = xi - fl;
+        i0[d] = (int)((long long)fl & (N - 1));
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                const int i = wrapn(i0[0] + a, N), j = wrapn(i0[1] + b, N), k = wrapn(i0[2] + c, N);
+                const int blk = L.map[((size_t)(i >> 3) * M + (j >> 3)) * M + (k >> 3)];
+                if (blk < 0) continue;
+                const double w = (a ? t[0] : 1.0 - t[0]) * (b ? t[1] : 1.0 - t[1]) * (c ? t[2] : 1.0 - t[2]);
+                unsafeAtomicAdd(&L.f[0][(size_t)blk * sub_vol(0) + pidx(0, i & 7, j & 7, k & 7)], w);
+            }
+}
+
+// f = s (m / mbar - 1) on interior cells, per-block max |f| partials
+__global__ __launch_bounds__(512) void k_amr_source(LevelDev L, double s, double mbar, double *__restrict__ partial)
+{
+    __shared__ double sh[8];
+    const int blk = blockIdx.x, t = threadIdx.x;
+    const int x = t >> 6, y = (t >> 3) & 7, z = t & 7;
+    double *f = L.f[0] + (size_t)blk * sub_vol(0);
+    const size_t q = pidx(0, x, y, z);
+    const double v = s * (f[q] / mbar - 1.0);
+    f[q] = v;
+    double mx = fabs(v);
+    for (int o = 32; o > 0; o >>= 1) {
+        const double other = __shfl_xor(mx, o, 64);
+        mx = (other != other || other > mx) ? other : mx;
+    }
+    if ((t & 63) == 0) sh[t >> 6] = mx;
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < 8; ++w) mx = (sh[w] != sh[w] || sh[w] > mx) ? sh[w] : mx;
+        partial[blk] = mx;
+    }
+}
+
+// frozen values on ghost faces without a neighbour (u[m]), zero corrections there (E[m]);
+// for m == 0 also the initial guess on interior cells
+__global__ void k_amr_frozen(LevelDev L, Composite C, int l, int m)
+{
+    const int b = sub_b(m), p = sub_p(m);
+    const int vol = p * p * p;
+    const size_t n = (size_t)L.nb * vol;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / vol), q = (int)(id % vol);
+        const int x = q / (p * p) - 1, y = (q / p) % p - 1, z = q % p - 1;
+        const int outside = (x < 0 || x >= b) + (y < 0 || y >= b) + (z < 0 || z >= b);
+        const int gx = (L.org[3 * blk + 0] >> m) + x, gy = (L.org[3 * blk + 1] >> m) + y,
+                  gz = (L.org[3 * blk + 2] >> m) + z;
+        if (outside == 0) {
+            if (m == 0) L.u[0][id] = prolong_parent(C, l, gx, gy, gz);
+            continue;
+        }
+        if (outside != 1) continue;  // edges and corners are never read by the 7-point stencil
+        const int face = x < 0 ? 0 : x >= b ? 1 : y < 0 ? 2 : y >= b ? 3 : z < 0 ? 4 : 5;
+        if (L.nbr[6 * blk + face] >= 0) continue;
+        L.u[m][id] = (m == 0) ? prolong_parent(C, l, gx, gy, gz) : comp_at(C, l - m, gx, gy, gz);
+        L.E[m][id] = 0.0;
+    }
+}
+
+// copy neighbours' boundary layers into the ghost faces of X (sublevel m)
+__global__ void k_amr_exchange(LevelDev L, double *__restrict__ X, int m)
+{
+    const int b = sub_b(m);
+    const size_t per = (size_t)6 * b * b;
+    const size_t n = (size_t)L.nb * per;
+    const size_t vol = sub_vol(m);
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / per);
+        const int r = (int)(id % per);
+        const int face = r / (b * b), s = (r / b) % b, t = r % b;
+        const int nb = L.nbr[6 * blk + face];
+        if (nb < 0) continue;
+        int dst[3], src[3];
+        const int ax = face >> 1, hi = face & 1;
+        const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;  // the two in-face axes
+        dst[ax] = hi ? b : -1;
+        src[ax] = hi ? 0 : b - 1;
+        dst[o1] = src[o1] = s;
+        dst[o2] = src[o2] = t;
+        X[(size_t)blk * vol + pidx(m, dst[0], dst[1], dst[2])] = X[(size_t)nb * vol + pidx(m, src[0], src[1], src[2])];
+    }
+}
+
+__device__ __forceinline__ void amr_op(const double *__restrict__ U, int m, int x, int y, int z, double ih2,
+                                       double bC, double q, double &L, double &J)
+{
+    const double uc = U[pidx(m, x, y, z)];
+    const double nb[6] = {U[pidx(m, x + 1, y, z)], U[pidx(m, x - 1, y, z)], U[pidx(m, x, y + 1, z)],
+                          U[pidx(m, x, y - 1, z)], U[pidx(m, x, y, z + 1)], U[pidx(m, x, y, z - 1)]};
+    const double ec = exp(uc);
+    double S1 = 0.0, S2 = 0.0, S3 = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const double d = nb[s] - uc, en = exp(nb[s]);
+        S1 += d;
+        S2 += en;
+        S3 += en * d;
+    }
+    const double em = expm1(-q * uc);
+    L = ih2 * 0.5 * (S3 + ec * S1) + bC * em;
+    J = ih2 * 0.5 * (ec * (S1 - 6.0) - S2) - bC * q * (1.0 + em);
+}
+
+__global__ void k_amr_sweep(LevelDev L, int m, int colour, double ih2, double bC, double q, double max_du)
+{
+    const int b = sub_b(m), vol = sub_vol(m);
+    const int cells = b * b * b;
+    const size_t n = (size_t)L.nb * cells;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / cells), c = (int)(id % cells);
+        const int x = c / (b * b), y = (c / b) % b, z = c % b;
+        const int gx = (L.org[3 * blk] >> m) + x, gy = (L.org[3 * blk + 1] >> m) + y, gz = (L.org[3 * blk + 2] >> m) + z;
+        if (((gx + gy + gz) & 1) != colour) continue;
+        double *U = L.u[m] + (size_t)blk * vol;
+        double Lv, J;
+        amr_op(U, m, x, y, z, ih2, bC, q, Lv, J);
+        double du = -(Lv - L.f[m][(size_t)blk * vol + pidx(m, x, y, z)]) / J;
+        if (max_du > 0.0) du = fmin(fmax(du, -max_du), max_du);
+        U[pidx(m, x, y, z)] += du;
+    }
+}
+
+// coarse interior cell: ubar = mean of children's u, f_c = mean of children's residuals,
+// u_c = ubar
+__global__ void k_amr_restrict(LevelDev L, int m, double ih2, double bC, double q)
+{
+    const int bc = sub_b(m + 1), volf = sub_vol(m), volc = sub_vol(m + 1);
+    const int cells = bc * bc * bc;
+    const size_t n = (size_t)L.nb * cells;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / cells), c = (int)(id % cells);
+        const int X = c / (bc * bc), Y = (c / bc) % bc, Z = c % bc;
+        const double *U = L.u[m] + (size_t)blk * volf;
+        const double *F = L.f[m] + (size_t)blk * volf;
+        double su = 0.0, sr = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b2 = 0; b2 < 2; ++b2)
+                for (int d = 0; d < 2; ++d) {
+                    const int x = 2 * X + a, y = 2 * Y + b2, z = 2 * Z + d;
+                    double Lv, J;
+                    amr_op(U, m, x, y, z, ih2, bC, q, Lv, J);
+                    su += U[pidx(m, x, y, z)];
+                    sr += F[pidx(m, x, y, z)] - Lv;
+                }
+        const size_t qc = (size_t)blk * volc + pidx(m + 1, X, Y, Z);
+        L.ub[m + 1][qc] = su / 8.0;
+        L.f[m + 1][qc] = sr / 8.0;
+        L.u[m + 1][qc] = su / 8.0;
+    }
+}
+
+// f += L(u) on interior cells of sublevel m (the FAS coarse source)
+__global__ void k_amr_coarse_rhs(LevelDev L, int m, double ih2, double bC, double q)
+{
+    const int b = sub_b(m), vol = sub_vol(m);
+    const int cells = b * b * b;
+    const size_t n = (size_t)L.nb * cells;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / cells), c = (int)(id % cells);
+        const int x = c / (b * b), y = (c / b) % b, z = c % b;
+        double Lv, J;
+        amr_op(L.u[m] + (size_t)blk * vol, m, x, y, z, ih2, bC, q, Lv, J);
+        L.f[m][(size_t)blk * vol + pidx(m, x, y, z)] += Lv;
+    }
+}
+
+__global__ void k_amr_make_e(LevelDev L, int m)
+{
+    const int b = sub_b(m), vol = sub_vol(m);
+    const int cells = b * b * b;
+    const size_t n = (size_t)L.nb * cells;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / cells), c = (int)(id % cells);
+        const size_t q = (size_t)blk * vol + pidx(m, c / (b * b), (c / b) % b, c % b);
+        L.E[m][q] = L.u[m][q] - L.ub[m][q];
+    }
+}
+
+// u[m] += P(E[m+1]) with the linear (mode 0) or injected (mode 1) reconstruction
+__global__ void k_amr_prolong(LevelDev L, int m, int mode)
+{
+    const int b = sub_b(m), vol = sub_vol(m), volc = sub_vol(m + 1);
+    const int cells = b * b * b;
+    const size_t n = (size_t)L.nb * cells;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / cells), c = (int)(id % cells);
+        const int x = c / (b * b), y = (c / b) % b, z = c % b;
+        const double *E = L.E[m + 1] + (size_t)blk * volc;
+        const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+        double v = E[pidx(m + 1, X, Y, Z)];
+        if (mode == 0) {
+            v += ((x & 1) ? 0.125 : -0.125) * (E[pidx(m + 1, X + 1, Y, Z)] - E[pidx(m + 1, X - 1, Y, Z)]);
+            v += ((y & 1) ? 0.125 : -0.125) * (E[pidx(m + 1, X, Y + 1, Z)] - E[pidx(m + 1, X, Y - 1, Z)]);
+            v += ((z & 1) ? 0.125 : -0.125) * (E[pidx(m + 1, X, Y, Z + 1)] - E[pidx(m + 1, X, Y, Z - 1)]);
+        }
+        L.u[m][(size_t)blk * vol + pidx(m, x, y, z)] += v;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_amr_resnorm(LevelDev L, double ih2, double bC, double q,
+                                                      double *__restrict__ partial)
+{
+    __shared__ double sh[8];
+    const int blk = blockIdx.x, t = threadIdx.x;
+    const int x = t >> 6, y = (t >> 3) & 7, z = t & 7;
+    double Lv, J;
+    amr_op(L.u[0] + (size_t)blk * sub_vol(0), 0, x, y, z, ih2, bC, q, Lv, J);
+    double mx = fabs(L.f[0][(size_t)blk * sub_vol(0) + pidx(0, x, y, z)] - Lv);
+    for (int o = 32; o > 0; o >>= 1) {
+        const double other = __shfl_xor(mx, o, 64);
+        mx = (other != other || other > mx) ? other : mx;
+    }
+    if ((t & 63) == 0) sh[t >> 6] = mx;
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < 8; ++w) mx = (sh[w] != sh[w] || sh[w] > mx) ? sh[w] : mx;
+        partial[blk] = mx;
+    }
+}
+
+__global__ void k_max_final(const double *__restrict__ partial, int n, double *__restrict__ out)
+{
+    __shared__ double sh[16];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = (partial[i] != partial[i] || partial[i] > mx) ? partial[i] : mx;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double other = __shfl_xor(mx, o, 64);
+        mx = (other != other || other > mx) ? other : mx;
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / 64); ++w) mx = (sh[w] != sh[w] || sh[w] > mx) ? sh[w] : mx;
+        out[0] = mx;
+    }
+}
+
+__global__ void k_amr_copy_out(LevelDev L, double *__restrict__ out)
+{
+    const size_t n = (size_t)L.nb * 512;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / 512), c = (int)(id % 512);
+        out[id] = L.u[0][(size_t)blk * sub_vol(0) + pidx(0, c >> 6, (c >> 3) & 7, c & 7)];
+    }
+}
+
+inline unsigned grid_of(size_t n, unsigned cap = 65535) { return (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, cap)); }
+
+}  // namespace
+}  // namespace mgfr
+
+using namespace mgfr;
+
+// ====================================================================== host
+
+struct mgfr_amr {
+    mgfr_params p{};
+    hipStream_t stream = nullptr;
+    int nref = 0, N0 = 0, lg0 = 0;
+    int64_t max_blocks = 0;
+    mgfr_ctx *base = nullptr;
+    double *delta0 = nullptr, *u0 = nullptr;
+    int *cnt0 = nullptr;      // [N0^3] counts
+    int *cntb = nullptr;      // [max_blocks * 512] counts
+    double *partial = nullptr, *dscal = nullptr, *hscal = nullptr;
+    // per refined level
+    int nb[kMaxRef + 1] = {0, 0, 0};
+    int *map[kMaxRef + 1] = {nullptr}, *org[kMaxRef + 1] = {nullptr}, *nbr[kMaxRef + 1] = {nullptr};
+    double *arr[kMaxRef + 1][4][kSub] = {};  // u, f, ub, E per sublevel
+    std::vector<int> horg[kMaxRef + 1];
+    mgfr_stats st[kMaxRef + 1];
+    double beta = 0, C = 0, fbar = 0;
+};
+
+namespace {
+
+LevelDev level_dev(const mgfr_amr *A, int l)
+{
+    LevelDev L{};
+    L.lg = A->lg0 + l;
+    L.nb = A->nb[l];
+    L.mlg = L.lg - 3;
+    L.map = A->map[l];
+    L.org = A->org[l];
+    L.nbr = A->nbr[l];
+    for (int m = 0; m < kSub; ++m) {
+        L.u[m] = A->arr[l][0][m];
+        L.f[m] = A->arr[l][1][m];
+        L.ub[m] = A->arr[l][2][m];
+        L.E[m] = A->arr[l][3][m];
+    }
+    return L;
+}
+
+Composite composite(const mgfr_amr *A, int nsolved)
+{
+    Composite C{};
+    C.u0 = A->u0;
+    C.lg0 = A->lg0;
+    for (int l = 1; l <= A->nref; ++l) C.lev[l] = level_dev(A, l);
+    C.nsolved = nsolved;
+    return C;
+}
+
+void amr_free(mgfr_amr *A)
+{
+    if (!A) return;
+    if (A->base) mgfr_destroy(A->base);
+    (void)hipFree(A->delta0);
+    (void)hipFree(A->u0);
+    (void)hipFree(A->cnt0);
+    (void)hipFree(A->cntb);
+    (void)hipFree(A->partial);
+    (void)hipFree(A->dscal);
+    if (A->hscal) (void)hipHostFree(A->hscal);
+    for (int l = 1; l <= kMaxRef; ++l) {
+        (void)hipFree(A->map[l]);
+        (void)hipFree(A->org[l]);
+        (void)hipFree(A->nbr[l]);
+        for (int a = 0; a < 4; ++a)
+            for (int m = 0; m < kSub; ++m) (void)hipFree(A->arr[l][a][m]);
+    }
+    delete A;
+}
+
+// Upload block list `blocks` (sorted linear block indices) of level l: origins,
+// block map and face neighbours.
+int upload_level(mgfr_amr *A, int l, const std::vector<int64_t> &blocks)
+{
+    const int N = A->N0 << l, M = N / 8;
+    if ((int64_t)blocks.size() > A->max_blocks)
+        return set_error(MGFR_ERR_ARG, "level %d needs %zu blocks, more than max_blocks = %lld", l, blocks.size(),
+                         (long long)A->max_blocks);
+    std::vector<int> map((size_t)M * M * M, -1), org(3 * blocks.size()), nbr(6 * blocks.size());
+    for (size_t b = 0; b < blocks.size(); ++b) map[blocks[b]] = (int)b;
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        const int64_t li = blocks[b];
+        const int bx = (int)(li / ((int64_t)M * M)), by = (int)((li / M) % M), bz = (int)(li % M);
+        org[3 * b] = 8 * bx;
+        org[3 * b + 1] = 8 * by;
+        org[3 * b + 2] = 8 * bz;
+        const int d[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+        for (int f = 0; f < 6; ++f) {
+            const int x = (bx + d[f][0] + M) % M, y = (by + d[f][1] + M) % M, z = (bz + d[f][2] + M) % M;
+            nbr[6 * b + f] = map[((size_t)x * M + y) * M + z];
+        }
+    }
+    A->nb[l] = (int)blocks.size();
+    A->horg[l] = org;
+    MGFR_HIP(hipMemcpyAsync(A->map[l], map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice, A->stream));
+    if (!blocks.empty()) {
+        MGFR_HIP(hipMemcpyAsync(A->org[l], org.data(), org.size() * sizeof(int), hipMemcpyHostToDevice, A->stream));
+        MGFR_HIP(hipMemcpyAsync(A->nbr[l], nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice, A->stream));
+    }
+    MGFR_HIP(hipStreamSynchronize(A->stream));  // host vectors go out of scope
+    return MGFR_OK;
+}
+
+int read_max(mgfr_amr *A, int n, double *out)
+{
+    k_max_final<<<1, 1024, 0, A->stream>>>(A->partial, n, A->dscal);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipMemcpyAsync(A->hscal, A->dscal, sizeof(double), hipMemcpyDeviceToHost, A->stream));
+    MGFR_HIP(hipStreamSynchronize(A->stream));
+    *out = A->hscal[0];
+    return MGFR_OK;
+}
+
+struct SubConst {
+    double ih2[kSub];
+};
+
+int amr_sweeps(mgfr_amr *A, const LevelDev &L, int m, int sweeps, const SubConst &K)
+{
+    const int b = sub_b(m);
+    const size_t cells = (size_t)L.nb * b * b * b, faces = (size_t)L.nb * 6 * b * b;
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+            k_amr_sweep<<<grid_of(cells), 256, 0, A->stream>>>(L, m, colour, K.ih2[m], A->beta * A->C,
+                                                                1.0 / (A->p.n + 1), A->p.max_du);
+            k_amr_exchange<<<grid_of(faces), 256, 0, A->stream>>>(L, L.u[m], m);
+        }
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
+}
+
+int amr_vcycle(mgfr_amr *A, const LevelDev &L, int m, const SubConst &K)
+{
+    const double bC = A->beta * A->C, q = 1.0 / (A->p.n + 1);
+    if (m == kSub - 1) return amr_sweeps(A, L, m, A->p.coarse_sweeps, K);
+    int rc;
+    if ((rc = amr_sweeps(A, L, m, A->p.pre_smooth, K))) return rc;
+    const int bc = sub_b(m + 1);
+    const size_t cc = (size_t)L.nb * bc * bc * bc, fc = (size_t)L.nb * 6 * bc * bc;
+    const int b = sub_b(m);
+    const size_t cf = (size_t)L.nb * b * b * b, ff = (size_t)L.nb * 6 * b * b;
+    k_amr_restrict<<<grid_of(cc), 256, 0, A->stream>>>(L, m, K.ih2[m], bC, q);
+    k_amr_exchange<<<grid_of(fc), 256, 0, A->stream>>>(L, L.u[m + 1], m + 1);
+    k_amr_coarse_rhs<<<grid_of(cc), 256, 0, A->stream>>>(L, m + 1, K.ih2[m + 1], bC, q);
+    MGFR_HIP(hipGetLastError());
+    if ((rc = amr_vcycle(A, L, m + 1, K))) return rc;
+    k_amr_make_e<<<grid_of(cc), 256, 0, A->stream>>>(L, m + 1);
+    k_amr_exchange<<<grid_of(fc), 256, 0, A->stream>>>(L, L.E[m + 1], m + 1);
+    k_amr_prolong<<<grid_of(cf), 256, 0, A->stream>>>(L, m, A->p.prolong);
+    k_amr_exchange<<<grid_of(ff), 256, 0, A->stream>>>(L, L.u[m], m);
+    MGFR_HIP(hipGetLastError());
+    return amr_sweeps(A, L, m, A->p.post_smooth, K);
+}
+
+int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
+{
+    mgfr_stats &st = A->st[l];
+    memset(&st, 0, sizeof st);
+    LevelDev L = level_dev(A, l);
+    if (L.nb == 0) {
+        st.status = MGFR_OK;
+        return MGFR_OK;
+    }
+    const int N = 1 << L.lg;
+    const double h = A->p.box / N;
+    SubConst K;
+    for (int m = 0; m < kSub; ++m) {
+        const double hm = h * (1 << m);
+        K.ih2[m] = 1.0 / (hm * hm);
+    }
+    // clear every array (ghost faces included) of this level
+    for (int a = 0; a < 4; ++a)
+        for (int m = 0; m < kSub; ++m)
+            MGFR_HIP(hipMemsetAsync(A->arr[l][a][m], 0, (size_t)L.nb * sub_vol(m) * sizeof(double), A->stream));
+    // source
+    const unsigned pg = (unsigned)((np + 255) / 256);
+    k_amr_cic<<<pg, 256, 0, A->stream>>>(pos, np, L, h);
+    const double mbar = (double)np / ((double)N * N * N);
+    const double s = A->beta * A->p.omega_m / (A->p.a * A->p.a * A->p.a);
+    k_amr_source<<<L.nb, 512, 0, A->stream>>>(L, s, mbar, A->partial);
+    double D;
+    int rc;
+    if ((rc = read_max(A, L.nb, &D))) return rc;
+    if (!std::isfinite(D)) return set_error(MGFR_ERR_NONFINITE, "level %d source is not finite", l);
+    if (D == 0.0) D = A->beta * A->C;
+    st.scale = D;
+    // initial guess, frozen ghosts and zero-correction ghosts for every sublevel
+    const Composite Cp = composite(A, l - 1);
+    for (int m = 0; m < kSub; ++m)
+        k_amr_frozen<<<grid_of((size_t)L.nb * sub_vol(m)), 256, 0, A->stream>>>(L, Cp, l, m);
+    const size_t ff = (size_t)L.nb * 6 * 64;
+    k_amr_exchange<<<grid_of(ff), 256, 0, A->stream>>>(L, L.u[0], 0);
+    MGFR_HIP(hipGetLastError());
+    const double bC = A->beta * A->C, q = 1.0 / (A->p.n + 1);
+    k_amr_resnorm<<<L.nb, 512, 0, A->stream>>>(L, K.ih2[0], bC, q, A->partial);
+    double rmax;
+    if ((rc = read_max(A, L.nb, &rmax))) return rc;
+    double res = rmax / D;
+    st.res0 = res;
+    int cyc = 0, status;
+    for (;;) {
+        if (!std::isfinite(res)) { status = MGFR_ERR_NONFINITE; break; }
+        if (res <= A->p.tol) { status = MGFR_OK; break; }
+        if (cyc >= A->p.max_vcycles) { status = MGFR_NOT_CONVERGED; break; }
+        if ((rc = amr_vcycle(A, L, 0, K))) return rc;
+        k_amr_resnorm<<<L.nb, 512, 0, A->stream>>>(L, K.ih2[0], bC, q, A->partial);
+        if ((rc = read_max(A, L.nb, &rmax))) return rc;
+        res = rmax / D;
+        if (cyc < MGFR_MAX_HIST) st.res_hist[cyc] = res;
+        ++cyc;
+    }
+    st.vcycles = st.outer_iters = cyc;
+    st.res = res;
+    st.status = status;
+    return MGFR_OK;
+}
+
+}  // namespace
+
+extern "C" int mgfr_amr_create(const mgfr_params *p, int64_t max_blocks, void *stream, mgfr_amr **out)
+{
+    if (!out) return set_error(MGFR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p) return set_error(MGFR_ERR_ARG, "params is NULL");
+    if (p->refine_levels < 1 || p->refine_levels > kMaxRef)
+        return set_error(MGFR_ERR_ARG, "refine_levels must be 1 or 2 for the adaptive solver");
+    if (p->mesh < 32 || p->mesh > 512) return set_error(MGFR_ERR_ARG, "the base mesh must be 32..512");
+    if (max_blocks < 1 || max_blocks > (1 << 22)) return set_error(MGFR_ERR_ARG, "max_blocks must be in [1, 2^22]");
+    mgfr_params bp = *p;
+    bp.refine_levels = 0;
+    bp.nn_mode = MGFR_NN_NONE;
+    mgfr_amr *A = new (std::nothrow) mgfr_amr();
+    if (!A) return set_error(MGFR_ERR_OOM, "host allocation failed");
+    A->p = *p;
+    A->stream = (hipStream_t)stream;
+    A->nref = p->refine_levels;
+    A->N0 = p->mesh;
+    while ((1 << A->lg0) < A->N0) ++A->lg0;
+    A->max_blocks = max_blocks;
+    int rc = mgfr_create(&bp, stream, &A->base);
+    auto fail = [&](int code) {
+        amr_free(A);
+        return code;
+    };
+    if (rc) return fail(rc);
+    mgfr_background(&bp, &A->fbar, &A->beta, &A->C);
+    const size_t n0 = (size_t)A->N0 * A->N0 * A->N0;
+    hipError_t e = hipSuccess;
+    auto M = [&](void **ptr, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+    };
+    M((void **)&A->delta0, n0 * sizeof(double));
+    M((void **)&A->u0, n0 * sizeof(double));
+    M((void **)&A->cnt0, n0 * sizeof(int));
+    M((void **)&A->cntb, (size_t)max_blocks * 512 * sizeof(int));
+    M((void **)&A->partial, (size_t)std::max<int64_t>(max_blocks, 1024) * sizeof(double));
+    M((void **)&A->dscal, 8 * sizeof(double));
+    for (int l = 1; l <= A->nref; ++l) {
+        const size_t Mside = (size_t)(A->N0 << l) / 8;
+        M((void **)&A->map[l], Mside * Mside * Mside * sizeof(int));
+        M((void **)&A->org[l], (size_t)max_blocks * 3 * sizeof(int));
+        M((void **)&A->nbr[l], (size_t)max_blocks * 6 * sizeof(int));
+        for (int a = 0; a < 4; ++a)
+            for (int m = 0; m < kSub; ++m) M((void **)&A->arr[l][a][m], (size_t)max_blocks * sub_vol(m) * sizeof(double));
+    }
+    if (e == hipSuccess) e = hipHostMalloc(&A->hscal, 8 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(hip_fail(e, "adaptive-mesh allocation", __FILE__, __LINE__));
+    *out = A;
+    return MGFR_OK;
+}
+
+extern "C" void mgfr_amr_destroy(mgfr_amr *A) { amr_free(A); }
+
+extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double *u0_out, mgfr_stats *st_levels)
+{
+    if (!A || !pos) return set_error(MGFR_ERR_ARG, "amr and pos must be non-NULL");
+    if (np < 1) return set_error(MGFR_ERR_ARG, "np must be >= 1");
+    int rc;
+    const int N0 = A->N0;
+    const size_t n0 = (size_t)N0 * N0 * N0;
+    // base level: the uniform solver
+    if ((rc = mgfr_set_stream(A->base, A->stream))) return rc;
+    if ((rc = mgfr_assign_density(A->base, pos, nullptr, np, A->delta0))) return rc;
+    MGFR_HIP(hipMemsetAsync(A->u0, 0, n0 * sizeof(double), A->stream));
+    rc = mgfr_solve(A->base, A->delta0, A->u0, nullptr, &A->st[0]);
+    if (rc < 0) return rc;
+    const unsigned pg = (unsigned)((np + 255) / 256);
+    // level-1 blocks from base counts
+    MGFR_HIP(hipMemsetAsync(A->cnt0, 0, n0 * sizeof(int), A->stream));
+    k_ngp_count<<<pg, 256, 0, A->stream>>>(pos, np, A->lg0, A->p.box / N0, A->cnt0);
+    MGFR_HIP(hipGetLastError());
+    std::vector<int> hc(n0);
+    MGFR_HIP(hipMemcpyAsync(hc.data(), A->cnt0, n0 * sizeof(int), hipMemcpyDeviceToHost, A->stream));
+    MGFR_HIP(hipStreamSynchronize(A->stream));
+    const int M1 = N0 / 4;
+    std::vector<char> blk1((size_t)M1 * M1 * M1, 0);
+    for (int i = 0; i < N0; ++i)
+        for (int j = 0; j < N0; ++j)
+            for (int k = 0; k < N0; ++k)
+                if (hc[((size_t)i * N0 + j) * N0 + k] > 8) blk1[((size_t)(i / 4) * M1 + j / 4) * M1 + k / 4] = 1;
+    auto listof = [](const std::vector<char> &v) {
+        std::vector<int64_t> L;
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i]) L.push_back((int64_t)i);
+        return L;
+    };
+    if ((rc = upload_level(A, 1, listof(blk1)))) return rc;
+    if (A->nref >= 2) {
+        // level-2 blocks from level-1 counts inside level-1 blocks
+        const int N1 = 2 * N0, M2 = N1 / 4;
+        LevelDev L1 = level_dev(A, 1);
+        const size_t nc = (size_t)A->nb[1] * 512;
+        if (nc) {
+            MGFR_HIP(hipMemsetAsync(A->cntb, 0, nc * sizeof(int), A->stream));
+            k_ngp_count_blocks<<<pg, 256, 0, A->stream>>>(pos, np, L1, A->p.box / N1, A->cntb);
+            MGFR_HIP(hipGetLastError());
+        }
+        std::vector<int> hb(nc);
+        if (nc) MGFR_HIP(hipMemcpyAsync(hb.data(), A->cntb, nc * sizeof(int), hipMemcpyDeviceToHost, A->stream));
+        MGFR_HIP(hipStreamSynchronize(A->stream));
+        std::vector<char> blk2((size_t)M2 * M2 * M2, 0);
+        const std::vector<int> &o1 = A->horg[1];
+        for (int b = 0; b < A->nb[1]; ++b)
+            for (int c = 0; c < 512; ++c)
+                if (hb[(size_t)b * 512 + c] > 8) {
+                    const int i = o1[3 * b] + (c >> 6), j = o1[3 * b + 1] + ((c >> 3) & 7), k = o1[3 * b + 2] + (c & 7);
+                    blk2[((size_t)(i / 4) * M2 + j / 4) * M2 + k / 4] = 1;
+                }
+        // proper nesting: level-1 blocks within two level-1 cells of every level-2 block
+        for (int bi = 0; bi < M2; ++bi)
+            for (int bj = 0; bj < M2; ++bj)
+                for (int bk = 0; bk < M2; ++bk) {
+                    if (!blk2[((size_t)bi * M2 + bj) * M2 + bk]) continue;
+                    for (int ci = 4 * bi - 2; ci < 4 * bi + 6; ++ci)
+                        for (int cj = 4 * bj - 2; cj < 4 * bj + 6; ++cj)
+                            for (int ck = 4 * bk - 2; ck < 4 * bk + 6; ++ck) {
+                                const int x = ((ci % N1) + N1) % N1, y = ((cj % N1) + N1) % N1, z = ((ck % N1) + N1) % N1;
+                                blk1[((size_t)(x / 8) * M1 + y / 8) * M1 + z / 8] = 1;
+                            }
+                }
+        if ((rc = upload_level(A, 1, listof(blk1)))) return rc;
+        if ((rc = upload_level(A, 2, listof(blk2)))) return rc;
+    }
+    int worst = A->st[0].status;
+    for (int l = 1; l <= A->nref; ++l) {
+        if ((rc = solve_level(A, l, pos, np))) return rc;
+        const int s = A->st[l].status;
+        if (s != MGFR_OK && (worst == MGFR_OK || s < 0)) worst = s;
+    }
+    if (u0_out) MGFR_HIP(hipMemcpyAsync(u0_out, A->u0, n0 * sizeof(double), hipMemcpyDeviceToDevice, A->stream));
+    MGFR_HIP(hipStreamSynchronize(A->stream));
+    if (st_levels)
+        for (int l = 0; l <= A->nref; ++l) st_levels[l] = A->st[l];
+    return worst;
+}
+
+extern "C" int64_t mgfr_amr_num_blocks(const mgfr_amr *A, int level)
+{
+    if (!A || level < 1 || level > A->nref) return -1;
+    return A->nb[level];
+}
+
+extern "C" int mgfr_amr_get_level(mgfr_amr *A, int level, int32_t *origins_host, double *u)
+{
+    if (!A || level < 1 || level > A->nref) return set_error(MGFR_ERR_ARG, "invalid level");
+    const LevelDev L = level_dev(A, level);
+    if (origins_host && L.nb) memcpy(origins_host, A->horg[level].data(), 3 * sizeof(int) * (size_t)L.nb);
+    if (u && L.nb) {
+        k_amr_copy_out<<<grid_of((size_t)L.nb * 512), 256, 0, A->stream>>>(L, u);
+        MGFR_HIP(hipGetLastError());
+        MGFR_HIP(hipStreamSynchronize(A->stream));
+    }
+    return MGFR_OK;
+}

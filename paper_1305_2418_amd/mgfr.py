@@ -142,6 +142,13 @@ def lib() -> C.CDLL:
         L.mgfr_conv3d_fwd.argtypes = [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, C.c_int, C.c_int, _VP, _VP, _VP]
         L.mgfr_conv3d_bwd_data.argtypes = [_VP, C.c_int, C.c_int, C.c_int, _VP, C.c_int, _VP, _VP, _VP]
         L.mgfr_conv3d_bwd_weight.argtypes = [_VP, _VP, C.c_int, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]
+        L.mgfr_amr_create.argtypes = [C.POINTER(_Params), C.c_int64, _VP, C.POINTER(_VP)]
+        L.mgfr_amr_destroy.argtypes = [_VP]
+        L.mgfr_amr_destroy.restype = None
+        L.mgfr_amr_solve.argtypes = [_VP, _VP, C.c_int64, _VP, _VP]
+        L.mgfr_amr_num_blocks.argtypes = [_VP, C.c_int]
+        L.mgfr_amr_num_blocks.restype = C.c_int64
+        L.mgfr_amr_get_level.argtypes = [_VP, C.c_int, _VP, _VP]
         _lib = L
     return _lib
 
@@ -403,3 +410,52 @@ def conv3d_bwd_weight(x: torch.Tensor, dz: torch.Tensor):
     _check(lib().mgfr_conv3d_bwd_weight(x.data_ptr(), dz.data_ptr(), B, S, Cin, Cout, dw.data_ptr(),
                                         db.data_ptr(), _stream_ptr()))
     return dw, db
+
+
+class Amr:
+    """Base mesh plus block-refined levels (one-way interface)."""
+
+    def __init__(self, params: Params, max_blocks: int = 65536, stream=None):
+        if params.refine_levels < 1:
+            raise ValueError("refine_levels must be 1 or 2")
+        self.params = params
+        self._p = params.to_c()
+        h = _VP()
+        s = _stream_ptr() if stream is None else stream
+        _check(lib().mgfr_amr_create(C.byref(self._p), int(max_blocks), s, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgfr_amr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, pos: torch.Tensor, allow_not_converged=False):
+        """Returns (u0 [N0^3] tensor, [Stats per level])."""
+        N0 = self.params.mesh
+        npart = pos.shape[0]
+        _dev(pos, torch.float32, (npart, 3), "pos")
+        u0 = torch.empty((N0, N0, N0), dtype=torch.float64, device=pos.device)
+        nl = self.params.refine_levels + 1
+        sts = (_Stats * nl)()
+        rc = lib().mgfr_amr_solve(self._h, pos.data_ptr(), npart, u0.data_ptr(), sts)
+        _check(rc, allow_not_converged=allow_not_converged)
+        return u0, [Stats.from_c(sts[i]) for i in range(nl)]
+
+    def level(self, l: int):
+        """(origins int32 [nb, 3] numpy, u float64 [nb, 8, 8, 8] tensor) of refined level l."""
+        import numpy as np
+        nb = int(lib().mgfr_amr_num_blocks(self._h, l))
+        if nb < 0:
+            raise ValueError("invalid level")
+        org = np.zeros((nb, 3), dtype=np.int32)
+        u = torch.empty((nb, 8, 8, 8), dtype=torch.float64, device="cuda")
+        _check(lib().mgfr_amr_get_level(self._h, l, org.ctypes.data_as(C.c_void_p) if nb else None,
+                                        u.data_ptr() if nb else None))
+        return org, u

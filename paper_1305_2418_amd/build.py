@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmgfr.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["mgfr_solver.hip", "mgfr_particles.hip", "mgfr_mixed.hip", "mgfr_nn.hip", "mgfr_amr.hip"]
+SOURCES = ["mgfr_solver.hip", "mgfr_particles.hip", "mgfr_mixed.hip", "mgfr_nn.hip", "mgfr_amr.hip", "mgfr_bin.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

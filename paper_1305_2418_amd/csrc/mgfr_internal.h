@@ -68,6 +68,13 @@ struct mgfr_ctx {
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
     // learned warm start (owned by the network module)
     void *nn = nullptr;
+    // particle binning by 8^3 tiles of CIC lower-corner cells (mgfr_bin.hip)
+    int binning = 1;           // 0: assign by direct global atomics
+    int64_t bin_cap = 0;       // particles the binning workspace holds
+    int64_t perm_np = 0;       // particle count of the last binning (0: none)
+    uint32_t *bkey = nullptr, *bkey_s = nullptr, *bidx = nullptr, *perm = nullptr;
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
 };
 
 namespace mgfr {
@@ -102,6 +109,25 @@ int collect_timing(mgfr_ctx *c, mgfr_stats *st);
 // mixed precision (mgfr_mixed.hip)
 int mixed_alloc(mgfr_ctx *c);
 int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D);
+
+// particle binning (mgfr_bin.hip)
+constexpr int kBinLg = 3;  // tile edge 2^kBinLg cells
+int bin_reserve(mgfr_ctx *c, int64_t np);
+int bin_particles(mgfr_ctx *c, const float *pos, int64_t np);  // keys + sort; sets perm_np
+void bin_free(mgfr_ctx *c);
+
+// Cloud-in-cell weights along one axis: xi = x/h - 1/2, i0 = floor(xi), t = xi - i0,
+// weights (1 - t, t) on cells (i0, i0 + 1) mod N.  Returns false for positions
+// that are not finite or so large that floor(xi) does not fit an int64.
+__device__ __forceinline__ bool cic_axis(float x, double h, int mask, int &i0, double &t)
+{
+    double xi = (double)x / h - 0.5;
+    if (!(fabs(xi) < 4.0e18)) return false;
+    double fl = floor(xi);
+    t = xi - fl;
+    i0 = (int)((long long)fl & (long long)mask);
+    return true;
+}
 
 // learned warm start (mgfr_nn.hip)
 int nn_warm_start(mgfr_ctx *c, const double *delta, double *u, double *t_ms);

@@ -12,19 +12,6 @@ namespace {
 
 __device__ __forceinline__ double nanmax2(double a, double b) { return (a != a || a > b) ? a : b; }
 
-// Cloud-in-cell weights along one axis: xi = x/h - 1/2, i0 = floor(xi), t = xi - i0,
-// weights (1 - t, t) on cells (i0, i0 + 1) mod N.  Returns false for positions
-// that are not finite or so large that floor(xi) does not fit an int64.
-__device__ __forceinline__ bool cic_axis(float x, double h, int mask, int &i0, double &t)
-{
-    double xi = (double)x / h - 0.5;
-    if (!(fabs(xi) < 4.0e18)) return false;
-    double fl = floor(xi);
-    t = xi - fl;
-    i0 = (int)((long long)fl & (long long)mask);
-    return true;
-}
-
 __global__ __launch_bounds__(kBlock) void k_cic_scatter(const float *__restrict__ pos,
                                                           const double *__restrict__ mass, int64_t np, int lg,
                                                           double h, double *__restrict__ m, int *__restrict__ flag)
@@ -53,6 +40,105 @@ __global__ __launch_bounds__(kBlock) void k_cic_scatter(const float *__restrict_
                 size_t cell = ((((size_t)ii[a] << lg) + jj[b]) << lg) + kk[c];
                 unsafeAtomicAdd(&m[cell], wx[a] * wy[b] * wz[c] * mp);
             }
+}
+
+constexpr int kCicPer = 8;                        // particles per thread and workgroup chunk
+constexpr int kCicChunk = kBlock * kCicPer;
+constexpr int kWin = (1 << kBinLg) + 1;           // LDS window edge: a tile plus one cell
+constexpr int kWin3 = kWin * kWin * kWin;
+
+// Cloud-in-cell assignment of binned particles.  Workgroup b takes the
+// sorted slots [b kCicChunk, (b + 1) kCicChunk); its slots split into runs of
+// equal tile key.  Each run is accumulated in a 9^3 LDS window (lower corners
+// in the tile, upper corners one cell beyond) and the window's non-zero
+// entries are added to the mesh with float64 atomics.  The slots are loaded
+// once, before the runs are walked.
+__global__ __launch_bounds__(kBlock) void k_cic_binned(const float *__restrict__ pos,
+                                                         const double *__restrict__ mass,
+                                                         const uint32_t *__restrict__ key_s,
+                                                         const uint32_t *__restrict__ perm, int64_t np, int lg,
+                                                         double h, double *__restrict__ m, int *__restrict__ flag)
+{
+    __shared__ double win[kWin3];
+    __shared__ int red[kBlock / 64];
+    const int tid = threadIdx.x;
+    const int64_t start = (int64_t)blockIdx.x * kCicChunk;
+    const int64_t end = start + kCicChunk < np ? start + kCicChunk : np;
+    const int mask = (1 << lg) - 1, tl = lg - kBinLg, tmask = (1 << tl) - 1;
+    uint32_t key[kCicPer];
+    float px[kCicPer], py[kCicPer], pz[kCicPer];
+    double pm[kCicPer];
+#pragma unroll
+    for (int s = 0; s < kCicPer; ++s) {
+        const int64_t i = start + tid + (int64_t)s * kBlock;
+        key[s] = 0xffffffffu;  // above every tile key
+        px[s] = py[s] = pz[s] = 0.0f;
+        pm[s] = 0.0;
+        if (i < end) {
+            key[s] = key_s[i];
+            const size_t p = perm[i];
+            px[s] = pos[3 * p + 0];
+            py[s] = pos[3 * p + 1];
+            pz[s] = pos[3 * p + 2];
+            pm[s] = mass ? mass[p] : 1.0;
+        }
+    }
+    for (int e = tid; e < kWin3; e += kBlock) win[e] = 0.0;
+    int64_t cur = start;
+    while (cur < end) {
+        const uint32_t t = key_s[cur];
+        // slots before cur hold smaller keys, so the run ends at start + #(key <= t)
+        int cnt = 0;
+#pragma unroll
+        for (int s = 0; s < kCicPer; ++s) cnt += key[s] <= t ? 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = cnt;
+        __syncthreads();
+        int total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) total += red[w];
+        const int64_t rend = start + total > cur ? start + total : cur + 1;
+        const int ti = (int)(t >> (2 * tl)) << kBinLg, tj = (int)((t >> tl) & tmask) << kBinLg,
+                  tk = (int)(t & tmask) << kBinLg;
+#pragma unroll
+        for (int s = 0; s < kCicPer; ++s) {
+            if (key[s] != t) continue;
+            int i0, j0, k0;
+            double tx, ty, tz;
+            const bool ok = cic_axis(px[s], h, mask, i0, tx) && cic_axis(py[s], h, mask, j0, ty) &&
+                            cic_axis(pz[s], h, mask, k0, tz) && isfinite(pm[s]);
+            const int a = i0 - ti, b = j0 - tj, c = k0 - tk;
+            if (!ok || (unsigned)a >= (1u << kBinLg) || (unsigned)b >= (1u << kBinLg) ||
+                (unsigned)c >= (1u << kBinLg)) {
+                flag[0] = 1;
+                continue;
+            }
+            const double mp = pm[s];
+            const double wx0 = (1.0 - tx) * mp, wx1 = tx * mp, wy0 = 1.0 - ty, wy1 = ty, wz0 = 1.0 - tz, wz1 = tz;
+            double *w0 = win + (a * kWin + b) * kWin + c;
+            atomicAdd(w0, wx0 * wy0 * wz0);
+            atomicAdd(w0 + 1, wx0 * wy0 * wz1);
+            atomicAdd(w0 + kWin, wx0 * wy1 * wz0);
+            atomicAdd(w0 + kWin + 1, wx0 * wy1 * wz1);
+            atomicAdd(w0 + kWin * kWin, wx1 * wy0 * wz0);
+            atomicAdd(w0 + kWin * kWin + 1, wx1 * wy0 * wz1);
+            atomicAdd(w0 + kWin * kWin + kWin, wx1 * wy1 * wz0);
+            atomicAdd(w0 + kWin * kWin + kWin + 1, wx1 * wy1 * wz1);
+        }
+        __syncthreads();
+        for (int e = tid; e < kWin3; e += kBlock) {
+            const double v = win[e];
+            if (v != 0.0) {
+                const int a = e / (kWin * kWin), b = (e / kWin) % kWin, c = e % kWin;
+                const size_t g = ((((size_t)((ti + a) & mask) << lg) + (size_t)((tj + b) & mask)) << lg) +
+                                 (size_t)((tk + c) & mask);
+                unsafeAtomicAdd(&m[g], v);
+                win[e] = 0.0;
+            }
+        }
+        __syncthreads();
+        cur = rend;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_partial(const double *__restrict__ x, size_t n,
@@ -102,12 +188,16 @@ __global__ __launch_bounds__(kBlock) void k_fr(const double *__restrict__ u, dou
 }
 
 // a = pref * sum_cells w_cell * (f_R[+d] - f_R[-d]) / (2h)
+// Particles are visited in the order perm (the binning's tile order) when it
+// is given, else in index order; each particle's result is the same either way.
 __global__ __launch_bounds__(kBlock) void k_force_gather(const double *__restrict__ fr, const float *__restrict__ pos,
-                                                           int64_t np, int lg, double h, double pref,
-                                                           float *__restrict__ acc, int *__restrict__ flag)
+                                                           const uint32_t *__restrict__ perm, int64_t np, int lg,
+                                                           double h, double pref, float *__restrict__ acc,
+                                                           int *__restrict__ flag)
 {
-    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= np) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= np) return;
+    const int64_t p = perm ? (int64_t)perm[i] : i;
     const int mask = (1 << lg) - 1;
     int i0, j0, k0;
     double tx, ty, tz;
@@ -163,7 +253,14 @@ extern "C" int mgfr_assign_density(mgfr_ctx *c, const float *pos, const double *
     MGFR_HIP(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
     const size_t pblocks = (size_t)((np + kBlock - 1) / kBlock);
     if (pblocks > 0x7fffffffULL) return set_error(MGFR_ERR_ARG, "np too large");
-    k_cic_scatter<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(pos, mass, np, L0.lg, L0.h, delta, c->dflag);
+    c->perm_np = 0;
+    if (c->binning && np <= c->bin_cap) {
+        if (int e = bin_particles(c, pos, np)) return e;
+        k_cic_binned<<<(unsigned)((np + kCicChunk - 1) / kCicChunk), kBlock, 0, c->stream>>>(
+            pos, mass, c->bkey_s, c->perm, np, L0.lg, L0.h, delta, c->dflag);
+    } else {
+        k_cic_scatter<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(pos, mass, np, L0.lg, L0.h, delta, c->dflag);
+    }
     unsigned g = grid_for(n, (size_t)c->nparts);
     k_sum_partial<<<g, kBlock, 0, c->stream>>>(delta, n, c->partial);
     k_sum_final<<<1, 1024, 0, c->stream>>>(c->partial, (int)g, c->dscal + 4);
@@ -193,11 +290,28 @@ extern "C" int mgfr_fifth_force(mgfr_ctx *c, const double *u, const float *pos, 
     const size_t pblocks = (size_t)((np + kBlock - 1) / kBlock);
     if (pblocks > 0x7fffffffULL) return set_error(MGFR_ERR_ARG, "np too large");
     const double pref = kCkms * kCkms / (2.0 * c->p.a);
-    k_force_gather<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(fr, pos, np, L0.lg, L0.h, pref, acc, c->dflag);
+    const uint32_t *perm = (c->perm_np == np && c->perm) ? c->perm : nullptr;
+    k_force_gather<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(fr, pos, perm, np, L0.lg, L0.h, pref, acc,
+                                                                 c->dflag);
     MGFR_HIP(hipGetLastError());
     int *hflag = (int *)(c->hscal + 6);
     MGFR_HIP(hipMemcpyAsync(hflag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     MGFR_HIP(hipStreamSynchronize(c->stream));
     if (*hflag) return set_error(MGFR_ERR_NONFINITE, "a particle position is not finite");
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_reserve_particles(mgfr_ctx *c, int64_t max_np)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (max_np < 0) return set_error(MGFR_ERR_ARG, "max_np must be >= 0");
+    return bin_reserve(c, max_np);
+}
+
+extern "C" int mgfr_set_binning(mgfr_ctx *c, int on)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    c->binning = on ? 1 : 0;
+    c->perm_np = 0;
     return MGFR_OK;
 }

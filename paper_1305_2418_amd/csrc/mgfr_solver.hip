@@ -689,6 +689,7 @@ static void free_ctx(mgfr_ctx *c)
 {
     if (!c) return;
     nn_free(c);
+    bin_free(c);
     for (int l = 0; l < kMaxLevels; ++l) {
         Level &L = c->lev[l];
         if (l > 0) {

@@ -121,6 +121,8 @@ def lib() -> C.CDLL:
         L.mgfr_set_timing.argtypes = [_VP, C.c_int]
         L.mgfr_set_fused_min_mesh.argtypes = [_VP, C.c_int]
         L.mgfr_assign_density.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
+        L.mgfr_reserve_particles.argtypes = [_VP, C.c_int64]
+        L.mgfr_set_binning.argtypes = [_VP, C.c_int]
         L.mgfr_solve.argtypes = [_VP, _VP, _VP, _VP, C.POINTER(_Stats)]
         L.mgfr_fifth_force.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
         L.mgfr_ngs_sweep.argtypes = [_VP, _VP, _VP, C.c_int]
@@ -197,7 +199,7 @@ def background(p: Params):
 class Solver:
     """One mgfr context: the level hierarchy for an N^3 mesh on the current device."""
 
-    def __init__(self, params: Params, stream=None):
+    def __init__(self, params: Params, stream=None, binning: bool = True):
         self.params = params
         self._p = params.to_c()
         h = _VP()
@@ -205,6 +207,9 @@ class Solver:
         _check(lib().mgfr_create(C.byref(self._p), s, C.byref(h)))
         self._h = h
         self.N = params.mesh
+        self._binning = bool(binning)
+        self._bin_cap = 0
+        _check(lib().mgfr_set_binning(h, 1 if binning else 0))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -230,12 +235,24 @@ class Solver:
     def set_fused_min_mesh(self, n: int):
         _check(lib().mgfr_set_fused_min_mesh(self._h, int(n)))
 
+    def reserve_particles(self, max_np: int):
+        """Allocate the particle-binning workspace for up to max_np particles."""
+        self._sync_stream()
+        _check(lib().mgfr_reserve_particles(self._h, int(max_np)))
+        self._bin_cap = max(self._bin_cap, int(max_np))
+
+    def set_binning(self, on: bool):
+        self._binning = bool(on)
+        _check(lib().mgfr_set_binning(self._h, 1 if on else 0))
+
     def assign_density(self, pos: torch.Tensor, mass: torch.Tensor | None = None,
                        out: torch.Tensor | None = None) -> torch.Tensor:
         self._sync_stream()
         if pos.dim() != 2 or pos.shape[1] != 3:
             raise ValueError("pos must be [np, 3]")
         npart = pos.shape[0]
+        if self._binning and self._bin_cap < npart < 2 ** 31:
+            self.reserve_particles(npart)
         pp = _dev(pos, torch.float32, None, "pos")
         mp = _dev(mass, torch.float64, (npart,), "mass", allow_none=True)
         if out is None:

@@ -6,8 +6,8 @@
 
 `traffic` converts the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of
 the sweep kernels into bytes per launch, scaled by what the same counters read
-for the 1 GiB device-to-device copy the benchmark runs with --calibrate-copy
-(the copy reads and writes exactly 1 GiB).
+for the streaming kernel the benchmark runs with --calibrate-copy (a bitwise
+NOT of 1 GiB of int32 into another buffer: it reads and writes exactly 1 GiB).
 """
 from __future__ import annotations
 
@@ -22,7 +22,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SWEEPS = {"k_mx_sweep_fused": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip"],
           "k_sweep_fused": ["paper_1305_2418_amd/csrc/mgfr_solver.hip"]}
-COPY = "copyBuffer"
+COPY = "bitwise_not"
 
 
 def _short(name: str) -> str:

@@ -163,14 +163,33 @@ def test_small_meshes_all_in_tail():
 
 # ------------------------------------------------------------------ mass assignment
 
-@pytest.mark.parametrize("N,npart_side,halos", [(32, 32, 0), (64, 64, 20), (32, 50, 5)])
-def test_assign_matches_oracle(N, npart_side, halos):
+@pytest.mark.parametrize("binning", [True, False])
+@pytest.mark.parametrize("N,npart_side,halos", [(32, 32, 0), (64, 64, 20), (32, 50, 5), (8, 30, 3)])
+def test_assign_matches_oracle(N, npart_side, halos, binning):
     mg = _mg()
-    print(f"[case] assign N={N} np={npart_side}^3", flush=True)
+    print(f"[case] assign N={N} np={npart_side}^3 binning={binning}", flush=True)
     pos = _load(npart_side, 5.0, 21, halos)
     ref = O.density_contrast(O.cic_assign(N, 100.0, pos.numpy()))
-    s = mg.Solver(_params(mg, N))
+    s = mg.Solver(_params(mg, N), binning=binning)
     d = s.assign_density(pos.to(DEV)).cpu().numpy()
+    assert np.abs(d - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("N", [16, 64])
+def test_assign_binned_dense_clump(N):
+    """Most particles in one tile (runs longer than a workgroup's chunk and
+    crossing chunk boundaries) plus a thin uniform background; np ragged."""
+    mg = _mg()
+    print(f"[case] assign dense clump N={N}", flush=True)
+    rng = np.random.default_rng(N)
+    h = 100.0 / N
+    clump = (37.3 + rng.normal(0.0, 0.6 * h, (23001, 3))).astype(np.float32)
+    back = rng.uniform(0.0, 100.0, (3011, 3)).astype(np.float32)
+    pos = np.concatenate([back[:1000], clump, back[1000:]])
+    mass = rng.uniform(0.5, 2.0, pos.shape[0])
+    ref = O.density_contrast(O.cic_assign(N, 100.0, pos, mass))
+    s = mg.Solver(_params(mg, N))
+    d = s.assign_density(torch.tensor(pos, device=DEV), torch.tensor(mass, device=DEV)).cpu().numpy()
     assert np.abs(d - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
 
 
@@ -211,6 +230,25 @@ def test_fifth_force_matches_oracle(N, a):
     scale = np.abs(ref).max()
     # float32 output: |err| <= 2^-24 |a| per component plus a float64 gather floor
     assert np.all(np.abs(acc - ref) <= 6.0e-8 * np.abs(ref) + 1e-10 * scale)
+
+
+def test_fifth_force_after_binned_assignment():
+    """The force visits particles in the order the last assignment binned them;
+    the result must not depend on it, also when the positions changed since."""
+    mg = _mg()
+    N = 32
+    d = _delta(N, 5.0, 33, halos=5)
+    p = _oparams(N, fr0_abs=1e-5)
+    _, u_o, _, _ = O.solve(p, d)
+    pos_a = _load(N, 5.0, 34, 5)
+    pos_b = _load(N, 5.0, 35, 8)  # same count, other positions
+    s = mg.Solver(_params(mg, N, fr0_abs=1e-5))
+    s.assign_density(pos_a.to(DEV))
+    u = torch.tensor(u_o, device=DEV)
+    for pos in (pos_a, pos_b):
+        ref = O.fifth_force(p, u_o, pos.numpy())
+        acc = s.fifth_force(u, pos.to(DEV)).cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(acc - ref) <= 6.0e-8 * np.abs(ref) + 1e-10 * np.abs(ref).max())
 
 
 # ----------------------------------------------------------------- error behaviour

@@ -226,7 +226,8 @@ def main():
         kernel, bpc = ("k_sweep_fused" if N >= 512 else "k_sweep_half (x2 per sweep)"), 24.0
         src = KERNEL_SRC["fp64"]
     else:
-        kernel, bpc = "k_mx_sweep_fused", 16.0  # read e, u, r and write e (float32)
+        # one colour pass: read u and e of every cell, r of the updated half, write the updated half (float32)
+        kernel, bpc = "k_mx_colour (x2 per sweep)", 12.0
         src = KERNEL_SRC["mixed"]
     alg_bytes = bpc * N ** 3
     achieved = alg_bytes / (head["sweep_launch_ms"] * 1e-3) / 1e9
@@ -234,7 +235,7 @@ def main():
     tpath = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if os.path.exists(tpath):
         tj = json.load(open(tpath))
-        ent = tj.get(kernel)
+        ent = tj.get(kernel.split(" ")[0])
         if ent and ent.get("source_hash") == source_hash(src) and ent.get("mesh") == N:
             traffic = ent.get("bytes_per_launch")
     out = {

@@ -122,11 +122,19 @@ int mgfr_set_stream(mgfr_ctx *ctx, void *stream);
  * or off (reported in mgfr_stats.t_sweep_ms). */
 int mgfr_set_timing(mgfr_ctx *ctx, int on);
 
-/* Smallest level size N at which a red-black sweep runs as one fused,
- * out-of-place kernel (both colours per launch, LDS-staged tiles); smaller
- * levels use one in-place kernel per colour.  Default 512; 0 = never;
+/* Float64 sweeps: smallest level size N at which a red-black sweep runs as
+ * one fused, out-of-place kernel (both colours per launch, LDS-staged tiles);
+ * smaller levels use one in-place kernel per colour.  Default 512; 0 = never;
  * otherwise n >= 64.  Results agree to rounding either way. */
 int mgfr_set_fused_min_mesh(mgfr_ctx *ctx, int n);
+
+/* Float32 correction sweeps of the mixed-precision solve: smallest level size
+ * N at which each colour runs as the plane-marching pass kernel (row tiles of
+ * cell pairs staged in LDS, exponentials evaluated once per cell); smaller
+ * levels use the plain one-thread-per-cell kernel.  Default 128; 0 = never;
+ * otherwise n >= 128.  Both apply the same update in the same red-black
+ * order; results agree to float32 rounding. */
+int mgfr_set_colour_min_mesh(mgfr_ctx *ctx, int n);
 
 /* Cloud-in-cell assignment (Sec. 3.1) of np particles onto the N^3 mesh and
  * delta = m / m_bar - 1 with m_bar the mean cell mass of the assignment.

@@ -34,7 +34,6 @@ struct Level {
     double *alt = nullptr;  // second buffer of out-of-place sweeps (current iterate is u)
     // float32 mirrors for the mixed-precision inner cycle
     float *e32 = nullptr, *r32 = nullptr, *u32 = nullptr, *ebar32 = nullptr;
-    float *alt32 = nullptr;  // second buffer of out-of-place float32 sweeps
 };
 
 struct Timer {
@@ -53,7 +52,7 @@ struct mgfr_ctx {
     mgfr::Level lev[mgfr::kMaxLevels];
     double *alt0 = nullptr;  // level-0 second buffer (owned)
     int fused_min_n = 512;   // levels with N >= this use the fused out-of-place sweep (0: never)
-    int fused32_min_n = 256; // the same for the float32 correction sweeps
+    int colour32_min_n = 128; // float32 sweeps on levels with N >= this by one-colour pass kernels (0: never)
     // reduction scratch
     double *partial = nullptr;  // [2 * nparts]
     int nparts = 0;

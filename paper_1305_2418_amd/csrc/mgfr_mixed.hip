@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 namespace mgfr {
 
@@ -34,10 +35,6 @@ namespace {
 struct MxConst {
     float ih2, bC, q, max_du;
 };
-
-#ifndef MGFR_FUSED32_JL
-#define MGFR_FUSED32_JL 16
-#endif
 
 __device__ __forceinline__ size_t ix(int i, int j, int k, int lg)
 {
@@ -56,7 +53,8 @@ __device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x
 __device__ __forceinline__ float fexpm1(float x)
 {
     const float p = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
-    return fabsf(x) < 0.25f ? p : fexp(x) - 1.0f;
+    const float q = fexp(x) - 1.0f;  // evaluated unconditionally: a select, not a branch
+    return __builtin_amdgcn_fmed3f(fabsf(x), 0.0f, 0.25f) < 0.25f ? p : q;
 }
 
 // Newton step on e at one cell from precomputed per-cell quantities:
@@ -279,163 +277,184 @@ __device__ __forceinline__ float mx_prolong(const float *__restrict__ ec, const 
     return v;
 }
 
-// Newton step on e from neighbour quantities passed individually (fused kernel).
-__device__ __forceinline__ float mx_step6(float ec, float Xc, float uc, float wc, float sc, float r,
-                                          float e0, float X0, float u0, float w0, float e1, float X1, float u1,
-                                          float w1, float e2, float X2, float u2, float w2, float e3, float X3,
-                                          float u3, float w3, float e4, float X4, float u4, float w4, float e5,
-                                          float X5, float u5, float w5, const MxConst &k)
+// ---------------------------------------------------------- colour pass (N >= 128)
+//
+// One colour of the float32 correction sweep on a level with N >= 128: the
+// cells with (i + j + k) & 1 == colour are updated in place; all six
+// neighbours of such a cell have the other colour and are only read.
+// Workgroup: CTJ rows of a 128-cell row tile plus one halo row on each side,
+// one wave per row, marching over `chunk` planes.  Lane l holds the pair
+// k = k0 + 2l, k0 + 2l + 1 of its row; in each plane one of the two is updated
+// (column s, the same for the whole wave) and the other is published in LDS
+// for the rows above and below and the neighbouring lanes.  s alternates from
+// plane to plane, so the plane loop is written out for both parities.  e^u and
+// expm1(e) of a cell are evaluated once, when its plane is loaded, and kept as
+// P = e^u expm1(e) and W = e^(u+e); the cells beyond the tile's ends in k come
+// from the first lanes of the upper halo wave.
+// Traffic per pass: read u, e, r and write e, 16 B per cell (the algorithm
+// needs 12: r and the new e of the updated half only).
+
+constexpr int CTJ = 8;    // updated rows per workgroup
+constexpr int CKW = 128;  // cells per row tile
+constexpr int CLW = 66;   // LDS row: 64 lanes and one halo slot on each side
+
+struct Cell4 {
+    float u, e, P, W;
+};
+
+__device__ __forceinline__ Cell4 mx_cell(float u, float e)
 {
-    const float en[6] = {e0, e1, e2, e3, e4, e5}, Xn[6] = {X0, X1, X2, X3, X4, X5};
-    const float un[6] = {u0, u1, u2, u3, u4, u5}, wn[6] = {w0, w1, w2, w3, w4, w5};
+    const float w = fexp(u);
+    const float P = w * fexpm1(e);
+    return Cell4{u, e, P, w + P};
+}
+
+__device__ __forceinline__ float4 pack(const Cell4 &c) { return make_float4(c.u, c.e, c.P, c.W); }
+__device__ __forceinline__ Cell4 unpack(const float4 &v) { return Cell4{v.x, v.y, v.z, v.w}; }
+
+// New e at a cell from the cell, its residual target r and its six neighbours
+// (the same Newton step as mx_step, on the P/W form).
+__device__ __forceinline__ float mx_update(const Cell4 &c, float r, const Cell4 &n0, const Cell4 &n1,
+                                           const Cell4 &n2, const Cell4 &n3, const Cell4 &n4, const Cell4 &n5,
+                                           const MxConst &k)
+{
     float Su = 0.f, Se = 0.f, A = 0.f, B = 0.f, SW = 0.f;
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const float du = un[t] - uc, de = en[t] - ec;
-        const float Wn = wn[t] + wn[t] * Xn[t];
+    auto add = [&](const Cell4 &n) {
+        const float du = n.u - c.u, de = n.e - c.e;
         Su += du;
         Se += de;
-        A += wn[t] * Xn[t] * du;
-        B += Wn * de;
-        SW += Wn;
-    }
-    const float wXc = wc * Xc, Wc = wc + wXc;
-    const float flux = 0.5f * ((A + wXc * Su) + (B + Wc * Se));
-    const float dflux = 0.5f * (Wc * (Su + Se - 6.0f) - SW);
-    const float cm = fexpm1(-k.q * ec);
+        A = fmaf(n.P, du, A);
+        B = fmaf(n.W, de, B);
+        SW += n.W;
+    };
+    add(n0);
+    add(n1);
+    add(n2);
+    add(n3);
+    add(n4);
+    add(n5);
+    const float flux = 0.5f * ((A + c.P * Su) + (B + c.W * Se));
+    const float dflux = 0.5f * (c.W * (Su + Se - 6.0f) - SW);
+    const float sc = fexp(-k.q * c.u);
+    const float cm = fexpm1(-k.q * c.e);
     const float N = k.ih2 * flux + k.bC * sc * cm;
     const float J = k.ih2 * dflux - k.q * k.bC * sc * (1.0f + cm);
     float d = -(N - r) * __builtin_amdgcn_rcpf(J);
     if (k.max_du > 0.f) d = fminf(fmaxf(d, -k.max_du), k.max_du);
-    return d;
+    return c.e + d;
 }
 
-// e^{-q u} from u and w = e^u: rsqrt(w) for n = 1
-template <bool N1>
-__device__ __forceinline__ float mx_s(float u, float w, float q)
+struct ColourArgs {
+    float *e;
+    const float *u, *r;
+    int lg, colour, chunk;
+    MxConst kc;
+};
+
+// The plane loop of one wave whose updated column in the first plane is S0.
+template <int S0>
+__device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int j0, int k0, int wv, int lane,
+                                               float4 *sB)
 {
-    if constexpr (N1) return __builtin_amdgcn_rsqf(w);
-    else return fexp(-q * u);
-}
+    const int lg = A.lg, m = (1 << lg) - 1;
+    const int row = wv - 1;                      // -1 and CTJ: halo rows
+    const bool upd = row >= 0 && row < CTJ;      // uniform over the wave
+    const size_t plane = (size_t)1 << (2 * lg);
+    const size_t rowoff = ((size_t)((j0 + row) & m) << lg) + (size_t)(k0 + 2 * lane);
+    auto at = [&](int pl) { return (size_t)(pl & m) * plane + rowoff; };
+    auto ld2 = [&](const float *a, int pl) { return *reinterpret_cast<const float2 *>(a + at(pl)); };
+    // k-halo duty: lanes 0..CTJ-1 of the upper halo wave serve row `lane`
+    const bool kh = wv == 0 && lane < CTJ;
+    const size_t khrow = (size_t)((j0 + lane) & m) << lg;
+    const int khpar = (A.colour + j0 + lane) & 1;  // updated column of that row in even planes
+    auto kh_at = [&](int pl) {
+        const int side = khpar ^ (pl & 1);
+        return (size_t)(pl & m) * plane + khrow + (size_t)(side ? ((k0 + CKW) & m) : ((k0 - 1) & m));
+    };
+    auto kh_slot = [&](int pl) { return (lane + 1) * CLW + ((khpar ^ (pl & 1)) ? CLW - 1 : 0); };
 
-// One full red-black sweep of the float32 correction e, out of place
-// (eout = sweep(ein)); same tiling and row-pair scheme as the float64 fused
-// sweep.  Each staged cell carries e, X = expm1(e), the linearisation point u
-// and w = e^u, computed once when the plane is loaded; X is refreshed after a
-// red update.  Traffic: read e, u, r and write e, 16 B/cell.
-constexpr int MKL = 64, MKI = 60;
-
-template <bool N1, int JL>
-__global__ __launch_bounds__(32 * JL) void k_mx_sweep_fused(const float *__restrict__ ein,
-                                                              const float *__restrict__ u,
-                                                              const float *__restrict__ r,
-                                                              float *__restrict__ eout, int lg, int chunk,
-                                                              MxConst kc)
-{
-    constexpr int JI = JL - 4;
-    __shared__ float sEv[2][JL][MKL], sX[2][JL][MKL], sU[2][JL][MKL], sW[2][JL][MKL];
-    const int N = 1 << lg, m = N - 1;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int k0 = blockIdx.x * MKI, j0 = blockIdx.y * JI, i0 = blockIdx.z * chunk;
-    const int kku = k0 - 2 + lane;
-    const int kg = kku & m;
-    const bool kin1 = lane >= 1 && lane <= MKL - 2;
-    const bool kint = lane >= 2 && lane <= MKL - 3 && kku < N;
-    const int ra = 2 * w, rb = ra + 1;
-    const int jga = (j0 - 2 + ra) & m, jgb = (j0 - 2 + rb) & m;
-    const bool in1a = ra >= 1 && ra <= JL - 2, in1b = rb >= 1 && rb <= JL - 2;
-    const bool inta = ra >= 2 && ra <= JL - 3 && j0 - 2 + ra < N;
-    const bool intb = rb >= 2 && rb <= JL - 3 && j0 - 2 + rb < N;
-    const bool lda = in1a && kin1, ldb = in1b && kin1;
-    const int lm = lane > 0 ? lane - 1 : 0, lp = lane < MKL - 1 ? lane + 1 : MKL - 1;
-    auto at = [&](int i, int jg) { return (((((size_t)(i & m)) << lg) + (size_t)jg) << lg) + (size_t)kg; };
-
-    // plane p-1 (red row of plane p-1 = black row of plane p)
-    float e0s = 0.f, X0s = 0.f, u0s = 0.f, w0s = 0.f;
-    // planes p (red updated, black old) and p+1 (old)
-    float e1a = ein[at(i0 - 2, jga)], e1b = ein[at(i0 - 2, jgb)];
-    float u1a = u[at(i0 - 2, jga)], u1b = u[at(i0 - 2, jgb)];
-    float e2a = ein[at(i0 - 1, jga)], e2b = ein[at(i0 - 1, jgb)];
-    float u2a = u[at(i0 - 1, jga)], u2b = u[at(i0 - 1, jgb)];
-    float r1s = 0.f;
-    float r2a = lda ? r[at(i0 - 1, jga)] : 0.f, r2b = ldb ? r[at(i0 - 1, jgb)] : 0.f;
-    float e4a = ein[at(i0, jga)], e4b = ein[at(i0, jgb)];
-    float u4a = u[at(i0, jga)], u4b = u[at(i0, jgb)];
-    float r4a = lda ? r[at(i0, jga)] : 0.f, r4b = ldb ? r[at(i0, jgb)] : 0.f;
-    float X1a = fexpm1(e1a), X1b = fexpm1(e1b), w1a = fexp(u1a), w1b = fexp(u1b);
-    float X2a = fexpm1(e2a), X2b = fexpm1(e2b), w2a = fexp(u2a), w2b = fexp(u2b);
-    int xb = 0;
-    for (int p = i0 - 2; p < i0 + chunk; ++p) {
-        const float e3a = e4a, e3b = e4b, u3a = u4a, u3b = u4b, r3a = r4a, r3b = r4b;
-        if (p + 1 < i0 + chunk) {
-            e4a = ein[at(p + 3, jga)];
-            e4b = ein[at(p + 3, jgb)];
-            u4a = u[at(p + 3, jga)];
-            u4b = u[at(p + 3, jgb)];
-            r4a = lda ? r[at(p + 3, jga)] : 0.f;
-            r4b = ldb ? r[at(p + 3, jgb)] : 0.f;
-        }
-        const float X3a = fexpm1(e3a), X3b = fexpm1(e3b), w3a = fexp(u3a), w3b = fexp(u3b);
-        __syncthreads();
-        sEv[xb][ra][lane] = e2a;
-        sEv[xb][rb][lane] = e2b;
-        sX[xb][ra][lane] = X2a;
-        sX[xb][rb][lane] = X2b;
-        sU[xb][ra][lane] = u2a;
-        sU[xb][rb][lane] = u2b;
-        sW[xb][ra][lane] = w2a;
-        sW[xb][rb][lane] = w2b;
-        __syncthreads();
-        const int sel = ((p + 1) + jga + kg) & 1;
-        const int rr = ra + sel;
-        const int rc = rr < 1 ? 1 : (rr > JL - 2 ? JL - 2 : rr);
-        {
-            const bool act = kin1 && (sel ? in1b : in1a);
-            const float ec = sel ? e2b : e2a, Xc = sel ? X2b : X2a, uc = sel ? u2b : u2a, wc = sel ? w2b : w2a;
-            const float d = mx_step6(
-                ec, Xc, uc, wc, mx_s<N1>(uc, wc, kc.q), sel ? r2b : r2a, sel ? e1b : e1a, sel ? X1b : X1a,
-                sel ? u1b : u1a, sel ? w1b : w1a, sel ? e3b : e3a, sel ? X3b : X3a, sel ? u3b : u3a,
-                sel ? w3b : w3a, sEv[xb][rc - 1][lane], sX[xb][rc - 1][lane], sU[xb][rc - 1][lane],
-                sW[xb][rc - 1][lane], sEv[xb][rc + 1][lane], sX[xb][rc + 1][lane], sU[xb][rc + 1][lane],
-                sW[xb][rc + 1][lane], sEv[xb][rc][lm], sX[xb][rc][lm], sU[xb][rc][lm], sW[xb][rc][lm],
-                sEv[xb][rc][lp], sX[xb][rc][lp], sU[xb][rc][lp], sW[xb][rc][lp], kc);
-            const float en = ec + d;
-            const float Xn = fexpm1(en);
-            e2a = (act && !sel) ? en : e2a;
-            X2a = (act && !sel) ? Xn : X2a;
-            e2b = (act && sel) ? en : e2b;
-            X2b = (act && sel) ? Xn : X2b;
-            if (act) {
-                sEv[xb][rr][lane] = en;
-                sX[xb][rr][lane] = Xn;
-            }
-        }
-        if (p >= i0) {
-            const int yb = xb ^ 1;
-            const bool act = kint && (sel ? intb : inta);
-            const float ec = sel ? e1b : e1a, Xc = sel ? X1b : X1a, uc = sel ? u1b : u1a, wc = sel ? w1b : w1a;
-            const float d = mx_step6(
-                ec, Xc, uc, wc, mx_s<N1>(uc, wc, kc.q), r1s, e0s, X0s, u0s, w0s, sel ? e2b : e2a,
-                sel ? X2b : X2a, sel ? u2b : u2a, sel ? w2b : w2a, sEv[yb][rc - 1][lane], sX[yb][rc - 1][lane],
-                sU[yb][rc - 1][lane], sW[yb][rc - 1][lane], sEv[yb][rc + 1][lane], sX[yb][rc + 1][lane],
-                sU[yb][rc + 1][lane], sW[yb][rc + 1][lane], sEv[yb][rc][lm], sX[yb][rc][lm], sU[yb][rc][lm],
-                sW[yb][rc][lm], sEv[yb][rc][lp], sX[yb][rc][lp], sU[yb][rc][lp], sW[yb][rc][lp], kc);
-            const float en = ec + d;
-            e1a = (act && !sel) ? en : e1a;
-            e1b = (act && sel) ? en : e1b;
-            if (kint && inta) eout[at(p, jga)] = e1a;
-            if (kint && intb) eout[at(p, jgb)] = e1b;
-        }
-        e0s = sel ? e1a : e1b;
-        X0s = sel ? X1a : X1b;
-        u0s = sel ? u1a : u1b;
-        w0s = sel ? w1a : w1b;
-        r1s = sel ? r2a : r2b;
-        e1a = e2a; e1b = e2b; X1a = X2a; X1b = X2b; u1a = u2a; u1b = u2b; w1a = w2a; w1b = w2b;
-        e2a = e3a; e2b = e3b; X2a = X3a; X2b = X3b; u2a = u3a; u2b = u3b; w2a = w3a; w2b = w3b;
-        r2a = r3a; r2b = r3b;
-        xb ^= 1;
+    // prologue: plane i0 (both columns), plane i0 - 1 (column S0), raw plane i0 + 1
+    Cell4 c0, c1, prev;
+    {
+        const float2 u0 = ld2(A.u, i0), e0 = ld2(A.e, i0);
+        const float2 um = ld2(A.u, i0 - 1), em = ld2(A.e, i0 - 1);
+        c0 = mx_cell(u0.x, e0.x);
+        c1 = mx_cell(u0.y, e0.y);
+        prev = S0 ? mx_cell(um.y, em.y) : mx_cell(um.x, em.x);
     }
+    float2 nu = ld2(A.u, i0 + 1), ne = ld2(A.e, i0 + 1);
+    float rr = upd ? A.r[at(i0) + S0] : 0.f;
+    float khu = 0.f, khe = 0.f;
+    if (kh) {
+        const size_t o = kh_at(i0);
+        khu = A.u[o];
+        khe = A.e[o];
+    }
+    int buf = 0;
+
+    // one plane with updated column S
+    auto step = [&](int p, auto Sc) {
+        constexpr int S = decltype(Sc)::value;
+        // loads for later planes
+        const float2 nu2 = ld2(A.u, p + 2), ne2 = ld2(A.e, p + 2);
+        const float rr2 = upd ? A.r[at(p + 1) + (1 - S)] : 0.f;
+        float khu2 = 0.f, khe2 = 0.f;
+        if (kh) {
+            const size_t o = kh_at(p + 1);
+            khu2 = A.u[o];
+            khe2 = A.e[o];
+        }
+        // plane p + 1 from the raw values loaded one plane ago
+        const Cell4 n0 = mx_cell(nu.x, ne.x), n1 = mx_cell(nu.y, ne.y);
+        float4 *B = sB + buf * (CTJ + 2) * CLW;
+        B[(row + 1) * CLW + lane + 1] = pack(S ? c0 : c1);
+        if (kh) B[kh_slot(p)] = pack(mx_cell(khu, khe));
+        __syncthreads();
+        if (upd) {
+            const Cell4 up = unpack(B[row * CLW + lane + 1]);
+            const Cell4 dn = unpack(B[(row + 2) * CLW + lane + 1]);
+            const Cell4 sd = unpack(B[(row + 1) * CLW + lane + (S ? 2 : 0)]);
+            const float en = S ? mx_update(c1, rr, c0, sd, up, dn, prev, n1, A.kc)
+                               : mx_update(c0, rr, c1, sd, up, dn, prev, n0, A.kc);
+            // the whole pair is written (full lines); the other cell's value is
+            // the one every reader of this pass sees
+            *reinterpret_cast<float2 *>(A.e + at(p)) = S ? make_float2(c0.e, en) : make_float2(en, c1.e);
+        }
+        prev = S ? c0 : c1;
+        c0 = n0;
+        c1 = n1;
+        nu = nu2;
+        ne = ne2;
+        rr = rr2;
+        khu = khu2;
+        khe = khe2;
+        buf ^= 1;
+    };
+    for (int p = i0; p < i0 + A.chunk; p += 2) {
+        step(p, std::integral_constant<int, S0>{});
+        step(p + 1, std::integral_constant<int, 1 - S0>{});
+    }
+}
+
+// grid: 1-D, (N / CKW) (N / CTJ) (N / chunk) workgroups, spread so that
+// workgroups adjacent in j run on the same XCD (they share halo rows)
+__global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour(ColourArgs A)
+{
+    __shared__ float4 sB[2 * (CTJ + 2) * CLW];
+    const int lg = A.lg;
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned L = (b & 7u) * (nb >> 3) + (b >> 3);  // nb is a multiple of 8
+    const int nkt = (1 << lg) / CKW, njt = (1 << lg) / CTJ;
+    const int kt = (int)(L % (unsigned)nkt), jt = (int)((L / (unsigned)nkt) % (unsigned)njt),
+              it = (int)(L / ((unsigned)nkt * (unsigned)njt));
+    const int k0 = kt * CKW, j0 = jt * CTJ, i0 = it * A.chunk;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int s0 = (A.colour + i0 + j0 + wv - 1) & 1;  // updated column of this wave's row in plane i0
+    if (s0)
+        mx_colour_rows<1>(A, i0, j0, k0, wv, lane, sB);
+    else
+        mx_colour_rows<0>(A, i0, j0, k0, wv, lane, sB);
 }
 
 // ------------------------------------------------------------------- kernels
@@ -642,40 +661,54 @@ MxConst mx_const(const mgfr_ctx *c, int l)
     return MxConst{(float)(1.0 / (c->lev[l].h * c->lev[l].h)), (float)c->bC, (float)c->q, (float)c->p.max_du};
 }
 
+// Per-launch timing of the finest level's sweep kernels: a pair of events
+// around each launch (read back by collect_timing).
+static int timer_slot(mgfr_ctx *c, bool timed, int &slot)
+{
+    slot = -1;
+    if (!timed) return MGFR_OK;
+    Timer &T = c->sweep_timer;
+    if (T.used + 2 > (int)T.ev.size())
+        for (int q = 0; q < 16; ++q) {
+            hipEvent_t ev;
+            MGFR_HIP(hipEventCreate(&ev));
+            T.ev.push_back(ev);
+        }
+    slot = T.used;
+    T.used += 2;
+    MGFR_HIP(hipEventRecord(T.ev[slot], c->stream));
+    return MGFR_OK;
+}
+
+static int timer_end(mgfr_ctx *c, int slot)
+{
+    if (slot >= 0) MGFR_HIP(hipEventRecord(c->sweep_timer.ev[slot + 1], c->stream));
+    return MGFR_OK;
+}
+
 int mx_launch_sweeps(mgfr_ctx *c, int l, int sweeps, bool timed)
 {
     Level &L = c->lev[l];
     const MxConst kc = mx_const(c, l);
     const size_t half = (size_t)1 << (3 * L.lg - 1);
+    const bool colour_pass = c->colour32_min_n > 0 && L.N >= c->colour32_min_n;
+    int slot, rc;
     for (int s = 0; s < sweeps; ++s) {
-        int slot = -1;
-        if (timed) {
-            Timer &T = c->sweep_timer;
-            if (T.used + 2 > (int)T.ev.size())
-                for (int q = 0; q < 16; ++q) {
-                    hipEvent_t ev;
-                    MGFR_HIP(hipEventCreate(&ev));
-                    T.ev.push_back(ev);
-                }
-            slot = T.used;
-            T.used += 2;
-            MGFR_HIP(hipEventRecord(T.ev[slot], c->stream));
-        }
-        const bool fused = c->fused32_min_n > 0 && L.N >= c->fused32_min_n && L.alt32 != nullptr;
-        if (fused) {
-            constexpr int JL = MGFR_FUSED32_JL;
-            const int chunk = L.N / 8 < 8 ? 8 : L.N / 8;
-            dim3 grid((unsigned)((L.N + MKI - 1) / MKI), (unsigned)((L.N + JL - 5) / (JL - 4)), (unsigned)(L.N / chunk));
-            if (c->p.n == 1)
-                k_mx_sweep_fused<true, JL><<<grid, 32 * JL, 0, c->stream>>>(L.e32, L.u32, L.r32, L.alt32, L.lg, chunk, kc);
-            else
-                k_mx_sweep_fused<false, JL><<<grid, 32 * JL, 0, c->stream>>>(L.e32, L.u32, L.r32, L.alt32, L.lg, chunk, kc);
-            std::swap(L.e32, L.alt32);
+        if (colour_pass) {
+            const int chunk = L.N / 8;
+            const unsigned nb = (unsigned)((L.N / CKW) * (L.N / CTJ) * (L.N / chunk));
+            for (int colour = 0; colour < 2; ++colour) {
+                if ((rc = timer_slot(c, timed, slot))) return rc;
+                k_mx_colour<<<nb, 64 * (CTJ + 2), 0, c->stream>>>(ColourArgs{L.e32, L.u32, L.r32, L.lg, colour, chunk, kc});
+                if ((rc = timer_end(c, slot))) return rc;
+            }
         } else {
-            for (int colour = 0; colour < 2; ++colour)
+            for (int colour = 0; colour < 2; ++colour) {
+                if ((rc = timer_slot(c, timed, slot))) return rc;
                 k_mx_sweep_half<<<nb(half), kBlock, 0, c->stream>>>(L.e32, L.u32, L.r32, L.lg, colour, kc);
+                if ((rc = timer_end(c, slot))) return rc;
+            }
         }
-        if (timed) MGFR_HIP(hipEventRecord(c->sweep_timer.ev[slot + 1], c->stream));
     }
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
@@ -733,7 +766,6 @@ int mixed_alloc(mgfr_ctx *c)
         Level &L = c->lev[l];
         const size_t bytes = sizeof(float) * (size_t)L.N * L.N * L.N;
         MGFR_HIP(hipMalloc(&L.e32, bytes));
-        if (L.N >= 64) MGFR_HIP(hipMalloc(&L.alt32, bytes));
         MGFR_HIP(hipMalloc(&L.r32, bytes));
         MGFR_HIP(hipMalloc(&L.u32, bytes));
         if (l > 0) MGFR_HIP(hipMalloc(&L.ebar32, bytes));

@@ -702,7 +702,6 @@ static void free_ctx(mgfr_ctx *c)
         (void)hipFree(L.r32);
         (void)hipFree(L.u32);
         (void)hipFree(L.ebar32);
-        (void)hipFree(L.alt32);
     }
     (void)hipFree(c->alt0);
     (void)hipFree(c->partial);
@@ -931,7 +930,14 @@ extern "C" int mgfr_set_fused_min_mesh(mgfr_ctx *c, int n)
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
     if (n != 0 && n < 64) return set_error(MGFR_ERR_ARG, "fused sweeps need levels of at least 64^3 (or 0 = off)");
     c->fused_min_n = n;
-    c->fused32_min_n = n;
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_set_colour_min_mesh(mgfr_ctx *c, int n)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (n != 0 && n < 128) return set_error(MGFR_ERR_ARG, "one-colour pass kernels need levels of at least 128^3 (or 0 = off)");
+    c->colour32_min_n = n;
     return MGFR_OK;
 }
 

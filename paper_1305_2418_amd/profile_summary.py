@@ -20,7 +20,8 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SWEEPS = {"k_mx_sweep_fused": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip"],
+SWEEPS = {"k_mx_colour": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip"],
+          "k_mx_sweep_fused": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip"],
           "k_sweep_fused": ["paper_1305_2418_amd/csrc/mgfr_solver.hip"]}
 COPY = "bitwise_not"
 

@@ -41,6 +41,16 @@ __device__ __forceinline__ size_t ix(int i, int j, int k, int lg)
     return (((((size_t)i) << lg) + (size_t)j) << lg) + (size_t)k;
 }
 
+// Index of cell (i,j,k) in a float32 correction-cycle array e, r or ebar of a
+// level: natural order, or (split) every (i,j) row holding its cells with
+// i + j + k even first (in k order), then the odd ones, so that a one-colour
+// pass reads and writes its half of a row contiguously.  u32 is always natural.
+__device__ __forceinline__ size_t sx(int i, int j, int k, int lg, bool split)
+{
+    const size_t row = ((((size_t)i) << lg) + (size_t)j) << lg;
+    return split ? row + ((size_t)((i + j + k) & 1) << (lg - 1)) + (size_t)(k >> 1) : row + (size_t)k;
+}
+
 __device__ __forceinline__ double nanmax_d(double a, double b) { return (a != a || a > b) ? a : b; }
 
 // e^x for the float32 correction cycle: the hardware base-2 exponential of
@@ -111,20 +121,19 @@ struct MxCell {
 };
 
 __device__ __forceinline__ void mx_gather(const float *__restrict__ e, const float *__restrict__ u, int i, int j,
-                                          int k, int lg, MxCell &c)
+                                          int k, int lg, MxCell &c, bool split = false)
 {
     const int m = (1 << lg) - 1;
-    const size_t idx[6] = {ix((i + 1) & m, j, k, lg), ix((i - 1) & m, j, k, lg), ix(i, (j + 1) & m, k, lg),
-                           ix(i, (j - 1) & m, k, lg), ix(i, j, (k + 1) & m, lg), ix(i, j, (k - 1) & m, lg)};
-    const size_t cc = ix(i, j, k, lg);
-    c.ec = e[cc];
-    c.uc = u[cc];
+    const int ni[6] = {(i + 1) & m, (i - 1) & m, i, i, i, i}, nj[6] = {j, j, (j + 1) & m, (j - 1) & m, j, j},
+              nk[6] = {k, k, k, k, (k + 1) & m, (k - 1) & m};
+    c.ec = e[sx(i, j, k, lg, split)];
+    c.uc = u[ix(i, j, k, lg)];
     c.Xc = fexpm1(c.ec);
     c.wc = fexp(c.uc);
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
-        c.en[t] = e[idx[t]];
-        c.un[t] = u[idx[t]];
+        c.en[t] = e[sx(ni[t], nj[t], nk[t], lg, split)];
+        c.un[t] = u[ix(ni[t], nj[t], nk[t], lg)];
         c.Xn[t] = fexpm1(c.en[t]);
         c.wn[t] = fexp(c.un[t]);
     }
@@ -146,10 +155,10 @@ __device__ __forceinline__ void mx_sweep_cell(float *__restrict__ e, const float
 }
 
 __device__ __forceinline__ float mx_value_at(const float *__restrict__ e, const float *__restrict__ u, int i, int j,
-                                             int k, int lg, const MxConst &kc)
+                                             int k, int lg, const MxConst &kc, bool split = false)
 {
     MxCell c;
-    mx_gather(e, u, i, j, k, lg, c);
+    mx_gather(e, u, i, j, k, lg, c, split);
     return mx_value(c.ec, c.Xc, c.uc, c.wc, c.en, c.Xn, c.un, c.wn, kc);
 }
 
@@ -157,7 +166,7 @@ __device__ __forceinline__ float mx_value_at(const float *__restrict__ e, const 
 // the 2x2x2 block and its 24 face neighbours are loaded and exponentiated once.
 __device__ __forceinline__ void mx_restrict_block(const float *__restrict__ e, const float *__restrict__ u,
                                                   const float *__restrict__ r, int I, int J, int K, int lg,
-                                                  const MxConst &kc, float &em, float &um, float &rm)
+                                                  const MxConst &kc, float &em, float &um, float &rm, bool split)
 {
     const int m = (1 << lg) - 1;
     const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
@@ -170,22 +179,20 @@ __device__ __forceinline__ void mx_restrict_block(const float *__restrict__ e, c
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const size_t cc = ix(i0 + a, j0 + b, k0 + c, lg);
-                Be[a * 4 + b * 2 + c] = e[cc];
-                Bu[a * 4 + b * 2 + c] = u[cc];
+                Be[a * 4 + b * 2 + c] = e[sx(i0 + a, j0 + b, k0 + c, lg, split)];
+                Bu[a * 4 + b * 2 + c] = u[ix(i0 + a, j0 + b, k0 + c, lg)];
             }
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const size_t f0 = ix((i0 + 2) & m, j0 + p, k0 + q, lg), f1 = ix((i0 - 1) & m, j0 + p, k0 + q, lg);
-            const size_t f2 = ix(i0 + p, (j0 + 2) & m, k0 + q, lg), f3 = ix(i0 + p, (j0 - 1) & m, k0 + q, lg);
-            const size_t f4 = ix(i0 + p, j0 + q, (k0 + 2) & m, lg), f5 = ix(i0 + p, j0 + q, (k0 - 1) & m, lg);
-            const size_t fi[6] = {f0, f1, f2, f3, f4, f5};
+            const int fi[6] = {(i0 + 2) & m, (i0 - 1) & m, i0 + p, i0 + p, i0 + p, i0 + p};
+            const int fj[6] = {j0 + p, j0 + p, (j0 + 2) & m, (j0 - 1) & m, j0 + q, j0 + q};
+            const int fk[6] = {k0 + q, k0 + q, k0 + q, k0 + q, (k0 + 2) & m, (k0 - 1) & m};
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
-                Fe[f][p * 2 + q] = e[fi[f]];
-                Fu[f][p * 2 + q] = u[fi[f]];
+                Fe[f][p * 2 + q] = e[sx(fi[f], fj[f], fk[f], lg, split)];
+                Fu[f][p * 2 + q] = u[ix(fi[f], fj[f], fk[f], lg)];
             }
         }
 #pragma unroll
@@ -226,7 +233,7 @@ __device__ __forceinline__ void mx_restrict_block(const float *__restrict__ e, c
                 const float N = mx_value(Be[t], BX[t], Bu[t], Bw[t], en, Xn, un, wn, kc);
                 se += Be[t];
                 su += Bu[t];
-                sr += r[ix(i0 + a, j0 + b, k0 + c, lg)] - N;
+                sr += r[sx(i0 + a, j0 + b, k0 + c, lg, split)] - N;
             }
     em = 0.125f * se;
     um = 0.125f * su;
@@ -291,8 +298,8 @@ __device__ __forceinline__ float mx_prolong(const float *__restrict__ ec, const 
 // expm1(e) of a cell are evaluated once, when its plane is loaded, and kept as
 // P = e^u expm1(e) and W = e^(u+e); the cells beyond the tile's ends in k come
 // from the first lanes of the upper halo wave.
-// Traffic per pass: read u, e, r and write e, 16 B per cell (the algorithm
-// needs 12: r and the new e of the updated half only).
+// e, r and ebar of such a level are stored split by colour (see sx), so the
+// pass reads r and writes e of its half only: 12 B per cell.
 
 constexpr int CTJ = 8;    // updated rows per workgroup
 constexpr int CKW = 128;  // cells per row tile
@@ -357,82 +364,90 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
                                                float4 *sB)
 {
     const int lg = A.lg, m = (1 << lg) - 1;
+    const size_t hN = (size_t)1 << (lg - 1);
     const int row = wv - 1;                      // -1 and CTJ: halo rows
     const bool upd = row >= 0 && row < CTJ;      // uniform over the wave
+    const int jg = (j0 + row) & m;
     const size_t plane = (size_t)1 << (2 * lg);
-    const size_t rowoff = ((size_t)((j0 + row) & m) << lg) + (size_t)(k0 + 2 * lane);
-    auto at = [&](int pl) { return (size_t)(pl & m) * plane + rowoff; };
-    auto ld2 = [&](const float *a, int pl) { return *reinterpret_cast<const float2 *>(a + at(pl)); };
-    // k-halo duty: lanes 0..CTJ-1 of the upper halo wave serve row `lane`
+    const size_t rowbase = (size_t)jg << lg;
+    const size_t kk = (size_t)(k0 + 2 * lane), kh2 = (size_t)(k0 / 2 + lane);
+    auto pb = [&](int pl) { return (size_t)(pl & m) * plane + rowbase; };
+    // u in natural order; e and r split by colour (column 0 of plane pl lies in half (pl + jg) & 1)
+    auto ldu = [&](int pl) { return *reinterpret_cast<const float2 *>(A.u + pb(pl) + kk); };
+    auto lde = [&](int pl) {
+        const size_t b = pb(pl) + kh2;
+        const bool odd = ((pl + jg) & 1) != 0;
+        return make_float2(A.e[b + (odd ? hN : 0)], A.e[b + (odd ? 0 : hN)]);
+    };
+    auto at_c = [&](int pl) { return pb(pl) + (size_t)A.colour * hN + kh2; };  // the updated cell's slot
+    // k-halo duty: lanes 0..CTJ-1 of the upper halo wave serve row `lane`.  Every
+    // lane of every wave issues the same loads in every plane (lane mod CTJ), so
+    // that no load sits under a branch and the prefetch waits stay exact.
     const bool kh = wv == 0 && lane < CTJ;
-    const size_t khrow = (size_t)((j0 + lane) & m) << lg;
-    const int khpar = (A.colour + j0 + lane) & 1;  // updated column of that row in even planes
-    auto kh_at = [&](int pl) {
-        const int side = khpar ^ (pl & 1);
-        return (size_t)(pl & m) * plane + khrow + (size_t)(side ? ((k0 + CKW) & m) : ((k0 - 1) & m));
+    const int khq = lane & (CTJ - 1);
+    const size_t khrow = (size_t)((j0 + khq) & m) << lg;
+    const int khpar = (A.colour + j0 + khq) & 1;  // updated column of that row in even planes
+    auto kh_k = [&](int pl) { return (khpar ^ (pl & 1)) ? ((k0 + CKW) & m) : ((k0 - 1) & m); };
+    auto kh_u = [&](int pl) { return (size_t)(pl & m) * plane + khrow + (size_t)kh_k(pl); };
+    // the halo cell has the other colour
+    auto kh_e = [&](int pl) {
+        return (size_t)(pl & m) * plane + khrow + (size_t)(1 - A.colour) * hN + (size_t)(kh_k(pl) >> 1);
     };
     auto kh_slot = [&](int pl) { return (lane + 1) * CLW + ((khpar ^ (pl & 1)) ? CLW - 1 : 0); };
 
     // prologue: plane i0 (both columns), plane i0 - 1 (column S0), raw plane i0 + 1
     Cell4 c0, c1, prev;
     {
-        const float2 u0 = ld2(A.u, i0), e0 = ld2(A.e, i0);
-        const float2 um = ld2(A.u, i0 - 1), em = ld2(A.e, i0 - 1);
+        const float2 u0 = ldu(i0), e0 = lde(i0);
+        const float2 um = ldu(i0 - 1), em = lde(i0 - 1);
         c0 = mx_cell(u0.x, e0.x);
         c1 = mx_cell(u0.y, e0.y);
         prev = S0 ? mx_cell(um.y, em.y) : mx_cell(um.x, em.x);
     }
-    float2 nu = ld2(A.u, i0 + 1), ne = ld2(A.e, i0 + 1);
-    float rr = upd ? A.r[at(i0) + S0] : 0.f;
-    float khu = 0.f, khe = 0.f;
-    if (kh) {
-        const size_t o = kh_at(i0);
-        khu = A.u[o];
-        khe = A.e[o];
-    }
+    // raw loads of step p: u, e of plane p + 1, r of plane p, the k-halo cell of plane p;
+    // two sets alternate so that no register holding a load in flight is copied
+    struct Raw {
+        float2 u, e;
+        float r, khu, khe;
+    };
+    auto load = [&](int p) {
+        Raw w;
+        w.u = ldu(p + 1);
+        w.e = lde(p + 1);
+        w.r = A.r[at_c(p)];  // halo rows: loaded, not used
+        w.khu = A.u[kh_u(p)];
+        w.khe = A.e[kh_e(p)];
+        return w;
+    };
+    Raw ra = load(i0), rb;
     int buf = 0;
 
-    // one plane with updated column S
-    auto step = [&](int p, auto Sc) {
+    // one plane with updated column S: consume cur (step p), load nxt (step p + 1)
+    auto step = [&](int p, auto Sc, const Raw &cur, Raw &nxt) {
         constexpr int S = decltype(Sc)::value;
-        // loads for later planes
-        const float2 nu2 = ld2(A.u, p + 2), ne2 = ld2(A.e, p + 2);
-        const float rr2 = upd ? A.r[at(p + 1) + (1 - S)] : 0.f;
-        float khu2 = 0.f, khe2 = 0.f;
-        if (kh) {
-            const size_t o = kh_at(p + 1);
-            khu2 = A.u[o];
-            khe2 = A.e[o];
-        }
+        nxt = load(p + 1);
         // plane p + 1 from the raw values loaded one plane ago
-        const Cell4 n0 = mx_cell(nu.x, ne.x), n1 = mx_cell(nu.y, ne.y);
+        const Cell4 n0 = mx_cell(cur.u.x, cur.e.x), n1 = mx_cell(cur.u.y, cur.e.y);
         float4 *B = sB + buf * (CTJ + 2) * CLW;
         B[(row + 1) * CLW + lane + 1] = pack(S ? c0 : c1);
-        if (kh) B[kh_slot(p)] = pack(mx_cell(khu, khe));
+        if (kh) B[kh_slot(p)] = pack(mx_cell(cur.khu, cur.khe));
         __syncthreads();
         if (upd) {
             const Cell4 up = unpack(B[row * CLW + lane + 1]);
             const Cell4 dn = unpack(B[(row + 2) * CLW + lane + 1]);
             const Cell4 sd = unpack(B[(row + 1) * CLW + lane + (S ? 2 : 0)]);
-            const float en = S ? mx_update(c1, rr, c0, sd, up, dn, prev, n1, A.kc)
-                               : mx_update(c0, rr, c1, sd, up, dn, prev, n0, A.kc);
-            // the whole pair is written (full lines); the other cell's value is
-            // the one every reader of this pass sees
-            *reinterpret_cast<float2 *>(A.e + at(p)) = S ? make_float2(c0.e, en) : make_float2(en, c1.e);
+            const float en = S ? mx_update(c1, cur.r, c0, sd, up, dn, prev, n1, A.kc)
+                               : mx_update(c0, cur.r, c1, sd, up, dn, prev, n0, A.kc);
+            A.e[at_c(p)] = en;
         }
         prev = S ? c0 : c1;
         c0 = n0;
         c1 = n1;
-        nu = nu2;
-        ne = ne2;
-        rr = rr2;
-        khu = khu2;
-        khe = khe2;
         buf ^= 1;
     };
     for (int p = i0; p < i0 + A.chunk; p += 2) {
-        step(p, std::integral_constant<int, S0>{});
-        step(p + 1, std::integral_constant<int, 1 - S0>{});
+        step(p, std::integral_constant<int, S0>{}, ra, rb);
+        step(p + 1, std::integral_constant<int, 1 - S0>{}, rb, ra);
     }
 }
 
@@ -470,38 +485,65 @@ __global__ __launch_bounds__(kBlock) void k_mx_residual_restrict(const float *__
                                                                    const float *__restrict__ u,
                                                                    const float *__restrict__ r, int lg, MxConst kc,
                                                                    float *__restrict__ eb_c, float *__restrict__ u_c,
-                                                                   float *__restrict__ r_c)
+                                                                   float *__restrict__ r_c, bool split, bool split_c)
 {
     const int lgc = lg - 1;
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)), I = (int)(t >> (2 * lgc));
     float em, um, rm;
-    mx_restrict_block(e, u, r, I, J, K, lg, kc, em, um, rm);
-    eb_c[t] = em;
+    mx_restrict_block(e, u, r, I, J, K, lg, kc, em, um, rm, split);
+    const size_t tc = sx(I, J, K, lgc, split_c);
+    eb_c[tc] = em;
     u_c[t] = um;
-    r_c[t] = rm;
+    r_c[tc] = rm;
 }
 
 // r_c += N_c(eb); e_c = eb
 __global__ __launch_bounds__(kBlock) void k_mx_coarse_rhs(const float *__restrict__ eb, const float *__restrict__ u,
                                                             int lg, MxConst kc, float *__restrict__ rc,
-                                                            float *__restrict__ ec)
+                                                            float *__restrict__ ec, bool split)
 {
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int m = (1 << lg) - 1;
     const int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
-    rc[t] += mx_value_at(eb, u, i, j, k, lg, kc);
-    ec[t] = eb[t];
+    const size_t ts = sx(i, j, k, lg, split);
+    rc[ts] += mx_value_at(eb, u, i, j, k, lg, kc, split);
+    ec[ts] = eb[ts];
 }
 
 // one thread per coarse cell: its 8 daughters of the 2^lg mesh
 __global__ __launch_bounds__(kBlock) void k_mx_prolong_add(float *__restrict__ e, const float *__restrict__ ec,
-                                                             const float *__restrict__ eb, int lg, int mode)
+                                                             const float *__restrict__ eb, int lg, int mode, bool split,
+                                                             bool split_c)
 {
-    const int lgc = lg - 1;
+    const int lgc = lg - 1, m = (1 << lgc) - 1;
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)), I = (int)(t >> (2 * lgc));
-    prolong_block(e, ec, eb, I, J, K, lgc, mode);
+    auto d = [&](int i, int j, int k) {
+        const size_t q = sx(i, j, k, lgc, split_c);
+        return ec[q] - eb[q];
+    };
+    const float v0 = d(I, J, K);
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if (mode == 0) {
+        gx = d((I + 1) & m, J, K) - d((I - 1) & m, J, K);
+        gy = d(I, (J + 1) & m, K) - d(I, (J - 1) & m, K);
+        gz = d(I, J, (K + 1) & m) - d(I, J, (K - 1) & m);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                float v = v0;
+                if (mode == 0) {
+                    v += (a ? 0.125f : -0.125f) * gx;
+                    v += (b ? 0.125f : -0.125f) * gy;
+                    v += (c ? 0.125f : -0.125f) * gz;
+                }
+                e[sx(2 * I + a, 2 * J + b, 2 * K + c, lg, split)] += v;
+            }
 }
 
 struct MxTail {
@@ -574,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_mx_outer_residual(const double *__re
                                                                 const double *__restrict__ f, int lg, OpConst kc,
                                                                 float *__restrict__ r32, float *__restrict__ u32,
                                                                 float *__restrict__ e32,
-                                                                double *__restrict__ partial, int nparts)
+                                                                double *__restrict__ partial, int nparts, bool split)
 {
     __shared__ double sh[2 * kBlock / 64];
     const int lgc = lg - 1;
@@ -593,9 +635,10 @@ __global__ __launch_bounds__(kBlock) void k_mx_outer_residual(const double *__re
                 for (int c = 0; c < 2; ++c) {
                     const size_t cc = ix(2 * I + a, 2 * J + b, 2 * K + c, lg);
                     const double r = br.r[(a * 2 + b) * 2 + c];
-                    r32[cc] = (float)r;
+                    const size_t cs = sx(2 * I + a, 2 * J + b, 2 * K + c, lg, split);
+                    r32[cs] = (float)r;
                     u32[cc] = (float)u[cc];
-                    e32[cc] = 0.0f;
+                    e32[cs] = 0.0f;
                     mx = nanmax_d(mx, fabs(r));
                     sm += r * r;
                 }
@@ -620,10 +663,145 @@ __global__ __launch_bounds__(kBlock) void k_mx_outer_residual(const double *__re
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_mx_update(double *__restrict__ u, const float *__restrict__ e, size_t n)
+// Float64 outer step of the mixed solve on a level-0 mesh with N >= 64:
+// v = u + e (ADD_E) or v = u, then r = f - L(v) at every cell.  Same plane
+// march as the colour pass: workgroups of RTJ rows of a 64-cell row tile plus
+// a halo row on each side (one wave per row, one cell per lane); v and e^v of
+// a plane are staged in LDS, so every exponential is evaluated once per cell
+// (plus the halo).  Writes v (ADD_E: into the second buffer uout), r and v as
+// float32 for the inner cycle, and per-workgroup max|r| and sum r^2.  Every
+// wave issues the same loads in every plane (see k_mx_colour).
+constexpr int RTJ = 8, RTK = 64, RLW = RTK + 2;
+
+struct CorrArgs {
+    const double *u, *f;
+    const float *e;
+    double *uout;
+    float *r32, *u32;
+    int lg, chunk, nunits;
+    bool split;
+    OpConst kc;
+    double *partial;
+    int nparts;
+};
+
+template <bool ADD_E>
+__global__ __launch_bounds__(64 * (RTJ + 2)) void k_mx_correct_residual(CorrArgs A)
 {
-    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock)
-        u[t] += (double)e[t];
+    __shared__ double2 sB[2 * (RTJ + 2) * RLW];
+    __shared__ double red[2 * (RTJ + 2)];
+    const int lg = A.lg, m = (1 << lg) - 1;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int row = wv - 1;
+    const bool upd = row >= 0 && row < RTJ;
+    const size_t plane = (size_t)1 << (2 * lg);
+    const int nkt = (1 << lg) / RTK, njt = (1 << lg) / RTJ;
+    // k-halo duty: lanes 0..2 RTJ - 1 of wave 0 serve row lane / 2, side lane & 1
+    const bool kh = wv == 0 && lane < 2 * RTJ;
+    const int khq = (lane & (2 * RTJ - 1)) >> 1, khs = lane & 1;
+    double mx = 0.0, sm = 0.0;
+    for (int unit = blockIdx.x; unit < A.nunits; unit += gridDim.x) {
+        const int kt = unit % nkt, jt = (unit / nkt) % njt, it = unit / (nkt * njt);
+        const int k0 = kt * RTK, j0 = jt * RTJ, i0 = it * A.chunk;
+        const int jg = (j0 + row) & m, k = k0 + lane;
+        const size_t rowoff = ((size_t)jg << lg) + (size_t)k;
+        const int khj = (j0 + khq) & m, khk = khs ? ((k0 + RTK) & m) : ((k0 - 1) & m);
+        const size_t khoff = ((size_t)khj << lg) + (size_t)khk;
+        auto eidx = [&](int pl, size_t off, int j, int kk) {
+            return (size_t)(pl & m) * plane +
+                   (A.split ? (((size_t)j << lg) + ((size_t)(((pl & m) + j + kk) & 1) << (lg - 1)) + (size_t)(kk >> 1))
+                            : off);
+        };
+        auto vload = [&](int pl, size_t off, int j, int kk) {
+            double v = A.u[(size_t)(pl & m) * plane + off];
+            if (ADD_E) v += (double)A.e[eidx(pl, off, j, kk)];
+            return v;
+        };
+        // raw loads of step p (u and e kept apart: they are summed where used,
+        // so that no arithmetic on a load in flight sits at the loop latch)
+        struct Raw {
+            double u, f, ku;
+            float e, ke;
+        };
+        auto load = [&](int p) {
+            Raw w;
+            w.u = A.u[(size_t)((p + 1) & m) * plane + rowoff];
+            w.e = ADD_E ? A.e[eidx(p + 1, rowoff, jg, k)] : 0.f;
+            w.f = A.f[(size_t)(p & m) * plane + rowoff];  // halo rows: loaded, not used
+            w.ku = A.u[(size_t)(p & m) * plane + khoff];
+            w.ke = ADD_E ? A.e[eidx(p, khoff, khj, khk)] : 0.f;
+            return w;
+        };
+        double vm = vload(i0 - 1, rowoff, jg, k), vc = vload(i0, rowoff, jg, k);
+        double Em = exp(vm), Ec = exp(vc);
+        Raw ra = load(i0), rb;
+        int buf = 0;
+        auto step = [&](int p, const Raw &cur, Raw &nxt) {
+            nxt = load(p + 1);
+            const double vp = cur.u + (double)cur.e, Ep = exp(vp);
+            double2 *B = sB + buf * (RTJ + 2) * RLW;
+            B[(row + 1) * RLW + lane + 1] = make_double2(vc, Ec);
+            if (kh) {
+                const double kv = cur.ku + (double)cur.ke;
+                B[(khq + 1) * RLW + (khs ? RLW - 1 : 0)] = make_double2(kv, exp(kv));
+            }
+            __syncthreads();
+            if (upd) {
+                const double2 a = B[row * RLW + lane + 1], b = B[(row + 2) * RLW + lane + 1];
+                const double2 c = B[(row + 1) * RLW + lane], d = B[(row + 1) * RLW + lane + 2];
+                const double d0 = vp - vc, d1 = vm - vc, d2 = b.x - vc, d3 = a.x - vc, d4 = d.x - vc, d5 = c.x - vc;
+                const double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
+                const double S3 = ((Ep * d0 + Em * d1) + (b.y * d2 + a.y * d3)) + (d.y * d4 + c.y * d5);
+                const double L = A.kc.ih2 * 0.5 * (S3 + Ec * S1) + A.kc.bC * expm1(-A.kc.q * vc);
+                const double r = cur.f - L;
+                const size_t o = (size_t)(p & m) * plane + rowoff;
+                if (ADD_E) A.uout[o] = vc;
+                A.u32[o] = (float)vc;
+                A.r32[A.split ? (size_t)(p & m) * plane + ((size_t)jg << lg) + ((size_t)(((p & m) + jg + k) & 1) << (lg - 1)) + (size_t)(k >> 1) : o] = (float)r;
+                mx = nanmax_d(mx, fabs(r));
+                sm += r * r;
+            }
+            vm = vc;
+            Em = Ec;
+            vc = vp;
+            Ec = Ep;
+            buf ^= 1;
+        };
+        for (int p = i0; p < i0 + A.chunk; p += 2) {
+            step(p, ra, rb);
+            step(p + 1, rb, ra);
+        }
+        __syncthreads();  // the next unit reuses the LDS buffers
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = nanmax_d(mx, __shfl_xor(mx, o, 64));
+        sm += __shfl_xor(sm, o, 64);
+    }
+    if (lane == 0) {
+        red[wv] = mx;
+        red[RTJ + 2 + wv] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < RTJ + 2; ++w) {
+            mx = nanmax_d(mx, red[w]);
+            sm += red[RTJ + 2 + w];
+        }
+        A.partial[blockIdx.x] = mx;
+        A.partial[A.nparts + blockIdx.x] = sm;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mx_update(double *__restrict__ u, const float *__restrict__ e, int lg,
+                                                        bool split)
+{
+    const size_t n = (size_t)1 << (3 * lg);
+    const int m = (1 << lg) - 1;
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock) {
+        const int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
+        u[t] += (double)e[sx(i, j, k, lg, split)];
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_mx_final(const double *__restrict__ partial, int nparts,
@@ -661,6 +839,9 @@ MxConst mx_const(const mgfr_ctx *c, int l)
     return MxConst{(float)(1.0 / (c->lev[l].h * c->lev[l].h)), (float)c->bC, (float)c->q, (float)c->p.max_du};
 }
 
+// Levels swept by the one-colour pass kernel store e, r and ebar split by colour.
+static bool split_level(const mgfr_ctx *c, int l) { return c->colour32_min_n > 0 && c->lev[l].N >= c->colour32_min_n; }
+
 // Per-launch timing of the finest level's sweep kernels: a pair of events
 // around each launch (read back by collect_timing).
 static int timer_slot(mgfr_ctx *c, bool timed, int &slot)
@@ -691,7 +872,7 @@ int mx_launch_sweeps(mgfr_ctx *c, int l, int sweeps, bool timed)
     Level &L = c->lev[l];
     const MxConst kc = mx_const(c, l);
     const size_t half = (size_t)1 << (3 * L.lg - 1);
-    const bool colour_pass = c->colour32_min_n > 0 && L.N >= c->colour32_min_n;
+    const bool colour_pass = split_level(c, l);
     int slot, rc;
     for (int s = 0; s < sweeps; ++s) {
         if (colour_pass) {
@@ -748,12 +929,14 @@ int mx_vcycle(mgfr_ctx *c, int l)
     if ((rc = mx_launch_sweeps(c, l, c->p.pre_smooth, l == 0 && c->timing))) return rc;
     Level &Lc = c->lev[l + 1];
     const size_t nc = (size_t)1 << (3 * Lc.lg);
+    const bool sf = split_level(c, l), sc = split_level(c, l + 1);
     k_mx_residual_restrict<<<nb(nc), kBlock, 0, c->stream>>>(L.e32, L.u32, L.r32, L.lg, mx_const(c, l), Lc.ebar32,
-                                                             Lc.u32, Lc.r32);
-    k_mx_coarse_rhs<<<nb(nc), kBlock, 0, c->stream>>>(Lc.ebar32, Lc.u32, Lc.lg, mx_const(c, l + 1), Lc.r32, Lc.e32);
+                                                             Lc.u32, Lc.r32, sf, sc);
+    k_mx_coarse_rhs<<<nb(nc), kBlock, 0, c->stream>>>(Lc.ebar32, Lc.u32, Lc.lg, mx_const(c, l + 1), Lc.r32, Lc.e32,
+                                                      sc);
     MGFR_HIP(hipGetLastError());
     if ((rc = mx_vcycle(c, l + 1))) return rc;
-    k_mx_prolong_add<<<nb(nc), kBlock, 0, c->stream>>>(L.e32, Lc.e32, Lc.ebar32, L.lg, c->p.prolong);
+    k_mx_prolong_add<<<nb(nc), kBlock, 0, c->stream>>>(L.e32, Lc.e32, Lc.ebar32, L.lg, c->p.prolong, sf, sc);
     MGFR_HIP(hipGetLastError());
     return mx_launch_sweeps(c, l, c->p.post_smooth, l == 0 && c->timing);
 }
@@ -781,8 +964,53 @@ static int outer_residual(mgfr_ctx *c, double *rmax, double *rsq)
     const size_t nblk = (size_t)1 << (3 * (L0.lg - 1));
     const unsigned g = (unsigned)std::min<size_t>(nb(nblk), (size_t)c->nparts);
     k_mx_outer_residual<<<g, kBlock, 0, c->stream>>>(L0.u, L0.f, L0.lg, level_const(c, 0), L0.r32, L0.u32, L0.e32,
-                                                      c->partial, (int)g);
+                                                      c->partial, (int)g, split_level(c, 0));
     k_mx_final<<<1, 1024, 0, c->stream>>>(c->partial, (int)g, c->dscal);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipMemcpyAsync(c->hscal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    MGFR_HIP(hipStreamSynchronize(c->stream));
+    *rmax = c->hscal[0];
+    *rsq = c->hscal[1];
+    return MGFR_OK;
+}
+
+// Outer step: (add_e) u <- u + e, then the float64 residual of u, the inner
+// problem's float32 arrays and e = 0; returns max|r| and sum r^2 on the host.
+// On meshes with N >= 64 one plane-marching kernel does both (the new iterate
+// goes to the second level-0 buffer, which then becomes the current one).
+static int outer_step(mgfr_ctx *c, bool add_e, double *rmax, double *rsq)
+{
+    Level &L0 = c->lev[0];
+    const size_t n = (size_t)L0.N * L0.N * L0.N;
+    if (L0.N < RTK || L0.alt == nullptr) {
+        if (add_e)
+            k_mx_update<<<(unsigned)std::min<size_t>(nb(n), 8192), kBlock, 0, c->stream>>>(L0.u, L0.e32, L0.lg,
+                                                                                            split_level(c, 0));
+        MGFR_HIP(hipGetLastError());
+        return outer_residual(c, rmax, rsq);
+    }
+    CorrArgs A;
+    A.u = L0.u;
+    A.f = L0.f;
+    A.e = L0.e32;
+    A.uout = add_e ? L0.alt : nullptr;
+    A.r32 = L0.r32;
+    A.u32 = L0.u32;
+    A.lg = L0.lg;
+    A.chunk = L0.N / 8;
+    A.nunits = (L0.N / RTK) * (L0.N / RTJ) * 8;
+    A.split = split_level(c, 0);
+    A.kc = level_const(c, 0);
+    A.partial = c->partial;
+    const int g = std::min(A.nunits, c->nparts);
+    A.nparts = g;
+    if (add_e)
+        k_mx_correct_residual<true><<<g, 64 * (RTJ + 2), 0, c->stream>>>(A);
+    else
+        k_mx_correct_residual<false><<<g, 64 * (RTJ + 2), 0, c->stream>>>(A);
+    if (add_e) std::swap(L0.u, L0.alt);
+    MGFR_HIP(hipMemsetAsync(L0.e32, 0, n * sizeof(float), c->stream));
+    k_mx_final<<<1, 1024, 0, c->stream>>>(c->partial, g, c->dscal);
     MGFR_HIP(hipGetLastError());
     MGFR_HIP(hipMemcpyAsync(c->hscal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     MGFR_HIP(hipStreamSynchronize(c->stream));
@@ -797,14 +1025,16 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
     const size_t n = (size_t)L0.N * L0.N * L0.N;
     const double ncell = (double)n;
     double rmax, rsq;
-    int rc = outer_residual(c, &rmax, &rsq);
+    int rc = outer_step(c, false, &rmax, &rsq);
     if (rc) return rc;
     double res = rmax / D, prev = res;
     st->res0 = res;
     int it = 0, grow = 0, status;
     for (;;) {
         if (!std::isfinite(res) || grow >= 3) {
-            // fall back: plain float64 solve from u = 0
+            // fall back: plain float64 solve from u = 0 (in the caller's array)
+            L0.u = u;
+            L0.alt = c->alt0;
             MGFR_HIP(hipMemsetAsync(u, 0, n * sizeof(double), c->stream));
             st->fell_back = 1;
             const int outer = it;
@@ -815,9 +1045,7 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
         if (res <= c->p.tol) { status = MGFR_OK; break; }
         if (it >= c->p.max_vcycles) { status = MGFR_NOT_CONVERGED; break; }
         if ((rc = mx_vcycle(c, 0))) return rc;
-        k_mx_update<<<(unsigned)std::min<size_t>(nb(n), 8192), kBlock, 0, c->stream>>>(u, L0.e32, n);
-        MGFR_HIP(hipGetLastError());
-        if ((rc = outer_residual(c, &rmax, &rsq))) return rc;
+        if ((rc = outer_step(c, true, &rmax, &rsq))) return rc;
         if (c->timing && (rc = collect_timing(c, st))) return rc;
         prev = res;
         res = rmax / D;

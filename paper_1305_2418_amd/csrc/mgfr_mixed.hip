@@ -404,8 +404,9 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         c1 = mx_cell(u0.y, e0.y);
         prev = S0 ? mx_cell(um.y, em.y) : mx_cell(um.x, em.x);
     }
-    // raw loads of step p: u, e of plane p + 1, r of plane p, the k-halo cell of plane p;
-    // two sets alternate so that no register holding a load in flight is copied
+    // raw loads of step p: u, e of plane p + 1, r of plane p, the k-halo cell of plane p.
+    // They are issued two steps ahead; four register sets rotate with the
+    // four-plane loop body, so that no register holding a load in flight is copied.
     struct Raw {
         float2 u, e;
         float r, khu, khe;
@@ -419,14 +420,14 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         w.khe = A.e[kh_e(p)];
         return w;
     };
-    Raw ra = load(i0), rb;
+    Raw ra = load(i0), rb = load(i0 + 1), rc, rd;
     int buf = 0;
 
-    // one plane with updated column S: consume cur (step p), load nxt (step p + 1)
+    // one plane with updated column S: consume cur (step p), load nxt (step p + 2)
     auto step = [&](int p, auto Sc, const Raw &cur, Raw &nxt) {
         constexpr int S = decltype(Sc)::value;
-        nxt = load(p + 1);
-        // plane p + 1 from the raw values loaded one plane ago
+        nxt = load(p + 2);
+        // plane p + 1 from the raw values loaded two planes ago
         const Cell4 n0 = mx_cell(cur.u.x, cur.e.x), n1 = mx_cell(cur.u.y, cur.e.y);
         float4 *B = sB + buf * (CTJ + 2) * CLW;
         B[(row + 1) * CLW + lane + 1] = pack(S ? c0 : c1);
@@ -445,9 +446,13 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         c1 = n1;
         buf ^= 1;
     };
-    for (int p = i0; p < i0 + A.chunk; p += 2) {
-        step(p, std::integral_constant<int, S0>{}, ra, rb);
-        step(p + 1, std::integral_constant<int, 1 - S0>{}, rb, ra);
+    using Z0 = std::integral_constant<int, S0>;
+    using Z1 = std::integral_constant<int, 1 - S0>;
+    for (int p = i0; p < i0 + A.chunk; p += 4) {  // chunk is a multiple of 4
+        step(p, Z0{}, ra, rc);
+        step(p + 1, Z1{}, rb, rd);
+        step(p + 2, Z0{}, rc, ra);
+        step(p + 3, Z1{}, rd, rb);
     }
 }
 
@@ -470,6 +475,154 @@ __global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour(ColourArgs A)
         mx_colour_rows<1>(A, i0, j0, k0, wv, lane, sB);
     else
         mx_colour_rows<0>(A, i0, j0, k0, wv, lane, sB);
+}
+
+// ------------------------------------------------- restriction pass (N >= 128)
+//
+// Residual restriction from a split level with N >= 128 to the next coarser
+// level: for every coarse cell the means of e, u and r - N(e) over its eight
+// daughters.  Same workgroups and plane march as the colour pass, but both
+// cells of a lane's pair need N(e), so both are published in LDS and the
+// k-halo holds both ends of every row.  The daughter sums run over the pair
+// (lane), the row pair (adjacent waves, combined in LDS) and the plane pair
+// (two consecutive steps).
+
+__device__ __forceinline__ float mx_nval(const Cell4 &c, const Cell4 &n0, const Cell4 &n1, const Cell4 &n2,
+                                         const Cell4 &n3, const Cell4 &n4, const Cell4 &n5, const MxConst &k)
+{
+    float Su = 0.f, Se = 0.f, A = 0.f, B = 0.f;
+    auto add = [&](const Cell4 &n) {
+        const float du = n.u - c.u, de = n.e - c.e;
+        Su += du;
+        Se += de;
+        A = fmaf(n.P, du, A);
+        B = fmaf(n.W, de, B);
+    };
+    add(n0);
+    add(n1);
+    add(n2);
+    add(n3);
+    add(n4);
+    add(n5);
+    const float flux = 0.5f * ((A + c.P * Su) + (B + c.W * Se));
+    return k.ih2 * flux + k.bC * fexp(-k.q * c.u) * fexpm1(-k.q * c.e);
+}
+
+struct RestrictArgs {
+    const float *e, *u, *r;
+    float *ebc, *uc, *rc;
+    int lg, chunk;
+    bool split_c;
+    MxConst kc;
+};
+
+__global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_restrict_pass(RestrictArgs A)
+{
+    __shared__ float4 sB[2 * (CTJ + 2) * CLW * 2];  // [buffer][row][slot][column]
+    __shared__ float4 sR[CTJ / 2][64];               // odd rows' daughter sums
+    const int lg = A.lg, m = (1 << lg) - 1, lgc = lg - 1;
+    const size_t hN = (size_t)1 << (lg - 1);
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned L = (b & 7u) * (nb >> 3) + (b >> 3);
+    const int nkt = (1 << lg) / CKW, njt = (1 << lg) / CTJ;
+    const int kt = (int)(L % (unsigned)nkt), jt = (int)((L / (unsigned)nkt) % (unsigned)njt),
+              it = (int)(L / ((unsigned)nkt * (unsigned)njt));
+    const int k0 = kt * CKW, j0 = jt * CTJ, i0 = it * A.chunk;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int row = wv - 1;
+    const bool upd = row >= 0 && row < CTJ;
+    const int jg = (j0 + row) & m;
+    const size_t plane = (size_t)1 << (2 * lg);
+    const size_t rowbase = (size_t)jg << lg;
+    const size_t kk = (size_t)(k0 + 2 * lane), kh2 = (size_t)(k0 / 2 + lane);
+    auto pb = [&](int pl) { return (size_t)(pl & m) * plane + rowbase; };
+    auto ld_split = [&](const float *a, int pl) {  // both cells of the pair from the two colour halves
+        const size_t q = pb(pl) + kh2;
+        const bool odd = ((pl + jg) & 1) != 0;
+        return make_float2(a[q + (odd ? hN : 0)], a[q + (odd ? 0 : hN)]);
+    };
+    // k-halo: lanes 0..2 CTJ - 1 of wave 0 serve row lane / 2, end lane & 1 (0: k0 - 1, 1: k0 + CKW)
+    const bool kh = wv == 0 && lane < 2 * CTJ;
+    const int khq = (lane & (2 * CTJ - 1)) >> 1, khs = lane & 1;
+    const int khj = (j0 + khq) & m, khk = khs ? ((k0 + CKW) & m) : ((k0 - 1) & m);
+    auto kh_u = [&](int pl) { return (size_t)(pl & m) * plane + ((size_t)khj << lg) + (size_t)khk; };
+    auto kh_e = [&](int pl) {
+        return (size_t)(pl & m) * plane + ((size_t)khj << lg) + ((size_t)(((pl & m) + khj + khk) & 1) << (lg - 1)) +
+               (size_t)(khk >> 1);
+    };
+    auto slot = [&](int r, int l, int col) { return ((r + 1) * CLW + l + 1) * 2 + col; };
+
+    Cell4 p0, p1, c0, c1;
+    {
+        const float2 um = *reinterpret_cast<const float2 *>(A.u + pb(i0 - 1) + kk), em = ld_split(A.e, i0 - 1);
+        const float2 u0 = *reinterpret_cast<const float2 *>(A.u + pb(i0) + kk), e0 = ld_split(A.e, i0);
+        p0 = mx_cell(um.x, em.x);
+        p1 = mx_cell(um.y, em.y);
+        c0 = mx_cell(u0.x, e0.x);
+        c1 = mx_cell(u0.y, e0.y);
+    }
+    // raw loads of step p: u, e of plane p + 1; r and the k-halo cell of plane p
+    struct Raw {
+        float2 u, e, r;
+        float khu, khe;
+    };
+    auto load = [&](int p) {
+        Raw w;
+        w.u = *reinterpret_cast<const float2 *>(A.u + pb(p + 1) + kk);
+        w.e = ld_split(A.e, p + 1);
+        w.r = ld_split(A.r, p);  // halo rows: loaded, not used
+        w.khu = A.u[kh_u(p)];
+        w.khe = A.e[kh_e(p)];
+        return w;
+    };
+    Raw ra = load(i0), rb;  // issued one step ahead (more would cost occupancy here)
+    int buf = 0;
+    float se = 0.f, su = 0.f, sr = 0.f;
+    auto step = [&](int p, bool second, const Raw &cur, Raw &nxt) {
+        nxt = load(p + 1);
+        const Cell4 n0 = mx_cell(cur.u.x, cur.e.x), n1 = mx_cell(cur.u.y, cur.e.y);
+        float4 *B = sB + buf * (CTJ + 2) * CLW * 2;
+        B[slot(row, lane, 0)] = pack(c0);
+        B[slot(row, lane, 1)] = pack(c1);
+        if (kh) B[khs ? slot(khq, CKW / 2, 0) : slot(khq, -1, 1)] = pack(mx_cell(cur.khu, cur.khe));
+        __syncthreads();
+        if (upd) {
+            const Cell4 up0 = unpack(B[slot(row - 1, lane, 0)]), up1 = unpack(B[slot(row - 1, lane, 1)]);
+            const Cell4 dn0 = unpack(B[slot(row + 1, lane, 0)]), dn1 = unpack(B[slot(row + 1, lane, 1)]);
+            const Cell4 lf = unpack(B[slot(row, lane - 1, 1)]), rt = unpack(B[slot(row, lane + 1, 0)]);
+            const float N0 = mx_nval(c0, p0, n0, up0, dn0, lf, c1, A.kc);
+            const float N1 = mx_nval(c1, p1, n1, up1, dn1, c0, rt, A.kc);
+            se += c0.e + c1.e;
+            su += c0.u + c1.u;
+            sr += (cur.r.x - N0) + (cur.r.y - N1);
+        }
+        if (second) {
+            if (upd && (row & 1)) sR[row >> 1][lane] = make_float4(se, su, sr, 0.f);
+            __syncthreads();
+            if (upd && !(row & 1)) {
+                const float4 o = sR[row >> 1][lane];
+                const int I = (p & m) >> 1, J = jg >> 1, K = k0 / 2 + lane;
+                const size_t nat = ((((size_t)I << lgc) + (size_t)J) << lgc) + (size_t)K;
+                const size_t spl = A.split_c ? ((((size_t)I << lgc) + (size_t)J) << lgc) +
+                                                   ((size_t)((I + J + K) & 1) << (lgc - 1)) + (size_t)(K >> 1)
+                                             : nat;
+                A.ebc[spl] = 0.125f * (se + o.x);
+                A.uc[nat] = 0.125f * (su + o.y);
+                A.rc[spl] = 0.125f * (sr + o.z);
+            }
+            se = su = sr = 0.f;
+        }
+        p0 = c0;
+        p1 = c1;
+        c0 = n0;
+        c1 = n1;
+        buf ^= 1;
+    };
+    for (int p = i0; p < i0 + A.chunk; p += 2) {
+        step(p, false, ra, rb);
+        step(p + 1, true, rb, ra);
+    }
 }
 
 // ------------------------------------------------------------------- kernels
@@ -735,10 +888,10 @@ __global__ __launch_bounds__(64 * (RTJ + 2)) void k_mx_correct_residual(CorrArgs
         };
         double vm = vload(i0 - 1, rowoff, jg, k), vc = vload(i0, rowoff, jg, k);
         double Em = exp(vm), Ec = exp(vc);
-        Raw ra = load(i0), rb;
+        Raw ra = load(i0), rb = load(i0 + 1), rc, rd;  // issued two steps ahead (see k_mx_colour)
         int buf = 0;
         auto step = [&](int p, const Raw &cur, Raw &nxt) {
-            nxt = load(p + 1);
+            nxt = load(p + 2);
             const double vp = cur.u + (double)cur.e, Ep = exp(vp);
             double2 *B = sB + buf * (RTJ + 2) * RLW;
             B[(row + 1) * RLW + lane + 1] = make_double2(vc, Ec);
@@ -768,9 +921,11 @@ __global__ __launch_bounds__(64 * (RTJ + 2)) void k_mx_correct_residual(CorrArgs
             Ec = Ep;
             buf ^= 1;
         };
-        for (int p = i0; p < i0 + A.chunk; p += 2) {
-            step(p, ra, rb);
-            step(p + 1, rb, ra);
+        for (int p = i0; p < i0 + A.chunk; p += 4) {
+            step(p, ra, rc);
+            step(p + 1, rb, rd);
+            step(p + 2, rc, ra);
+            step(p + 3, rd, rb);
         }
         __syncthreads();  // the next unit reuses the LDS buffers
     }
@@ -930,8 +1085,15 @@ int mx_vcycle(mgfr_ctx *c, int l)
     Level &Lc = c->lev[l + 1];
     const size_t nc = (size_t)1 << (3 * Lc.lg);
     const bool sf = split_level(c, l), sc = split_level(c, l + 1);
-    k_mx_residual_restrict<<<nb(nc), kBlock, 0, c->stream>>>(L.e32, L.u32, L.r32, L.lg, mx_const(c, l), Lc.ebar32,
-                                                             Lc.u32, Lc.r32, sf, sc);
+    if (sf && L.N >= CKW) {
+        const int chunk = L.N / 8;
+        const unsigned nbk = (unsigned)((L.N / CKW) * (L.N / CTJ) * (L.N / chunk));
+        k_mx_restrict_pass<<<nbk, 64 * (CTJ + 2), 0, c->stream>>>(
+            RestrictArgs{L.e32, L.u32, L.r32, Lc.ebar32, Lc.u32, Lc.r32, L.lg, chunk, sc, mx_const(c, l)});
+    } else {
+        k_mx_residual_restrict<<<nb(nc), kBlock, 0, c->stream>>>(L.e32, L.u32, L.r32, L.lg, mx_const(c, l),
+                                                                 Lc.ebar32, Lc.u32, Lc.r32, sf, sc);
+    }
     k_mx_coarse_rhs<<<nb(nc), kBlock, 0, c->stream>>>(Lc.ebar32, Lc.u32, Lc.lg, mx_const(c, l + 1), Lc.r32, Lc.e32,
                                                       sc);
     MGFR_HIP(hipGetLastError());

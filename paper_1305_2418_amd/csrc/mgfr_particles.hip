@@ -212,8 +212,26 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const double *__restric
         return;
     }
     const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
-    const int ii[2] = {i0, (i0 + 1) & mask}, jj[2] = {j0, (j0 + 1) & mask}, kk[2] = {k0, (k0 + 1) & mask};
+    // the 32 distinct cells the eight central differences need: the 2x2x2
+    // block B and one layer beyond it on each side along each axis
+    const int ix4[4] = {(i0 - 1) & mask, i0, (i0 + 1) & mask, (i0 + 2) & mask};
+    const int jx4[4] = {(j0 - 1) & mask, j0, (j0 + 1) & mask, (j0 + 2) & mask};
+    const int kx4[4] = {(k0 - 1) & mask, k0, (k0 + 1) & mask, (k0 + 2) & mask};
     auto at = [&](int i, int j, int k) { return fr[((((size_t)i << lg) + j) << lg) + k]; };
+    double B[2][2][2], X[2][2][2], Y[2][2][2], Z[2][2][2];  // X[s][b][c]: x layer s (0: i0-1, 1: i0+2)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) B[a][b][c] = at(ix4[a + 1], jx4[b + 1], kx4[c + 1]);
+            X[0][a][b] = at(ix4[0], jx4[a + 1], kx4[b + 1]);
+            X[1][a][b] = at(ix4[3], jx4[a + 1], kx4[b + 1]);
+            Y[0][a][b] = at(ix4[a + 1], jx4[0], kx4[b + 1]);
+            Y[1][a][b] = at(ix4[a + 1], jx4[3], kx4[b + 1]);
+            Z[0][a][b] = at(ix4[a + 1], jx4[b + 1], kx4[0]);
+            Z[1][a][b] = at(ix4[a + 1], jx4[b + 1], kx4[3]);
+        }
     double gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -221,11 +239,14 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const double *__restric
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const int i = ii[a], j = jj[b], k = kk[c];
                 const double w = wx[a] * wy[b] * wz[c];
-                gx += w * (at((i + 1) & mask, j, k) - at((i - 1) & mask, j, k));
-                gy += w * (at(i, (j + 1) & mask, k) - at(i, (j - 1) & mask, k));
-                gz += w * (at(i, j, (k + 1) & mask) - at(i, j, (k - 1) & mask));
+                // f at +d and -d of block cell (a,b,c)
+                const double xp = a ? X[1][b][c] : B[1][b][c], xm = a ? B[0][b][c] : X[0][b][c];
+                const double yp = b ? Y[1][a][c] : B[a][1][c], ym = b ? B[a][0][c] : Y[0][a][c];
+                const double zp = c ? Z[1][a][b] : B[a][b][1], zm = c ? B[a][b][0] : Z[0][a][b];
+                gx += w * (xp - xm);
+                gy += w * (yp - ym);
+                gz += w * (zp - zm);
             }
     const double s = pref / (2.0 * h);
     acc[3 * p + 0] = (float)(s * gx);

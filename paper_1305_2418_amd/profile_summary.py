@@ -62,7 +62,7 @@ def pmc(d, out, cmd):
     agg = _counters(d)
     lines = [f"# rocprofv3 counters (mean per dispatch)", f"# command: {cmd}", ""]
     for (k, c), v in sorted(agg.items(), key=lambda kv: (_short(kv[0][0]), kv[0][1])):
-        if any(s in k for s in list(SWEEPS) + [COPY, "k_mx_residual", "k_mx_prolong", "k_conv3d", "k_cic", "k_force"]):
+        if any(s in k for s in list(SWEEPS) + [COPY, "k_mx_correct", "k_mx_restrict", "k_mx_prolong", "k_conv3d", "k_cic", "k_force"]):
             lines.append(f"{_short(k):70s} {c:22s} n={len(v):5d} mean={sum(v) / len(v):.5g} max={max(v):.5g}")
     open(out, "w").write("\n".join(lines) + "\n")
 

@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-mesh", type=int, default=128)
     ap.add_argument("--workload", choices=["uniform", "amr"], default="uniform",
                     help="amr: 256^3 base + 2 block-refined levels on 256^3 particles with 50 NFW halos")
+    ap.add_argument("--also-a", default="0.5",
+                    help="comma-separated other scale factors at which mixed and mixed_nn are also timed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also stream 1 GiB through a plain elementwise kernel (reference for HBM counters)")
     return ap.parse_args()
@@ -89,14 +91,74 @@ def cpu_baseline(args, log):
                       f"{st.vcycles} V-cycles, single-threaded C oracle; {os.cpu_count()} host cpus seen"}
 
 
-def run_mode(mode, args, pos, dev, log):
+# The network's convolutions (input channels, output channels, level: 0 = S, 1 = S/2, 2 = S/4)
+NET_CONVS = [(16, 16, 0), (16, 16, 0), (16, 32, 1), (32, 32, 1), (32, 64, 2), (64, 64, 2),
+             (96, 32, 1), (32, 32, 1), (48, 16, 0), (16, 16, 0)]
+
+
+def net_forward_flops(S):
+    return sum(2 * 27 * ci * co * (S >> lev) ** 3 for ci, co, lev in NET_CONVS)
+
+
+def measure_mfma(N, dev, log):
+    """The network's forward pass on the N/4 mesh (its use in the warm start) timed with HIP events."""
+    import numpy as np
+    import torch
+    from paper_1305_2418_amd import mgfr
+    S = N // 4
+    net = mgfr.Net(seed=0, max_voxels=S ** 3)
+    net.set_params(np.load(WEIGHTS))
+    d = torch.randn((1, S, S, S), dtype=torch.float64, generator=torch.Generator().manual_seed(1)).to(dev)
+    cond = [(1.0, 1e-6)]
+    for _ in range(2):
+        net.predict(d, cond)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    a.record()
+    for _ in range(reps):
+        net.predict(d, cond)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    tf = net_forward_flops(S) / (ms * 1e-3) / 1e12
+    log(f"network forward at {S}^3: {ms:.3f} ms, {tf:.1f} TFLOP/s")
+    return {"kernel": f"k_conv3d (network forward, {S}^3, bf16 MFMA 16x16x32)", "ms": ms,
+            "flop": net_forward_flops(S), "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": tf / 2500.0}
+
+
+def measure_copy(dev, log):
+    """Achievable streaming bandwidth: bitwise NOT of 1 GiB into a second buffer, HIP events."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.int32, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        torch.bitwise_not(x, out=y)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    a.record()
+    for _ in range(reps):
+        torch.bitwise_not(x, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * (1 << 30) * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    log(f"streaming kernel: {gbs:.0f} GB/s")
+    del x, y
+    return gbs
+
+
+def run_mode(mode, args, pos, dev, log, a=None):
     import numpy as np
     import torch
     from paper_1305_2418_amd import mgfr
     N = args.mesh
+    a = args.a if a is None else a
     precision = mgfr.FP64 if mode == "fp64" else mgfr.MIXED
     nn_mode = mgfr.NN_COARSE if mode == "mixed_nn" else mgfr.NN_NONE
-    params = mgfr.Params(mesh=N, box=100.0, a=args.a, fr0_abs=args.fr0, tol=1e-8, precision=precision,
+    params = mgfr.Params(mesh=N, box=100.0, a=a, fr0_abs=args.fr0, tol=1e-8, precision=precision,
                          nn_mode=nn_mode, max_vcycles=100, pre_smooth=args.smooth, post_smooth=args.smooth,
                          prolong=prolong_code(args))
     solver = mgfr.Solver(params)
@@ -137,7 +199,7 @@ def run_mode(mode, args, pos, dev, log):
            "solve_cells_per_s": N ** 3 / (solve_ms * 1e-3), "vcycles": [s.vcycles for s in stats],
            "res": stats[-1].res, "fell_back": max(s.fell_back for s in stats), "nn_ms": stats[-1].t_nn_ms,
            "sweep_launch_ms": sweep_ms, "dfr_max": None}
-    log(f"[{mode}] step {ms:.2f} ms, solve {solve_ms:.2f} ms, V-cycles {out['vcycles']}, res {out['res']:.2e}, "
+    log(f"[{mode} a={a}] step {ms:.2f} ms, solve {solve_ms:.2f} ms, V-cycles {out['vcycles']}, res {out['res']:.2e}, "
         f"sweep launch {sweep_ms:.3f} ms, nn {out['nn_ms']:.2f} ms")
     del solver, net
     return out
@@ -221,6 +283,12 @@ def main():
     for mode in [m for m in args.compare.split(",") if m and m != args.mode] + [args.mode]:
         results[mode] = run_mode(mode, args, pos, dev, log)
     head = results[args.mode]
+    other_a = {}
+    for a in [float(x) for x in args.also_a.split(",") if x]:
+        if a != args.a:
+            other_a[str(a)] = {m: run_mode(m, args, pos, dev, log, a=a) for m in ("mixed", "mixed_nn")}
+    copy_gbs = measure_copy(dev, log)
+    mfma = measure_mfma(N, dev, log)
     # dominant kernel of the headline mode: the finest-level smoothing sweep
     if args.mode == "fp64":
         kernel, bpc = ("k_sweep_fused" if N >= 512 else "k_sweep_half (x2 per sweep)"), 24.0
@@ -257,10 +325,13 @@ def main():
                         f"cold start to 1e-8 with V({args.smooth},{args.smooth}), {args.prolong} prolongation, + fifth force",
             "mode": args.mode,
             "modes": results,
+            "modes_other_a": other_a,
         },
+        "mfma": mfma,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-                     "launch_ms": head["sweep_launch_ms"], "alg_bytes_per_launch": alg_bytes},
+                     "launch_ms": head["sweep_launch_ms"], "alg_bytes_per_launch": alg_bytes,
+                     "achievable_GBs": copy_gbs, "frac_of_achievable": achieved / copy_gbs},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, log)

@@ -58,7 +58,8 @@ extern "C" {
 #define MGFR_MIXED 1 /* float32 correction V-cycles inside a float64 defect-correction loop */
 
 #define MGFR_NN_NONE 0   /* initial guess = the u passed in */
-#define MGFR_NN_COARSE 1 /* initial guess from the learned network at the N/4 level */
+#define MGFR_NN_COARSE 1 /* initial guess from the learned network at the N/4 level, corrected
+                            on the coarse levels (mgfr_params.coarse_cycles) */
 
 #define MGFR_MAX_HIST 256
 
@@ -81,6 +82,10 @@ typedef struct mgfr_params {
     int precision;   /* MGFR_FP64 or MGFR_MIXED */
     int nn_mode;     /* MGFR_NN_NONE or MGFR_NN_COARSE */
     double max_du;   /* limit on |Newton step| per cell update; <= 0 disables the limit */
+    int coarse_cycles; /* MGFR_NN_COARSE only: V-cycles of the N/4 problem (from the network's
+                          prediction) and then of the N/2 problem (from the prolonged N/4 solution)
+                          before the prolonged N/2 solution starts the solve at N; 0 = prolong the
+                          prediction directly.  >= 0 */
 } mgfr_params;
 
 /* Per-solve report. */

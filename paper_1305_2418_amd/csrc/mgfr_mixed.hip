@@ -301,7 +301,10 @@ __device__ __forceinline__ float mx_prolong(const float *__restrict__ ec, const 
 // e, r and ebar of such a level are stored split by colour (see sx), so the
 // pass reads r and writes e of its half only: 12 B per cell.
 
-constexpr int CTJ = 8;    // updated rows per workgroup
+#ifndef MGFR_CTJ
+#define MGFR_CTJ 8
+#endif
+constexpr int CTJ = MGFR_CTJ;  // updated rows per workgroup (the last row tile may be partial)
 constexpr int CKW = 128;  // cells per row tile
 constexpr int CLW = 66;   // LDS row: 64 lanes and one halo slot on each side
 
@@ -366,10 +369,12 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
     const int lg = A.lg, m = (1 << lg) - 1;
     const size_t hN = (size_t)1 << (lg - 1);
     const int row = wv - 1;                      // -1 and CTJ: halo rows
-    const bool upd = row >= 0 && row < CTJ;      // uniform over the wave
+    const bool upd = row >= 0 && row < CTJ && j0 + row <= m;  // uniform over the wave
     const int jg = (j0 + row) & m;
     const size_t plane = (size_t)1 << (2 * lg);
     const size_t rowbase = (size_t)jg << lg;
+    // rows that update nothing load r of the tile's first row (already fetched)
+    const size_t rrowbase = upd ? rowbase : (size_t)j0 << lg;
     const size_t kk = (size_t)(k0 + 2 * lane), kh2 = (size_t)(k0 / 2 + lane);
     auto pb = [&](int pl) { return (size_t)(pl & m) * plane + rowbase; };
     // u in natural order; e and r split by colour (column 0 of plane pl lies in half (pl + jg) & 1)
@@ -380,11 +385,12 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         return make_float2(A.e[b + (odd ? hN : 0)], A.e[b + (odd ? 0 : hN)]);
     };
     auto at_c = [&](int pl) { return pb(pl) + (size_t)A.colour * hN + kh2; };  // the updated cell's slot
+    auto at_r = [&](int pl) { return (size_t)(pl & m) * plane + rrowbase + (size_t)A.colour * hN + kh2; };
     // k-halo duty: lanes 0..CTJ-1 of the upper halo wave serve row `lane`.  Every
     // lane of every wave issues the same loads in every plane (lane mod CTJ), so
     // that no load sits under a branch and the prefetch waits stay exact.
     const bool kh = wv == 0 && lane < CTJ;
-    const int khq = lane & (CTJ - 1);
+    const int khq = lane % CTJ;
     const size_t khrow = (size_t)((j0 + khq) & m) << lg;
     const int khpar = (A.colour + j0 + khq) & 1;  // updated column of that row in even planes
     auto kh_k = [&](int pl) { return (khpar ^ (pl & 1)) ? ((k0 + CKW) & m) : ((k0 - 1) & m); };
@@ -415,7 +421,7 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         Raw w;
         w.u = ldu(p + 1);
         w.e = lde(p + 1);
-        w.r = A.r[at_c(p)];  // halo rows: loaded, not used
+        w.r = A.r[at_r(p)];
         w.khu = A.u[kh_u(p)];
         w.khe = A.e[kh_e(p)];
         return w;
@@ -456,7 +462,7 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
     }
 }
 
-// grid: 1-D, (N / CKW) (N / CTJ) (N / chunk) workgroups, spread so that
+// grid: 1-D, (N / CKW) ceil(N / CTJ) (N / chunk) workgroups, spread so that
 // workgroups adjacent in j run on the same XCD (they share halo rows)
 __global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour(ColourArgs A)
 {
@@ -464,7 +470,7 @@ __global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour(ColourArgs A)
     const int lg = A.lg;
     const unsigned nb = gridDim.x, b = blockIdx.x;
     const unsigned L = (b & 7u) * (nb >> 3) + (b >> 3);  // nb is a multiple of 8
-    const int nkt = (1 << lg) / CKW, njt = (1 << lg) / CTJ;
+    const int nkt = (1 << lg) / CKW, njt = ((1 << lg) + CTJ - 1) / CTJ;
     const int kt = (int)(L % (unsigned)nkt), jt = (int)((L / (unsigned)nkt) % (unsigned)njt),
               it = (int)(L / ((unsigned)nkt * (unsigned)njt));
     const int k0 = kt * CKW, j0 = jt * CTJ, i0 = it * A.chunk;
@@ -508,6 +514,8 @@ __device__ __forceinline__ float mx_nval(const Cell4 &c, const Cell4 &n0, const 
     return k.ih2 * flux + k.bC * fexp(-k.q * c.u) * fexpm1(-k.q * c.e);
 }
 
+constexpr int PTJ = 8;  // fine rows per workgroup (even: rows pair up)
+
 struct RestrictArgs {
     const float *e, *u, *r;
     float *ebc, *uc, *rc;
@@ -516,22 +524,22 @@ struct RestrictArgs {
     MxConst kc;
 };
 
-__global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_restrict_pass(RestrictArgs A)
+__global__ __launch_bounds__(64 * (PTJ + 2)) void k_mx_restrict_pass(RestrictArgs A)
 {
-    __shared__ float4 sB[2 * (CTJ + 2) * CLW * 2];  // [buffer][row][slot][column]
-    __shared__ float4 sR[CTJ / 2][64];               // odd rows' daughter sums
+    __shared__ float4 sB[2 * (PTJ + 2) * CLW * 2];  // [buffer][row][slot][column]
+    __shared__ float4 sR[PTJ / 2][64];               // odd rows' daughter sums
     const int lg = A.lg, m = (1 << lg) - 1, lgc = lg - 1;
     const size_t hN = (size_t)1 << (lg - 1);
     const unsigned nb = gridDim.x, b = blockIdx.x;
     const unsigned L = (b & 7u) * (nb >> 3) + (b >> 3);
-    const int nkt = (1 << lg) / CKW, njt = (1 << lg) / CTJ;
+    const int nkt = (1 << lg) / CKW, njt = (1 << lg) / PTJ;
     const int kt = (int)(L % (unsigned)nkt), jt = (int)((L / (unsigned)nkt) % (unsigned)njt),
               it = (int)(L / ((unsigned)nkt * (unsigned)njt));
-    const int k0 = kt * CKW, j0 = jt * CTJ, i0 = it * A.chunk;
+    const int k0 = kt * CKW, j0 = jt * PTJ, i0 = it * A.chunk;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int row = wv - 1;
-    const bool upd = row >= 0 && row < CTJ;
+    const bool upd = row >= 0 && row < PTJ;
     const int jg = (j0 + row) & m;
     const size_t plane = (size_t)1 << (2 * lg);
     const size_t rowbase = (size_t)jg << lg;
@@ -542,9 +550,9 @@ __global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_restrict_pass(RestrictArg
         const bool odd = ((pl + jg) & 1) != 0;
         return make_float2(a[q + (odd ? hN : 0)], a[q + (odd ? 0 : hN)]);
     };
-    // k-halo: lanes 0..2 CTJ - 1 of wave 0 serve row lane / 2, end lane & 1 (0: k0 - 1, 1: k0 + CKW)
-    const bool kh = wv == 0 && lane < 2 * CTJ;
-    const int khq = (lane & (2 * CTJ - 1)) >> 1, khs = lane & 1;
+    // k-halo: lanes 0..2 PTJ - 1 of wave 0 serve row lane / 2, end lane & 1 (0: k0 - 1, 1: k0 + CKW)
+    const bool kh = wv == 0 && lane < 2 * PTJ;
+    const int khq = (lane & (2 * PTJ - 1)) >> 1, khs = lane & 1;
     const int khj = (j0 + khq) & m, khk = khs ? ((k0 + CKW) & m) : ((k0 - 1) & m);
     auto kh_u = [&](int pl) { return (size_t)(pl & m) * plane + ((size_t)khj << lg) + (size_t)khk; };
     auto kh_e = [&](int pl) {
@@ -582,7 +590,7 @@ __global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_restrict_pass(RestrictArg
     auto step = [&](int p, bool second, const Raw &cur, Raw &nxt) {
         nxt = load(p + 1);
         const Cell4 n0 = mx_cell(cur.u.x, cur.e.x), n1 = mx_cell(cur.u.y, cur.e.y);
-        float4 *B = sB + buf * (CTJ + 2) * CLW * 2;
+        float4 *B = sB + buf * (PTJ + 2) * CLW * 2;
         B[slot(row, lane, 0)] = pack(c0);
         B[slot(row, lane, 1)] = pack(c1);
         if (kh) B[khs ? slot(khq, CKW / 2, 0) : slot(khq, -1, 1)] = pack(mx_cell(cur.khu, cur.khe));
@@ -1032,7 +1040,7 @@ int mx_launch_sweeps(mgfr_ctx *c, int l, int sweeps, bool timed)
     for (int s = 0; s < sweeps; ++s) {
         if (colour_pass) {
             const int chunk = L.N / 8;
-            const unsigned nb = (unsigned)((L.N / CKW) * (L.N / CTJ) * (L.N / chunk));
+            const unsigned nb = (unsigned)((L.N / CKW) * ((L.N + CTJ - 1) / CTJ) * (L.N / chunk));
             for (int colour = 0; colour < 2; ++colour) {
                 if ((rc = timer_slot(c, timed, slot))) return rc;
                 k_mx_colour<<<nb, 64 * (CTJ + 2), 0, c->stream>>>(ColourArgs{L.e32, L.u32, L.r32, L.lg, colour, chunk, kc});
@@ -1087,8 +1095,8 @@ int mx_vcycle(mgfr_ctx *c, int l)
     const bool sf = split_level(c, l), sc = split_level(c, l + 1);
     if (sf && L.N >= CKW) {
         const int chunk = L.N / 8;
-        const unsigned nbk = (unsigned)((L.N / CKW) * (L.N / CTJ) * (L.N / chunk));
-        k_mx_restrict_pass<<<nbk, 64 * (CTJ + 2), 0, c->stream>>>(
+        const unsigned nbk = (unsigned)((L.N / CKW) * (L.N / PTJ) * (L.N / chunk));
+        k_mx_restrict_pass<<<nbk, 64 * (PTJ + 2), 0, c->stream>>>(
             RestrictArgs{L.e32, L.u32, L.r32, Lc.ebar32, Lc.u32, Lc.r32, L.lg, chunk, sc, mx_const(c, l)});
     } else {
         k_mx_residual_restrict<<<nb(nc), kBlock, 0, c->stream>>>(L.e32, L.u32, L.r32, L.lg, mx_const(c, l),

@@ -411,6 +411,21 @@ __global__ void k_restrict4(const double *__restrict__ fine, int lgc, double *__
     }
 }
 
+// coarse = mean of the 8 daughters (the restriction of Sec. 3.3) of a float64 field
+__global__ void k_restrict_mean(const double *__restrict__ fine, int lgc, double *__restrict__ coarse)
+{
+    const int Nc = 1 << lgc, lgf = lgc + 1;
+    const size_t n = (size_t)Nc * Nc * Nc;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int K = (int)(t & (Nc - 1)), J = (int)((t >> lgc) & (Nc - 1)), I = (int)(t >> (2 * lgc));
+        double s = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) s += fine[cidx(2 * I + a, 2 * J + b, 2 * K + c, lgf)];
+        coarse[t] = s * 0.125;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_prolong_field(double *__restrict__ u, const double *__restrict__ uc,
                                                             const double *__restrict__ zero, int lgc)
 {
@@ -861,10 +876,25 @@ int nn_warm_start(mgfr_ctx *c, const double *delta, double *u, double *t_ms)
     n->stream = saved;
     if (rc) return rc;
     k_to_u<<<gridn(n2), 256, 0, c->stream>>>(n->y32, n2, L2.u);
-    // prolong the prediction twice with the linear reconstruction (Sec. 3.3)
+    // Coarse correction (nested iteration): the prediction is the initial guess
+    // of the N/4 problem L(u) = R R f, which gets coarse_cycles V-cycles; its
+    // solution, prolonged, starts coarse_cycles V-cycles of the N/2 problem
+    // L(u) = R f, whose solution prolonged is the initial guess at N.  With
+    // coarse_cycles = 0 the prediction is prolonged directly.
+    const int cc = c->p.coarse_cycles;
+    if (cc > 0) {
+        k_restrict_mean<<<gridn(n1), 256, 0, c->stream>>>(c->lev[0].f, L1.lg, L1.f);
+        k_restrict_mean<<<gridn(n2), 256, 0, c->stream>>>(L1.f, lg2, L2.f);
+        MGFR_HIP(hipGetLastError());
+        for (int k = 0; k < cc; ++k)
+            if ((rc = vcycle64(c, 2))) return rc;
+    }
+    // prolong twice with the linear reconstruction (Sec. 3.3)
     MGFR_HIP(hipMemsetAsync(L2.ubar, 0, n2 * sizeof(double), c->stream));
     MGFR_HIP(hipMemsetAsync(L1.u, 0, n1 * sizeof(double), c->stream));
     k_prolong_field<<<(unsigned)((n2 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(L1.u, L2.u, L2.ubar, lg2);
+    for (int k = 0; k < cc; ++k)
+        if ((rc = vcycle64(c, 1))) return rc;
     MGFR_HIP(hipMemsetAsync(L1.ubar, 0, n1 * sizeof(double), c->stream));
     const size_t n0 = (size_t)c->lev[0].N * c->lev[0].N * c->lev[0].N;
     MGFR_HIP(hipMemsetAsync(u, 0, n0 * sizeof(double), c->stream));

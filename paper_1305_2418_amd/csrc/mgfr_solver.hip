@@ -646,6 +646,7 @@ static int validate(const mgfr_params *p)
     if (p->pre_smooth < 0 || p->post_smooth < 0) return set_error(MGFR_ERR_ARG, "smoothing counts must be >= 0");
     if (p->coarse_sweeps < 1) return set_error(MGFR_ERR_ARG, "coarse_sweeps must be >= 1");
     if (p->max_vcycles < 0) return set_error(MGFR_ERR_ARG, "max_vcycles must be >= 0");
+    if (p->coarse_cycles < 0) return set_error(MGFR_ERR_ARG, "coarse_cycles must be >= 0");
     if (p->prolong != MGFR_PROLONG_LINEAR && p->prolong != MGFR_PROLONG_INJECT)
         return set_error(MGFR_ERR_ARG, "prolong must be 0 (linear) or 1 (injection)");
     if (p->precision != MGFR_FP64 && p->precision != MGFR_MIXED)

@@ -37,7 +37,7 @@ class _Params(C.Structure):
                 ("mesh", C.c_int), ("refine_levels", C.c_int), ("tol", C.c_double),
                 ("pre_smooth", C.c_int), ("post_smooth", C.c_int), ("coarse_sweeps", C.c_int),
                 ("max_vcycles", C.c_int), ("prolong", C.c_int), ("precision", C.c_int),
-                ("nn_mode", C.c_int), ("max_du", C.c_double)]
+                ("nn_mode", C.c_int), ("max_du", C.c_double), ("coarse_cycles", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -68,12 +68,13 @@ class Params:
     precision: int = FP64
     nn_mode: int = NN_NONE
     max_du: float = 2.0
+    coarse_cycles: int = 0
 
     def to_c(self) -> _Params:
         return _Params(self.box, self.a, self.omega_m, self.omega_l, self.fr0_abs, self.n,
                        self.mesh, self.refine_levels, self.tol, self.pre_smooth, self.post_smooth,
                        self.coarse_sweeps, self.max_vcycles, self.prolong, self.precision,
-                       self.nn_mode, self.max_du)
+                       self.nn_mode, self.max_du, self.coarse_cycles)
 
 
 @dataclass

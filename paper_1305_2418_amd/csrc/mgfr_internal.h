@@ -61,6 +61,7 @@ struct mgfr_ctx {
     int *dflag = nullptr;       // device flag
     // mixed precision float64 scratch
     double *r64 = nullptr;
+    double *exp2tab = nullptr;  // 2^(j/64), j = 0..63, for the table-driven float64 exponential
     // timing
     bool timing = false;
     mgfr::Timer sweep_timer;

@@ -844,6 +844,7 @@ struct CorrArgs {
     OpConst kc;
     double *partial;
     int nparts;
+    const double *exp2tab;
 };
 
 template <bool ADD_E>
@@ -851,6 +852,9 @@ __global__ __launch_bounds__(64 * (RTJ + 2)) void k_mx_correct_residual(CorrArgs
 {
     __shared__ double2 sB[2 * (RTJ + 2) * RLW];
     __shared__ double red[2 * (RTJ + 2)];
+    __shared__ double tab[64];
+    if (threadIdx.x < 64) tab[threadIdx.x] = A.exp2tab[threadIdx.x];
+    __syncthreads();
     const int lg = A.lg, m = (1 << lg) - 1;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -895,17 +899,17 @@ __global__ __launch_bounds__(64 * (RTJ + 2)) void k_mx_correct_residual(CorrArgs
             return w;
         };
         double vm = vload(i0 - 1, rowoff, jg, k), vc = vload(i0, rowoff, jg, k);
-        double Em = exp(vm), Ec = exp(vc);
+        double Em = exp64(vm, tab), Ec = exp64(vc, tab);
         Raw ra = load(i0), rb = load(i0 + 1), rc, rd;  // issued two steps ahead (see k_mx_colour)
         int buf = 0;
         auto step = [&](int p, const Raw &cur, Raw &nxt) {
             nxt = load(p + 2);
-            const double vp = cur.u + (double)cur.e, Ep = exp(vp);
+            const double vp = cur.u + (double)cur.e, Ep = exp64(vp, tab);
             double2 *B = sB + buf * (RTJ + 2) * RLW;
             B[(row + 1) * RLW + lane + 1] = make_double2(vc, Ec);
             if (kh) {
                 const double kv = cur.ku + (double)cur.ke;
-                B[(khq + 1) * RLW + (khs ? RLW - 1 : 0)] = make_double2(kv, exp(kv));
+                B[(khq + 1) * RLW + (khs ? RLW - 1 : 0)] = make_double2(kv, exp64(kv, tab));
             }
             __syncthreads();
             if (upd) {
@@ -914,7 +918,7 @@ __global__ __launch_bounds__(64 * (RTJ + 2)) void k_mx_correct_residual(CorrArgs
                 const double d0 = vp - vc, d1 = vm - vc, d2 = b.x - vc, d3 = a.x - vc, d4 = d.x - vc, d5 = c.x - vc;
                 const double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
                 const double S3 = ((Ep * d0 + Em * d1) + (b.y * d2 + a.y * d3)) + (d.y * d4 + c.y * d5);
-                const double L = A.kc.ih2 * 0.5 * (S3 + Ec * S1) + A.kc.bC * expm1(-A.kc.q * vc);
+                const double L = A.kc.ih2 * 0.5 * (S3 + Ec * S1) + A.kc.bC * expm1_64(-A.kc.q * vc, tab);
                 const double r = cur.f - L;
                 const size_t o = (size_t)(p & m) * plane + rowoff;
                 if (ADD_E) A.uout[o] = vc;
@@ -1172,6 +1176,7 @@ static int outer_step(mgfr_ctx *c, bool add_e, double *rmax, double *rsq)
     A.split = split_level(c, 0);
     A.kc = level_const(c, 0);
     A.partial = c->partial;
+    A.exp2tab = c->exp2tab;
     const int g = std::min(A.nunits, c->nparts);
     A.nparts = g;
     if (add_e)

@@ -10,6 +10,40 @@ __device__ __forceinline__ size_t cidx(int i, int j, int k, int lg)
     return (((((size_t)i) << lg) + (size_t)j) << lg) + (size_t)k;
 }
 
+// e^x and e^x - 1 in float64 by table-driven reduction (Tang's method):
+// x = (64 m + j) ln2/64 + r with |r| <= ln2/128, so e^x = 2^m 2^(j/64) e^r, and
+// e^r - 1 is its Taylor series to r^5 (truncation below 2^-56).  ln2/64 is
+// split into a head with 32 trailing zero bits and a tail (the fdlibm split
+// of ln2 scaled by 1/64), so (64 m + j) times the head is exact.  tab[j] =
+// 2^(j/64), j = 0..63 (kept in LDS by the kernels that use it).  The parts
+// are S = 2^m tab[j] and p = e^r - 1: e^x = S + S p, and e^x - 1 = (S - 1) + S p,
+// where S - 1 is exact for S in [1/2, 2] (|x| < ln2), so no cancellation.
+struct Exp64 {
+    double S, p;
+};
+
+__device__ __forceinline__ Exp64 exp64_parts(double x, const double *tab)
+{
+    const double kd = rint(x * 92.33248261689366);
+    double r = fma(kd, -0.01083042469326756, x);
+    r = fma(kd, -2.9815858269852933e-12, r);
+    const int k = (int)kd;
+    const double p = r * (1.0 + r * (0.5 + r * (1.0 / 6.0 + r * (1.0 / 24.0 + r * (1.0 / 120.0)))));
+    return Exp64{ldexp(tab[k & 63], k >> 6), p};
+}
+
+__device__ __forceinline__ double exp64(double x, const double *tab)
+{
+    const Exp64 e = exp64_parts(x, tab);
+    return fma(e.S, e.p, e.S);
+}
+
+__device__ __forceinline__ double expm1_64(double x, const double *tab)
+{
+    const Exp64 e = exp64_parts(x, tab);
+    return fma(e.S, e.p, e.S - 1.0);
+}
+
 __device__ __forceinline__ double nanmax(double a, double b)
 {
     return (a != a || a > b) ? a : b;

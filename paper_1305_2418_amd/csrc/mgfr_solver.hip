@@ -709,6 +709,7 @@ static void free_ctx(mgfr_ctx *c)
     (void)hipFree(c->dscal);
     (void)hipFree(c->dflag);
     (void)hipFree(c->r64);
+    (void)hipFree(c->exp2tab);
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (hipEvent_t e : c->sweep_timer.ev) (void)hipEventDestroy(e);
     if (c->ev_a) (void)hipEventDestroy(c->ev_a);
@@ -747,6 +748,12 @@ static int create_impl(const mgfr_params *p, void *stream, mgfr_ctx *c)
     }
     c->nparts = 4096;
     MGFR_HIP(hipMalloc(&c->partial, sizeof(double) * 2 * c->nparts));
+    {
+        double tab[64];
+        for (int j = 0; j < 64; ++j) tab[j] = (double)exp2l((long double)j / 64.0L);
+        MGFR_HIP(hipMalloc(&c->exp2tab, sizeof tab));
+        MGFR_HIP(hipMemcpy(c->exp2tab, tab, sizeof tab, hipMemcpyHostToDevice));
+    }
     MGFR_HIP(hipMalloc(&c->dscal, sizeof(double) * 8));
     MGFR_HIP(hipMalloc(&c->dflag, sizeof(int) * 4));
     MGFR_HIP(hipHostMalloc(&c->hscal, sizeof(double) * 8, hipHostMallocDefault));

@@ -271,6 +271,9 @@ int mgfr_amr_create(const mgfr_params *p, int64_t max_blocks, void *stream, mgfr
 void mgfr_amr_destroy(mgfr_amr *amr);
 /* pos: float32 [np][3] (unit masses); u0: float64 [N0^3] output (base solution) or
  * NULL; st: HOST array of refine_levels + 1 stats (level 0 = base) or NULL.
+ * The base assignment bins the particles (see mgfr_reserve_particles); a call
+ * with more particles than any before grows that workspace first.  Refinement
+ * flags are built on the device; only the block maps reach the host.
  * Returns the worst level status (MGFR_NOT_CONVERGED if a level hit
  * max_vcycles); MGFR_ERR_ARG if a level needs more than max_blocks blocks. */
 int mgfr_amr_solve(mgfr_amr *amr, const float *pos, int64_t np, double *u0, mgfr_stats *st);

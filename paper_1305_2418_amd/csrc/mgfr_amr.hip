@@ -105,10 +105,14 @@ __device__ double prolong_parent(const Composite &C, int l, int i, int j, int k)
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void k_ngp_count(const float *__restrict__ pos, int64_t np, int lg, double h, int *__restrict__ cnt)
+// Particle loops visit the particles in the order perm (the base assignment's
+// tile order) when it is given, else in index order; results do not depend on it.
+__global__ void k_ngp_count(const float *__restrict__ pos, const uint32_t *__restrict__ perm, int64_t np, int lg,
+                            double h, int *__restrict__ cnt)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int64_t p = perm ? (int64_t)perm[i] : i;
     const int N = 1 << lg;
     int c[3];
     for (int d = 0; d < 3; ++d) {
@@ -120,11 +124,12 @@ __global__ void k_ngp_count(const float *__restrict__ pos, int64_t np, int lg, d
 }
 
 // nearest-grid-point counts at level-l resolution, into the level's blocks
-__global__ void k_ngp_count_blocks(const float *__restrict__ pos, int64_t np, LevelDev L, double h,
-                                   int *__restrict__ cnt)
+__global__ void k_ngp_count_blocks(const float *__restrict__ pos, const uint32_t *__restrict__ perm, int64_t np,
+                                   LevelDev L, double h, int *__restrict__ cnt)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int64_t p = perm ? (int64_t)perm[i] : i;
     const int N = 1 << L.lg, M = 1 << L.mlg;
     int c[3];
     for (int d = 0; d < 3; ++d) {
@@ -136,11 +141,60 @@ __global__ void k_ngp_count_blocks(const float *__restrict__ pos, int64_t np, Le
     if (b >= 0) atomicAdd(&cnt[(size_t)b * 512 + ((c[0] & 7) * 8 + (c[1] & 7)) * 8 + (c[2] & 7)], 1);
 }
 
-// cloud-in-cell masses of all particles onto the level's block cells (f[0] interior)
-__global__ void k_amr_cic(const float *__restrict__ pos, int64_t np, LevelDev L, double h)
+// Refinement flags (device byte maps of block positions, one per refined level).
+// Level 1: the aligned 4^3 group of base cells around every base cell holding
+// more than 8 particles.
+__global__ void k_flag_base(const int *__restrict__ cnt, int lg0, unsigned char *__restrict__ blk1)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+    const int N = 1 << lg0, M = N / 4;
+    const size_t n = (size_t)N * N * N;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        if (cnt[t] > 8) {
+            const int k = (int)(t & (N - 1)), j = (int)((t >> lg0) & (N - 1)), i = (int)(t >> (2 * lg0));
+            blk1[((size_t)(i >> 2) * M + (j >> 2)) * M + (k >> 2)] = 1;
+        }
+}
+
+// Level 2: the same around every cell of a level-1 block holding more than 8 particles.
+__global__ void k_flag_l1(const int *__restrict__ cntb, int nb1, const int *__restrict__ org1, int N1,
+                          unsigned char *__restrict__ blk2)
+{
+    const int M = N1 / 4;
+    const size_t n = (size_t)nb1 * 512;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        if (cntb[t] > 8) {
+            const int b = (int)(t >> 9), c = (int)(t & 511);
+            const int i = org1[3 * b] + (c >> 6), j = org1[3 * b + 1] + ((c >> 3) & 7), k = org1[3 * b + 2] + (c & 7);
+            blk2[((size_t)(i >> 2) * M + (j >> 2)) * M + (k >> 2)] = 1;
+        }
+}
+
+// Proper nesting: every level-1 block holding a level-1 cell within two cells of
+// a flagged level-2 block is flagged too.  The 8-cell range [4b - 2, 4b + 5]
+// along an axis touches at most two level-1 blocks: those of its two ends.
+__global__ void k_nest(const unsigned char *__restrict__ blk2, int N1, unsigned char *__restrict__ blk1)
+{
+    const int M2 = N1 / 4, M1 = N1 / 8;
+    const size_t n = (size_t)M2 * M2 * M2;
+    auto blk_of = [&](int c) { return (((c % N1) + N1) % N1) / 8; };
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        if (!blk2[t]) continue;
+        const int bk = (int)(t % M2), bj = (int)((t / M2) % M2), bi = (int)(t / ((size_t)M2 * M2));
+        const int xi[2] = {blk_of(4 * bi - 2), blk_of(4 * bi + 5)}, xj[2] = {blk_of(4 * bj - 2), blk_of(4 * bj + 5)},
+                  xk[2] = {blk_of(4 * bk - 2), blk_of(4 * bk + 5)};
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) blk1[((size_t)xi[a] * M1 + xj[b]) * M1 + xk[c]] = 1;
+    }
+}
+
+// cloud-in-cell masses of all particles onto the level's block cells (f[0] interior)
+__global__ void k_amr_cic(const float *__restrict__ pos, const uint32_t *__restrict__ perm, int64_t np, LevelDev L,
+                          double h)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= np) return;
+    const int64_t p = perm ? (int64_t)perm[q] : q;
     const int N = 1 << L.lg, M = 1 << L.mlg;
     int i0[3];
     double t[3];
@@ -415,6 +469,8 @@ struct mgfr_amr {
     double *delta0 = nullptr, *u0 = nullptr;
     int *cnt0 = nullptr;      // [N0^3] counts
     int *cntb = nullptr;      // [max_blocks * 512] counts
+    unsigned char *flag[kMaxRef + 1] = {nullptr};  // refinement flags per level-l block position
+    const uint32_t *perm = nullptr;                // tile order of the particles (base binning) or NULL
     double *partial = nullptr, *dscal = nullptr, *hscal = nullptr;
     // per refined level
     int nb[kMaxRef + 1] = {0, 0, 0};
@@ -463,6 +519,7 @@ void amr_free(mgfr_amr *A)
     (void)hipFree(A->u0);
     (void)hipFree(A->cnt0);
     (void)hipFree(A->cntb);
+    for (int l = 1; l <= kMaxRef; ++l) (void)hipFree(A->flag[l]);
     (void)hipFree(A->partial);
     (void)hipFree(A->dscal);
     if (A->hscal) (void)hipHostFree(A->hscal);
@@ -582,7 +639,7 @@ int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
             MGFR_HIP(hipMemsetAsync(A->arr[l][a][m], 0, (size_t)L.nb * sub_vol(m) * sizeof(double), A->stream));
     // source
     const unsigned pg = (unsigned)((np + 255) / 256);
-    k_amr_cic<<<pg, 256, 0, A->stream>>>(pos, np, L, h);
+    k_amr_cic<<<pg, 256, 0, A->stream>>>(pos, A->perm, np, L, h);
     const double mbar = (double)np / ((double)N * N * N);
     const double s = A->beta * A->p.omega_m / (A->p.a * A->p.a * A->p.a);
     k_amr_source<<<L.nb, 512, 0, A->stream>>>(L, s, mbar, A->partial);
@@ -666,6 +723,7 @@ extern "C" int mgfr_amr_create(const mgfr_params *p, int64_t max_blocks, void *s
     for (int l = 1; l <= A->nref; ++l) {
         const size_t Mside = (size_t)(A->N0 << l) / 8;
         M((void **)&A->map[l], Mside * Mside * Mside * sizeof(int));
+        M((void **)&A->flag[l], Mside * Mside * Mside);  // one byte per level-l block position
         M((void **)&A->org[l], (size_t)max_blocks * 3 * sizeof(int));
         M((void **)&A->nbr[l], (size_t)max_blocks * 6 * sizeof(int));
         for (int a = 0; a < 4; ++a)
@@ -688,64 +746,57 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
     const size_t n0 = (size_t)N0 * N0 * N0;
     // base level: the uniform solver
     if ((rc = mgfr_set_stream(A->base, A->stream))) return rc;
+    if (A->base->binning && np > A->base->bin_cap && np <= (int64_t)0x7fffffff &&
+        (rc = bin_reserve(A->base, np)))
+        return rc;
     if ((rc = mgfr_assign_density(A->base, pos, nullptr, np, A->delta0))) return rc;
     MGFR_HIP(hipMemsetAsync(A->u0, 0, n0 * sizeof(double), A->stream));
     rc = mgfr_solve(A->base, A->delta0, A->u0, nullptr, &A->st[0]);
     if (rc < 0) return rc;
     const unsigned pg = (unsigned)((np + 255) / 256);
-    // level-1 blocks from base counts
-    MGFR_HIP(hipMemsetAsync(A->cnt0, 0, n0 * sizeof(int), A->stream));
-    k_ngp_count<<<pg, 256, 0, A->stream>>>(pos, np, A->lg0, A->p.box / N0, A->cnt0);
-    MGFR_HIP(hipGetLastError());
-    std::vector<int> hc(n0);
-    MGFR_HIP(hipMemcpyAsync(hc.data(), A->cnt0, n0 * sizeof(int), hipMemcpyDeviceToHost, A->stream));
-    MGFR_HIP(hipStreamSynchronize(A->stream));
-    const int M1 = N0 / 4;
-    std::vector<char> blk1((size_t)M1 * M1 * M1, 0);
-    for (int i = 0; i < N0; ++i)
-        for (int j = 0; j < N0; ++j)
-            for (int k = 0; k < N0; ++k)
-                if (hc[((size_t)i * N0 + j) * N0 + k] > 8) blk1[((size_t)(i / 4) * M1 + j / 4) * M1 + k / 4] = 1;
-    auto listof = [](const std::vector<char> &v) {
+    A->perm = (A->base->perm_np == np) ? A->base->perm : nullptr;
+    auto listof = [](const std::vector<unsigned char> &v) {
         std::vector<int64_t> L;
         for (size_t i = 0; i < v.size(); ++i)
             if (v[i]) L.push_back((int64_t)i);
         return L;
     };
+    auto fetch = [&](int l, std::vector<unsigned char> &v) {
+        const size_t Ml = (size_t)(N0 << l) / 8;
+        v.resize(Ml * Ml * Ml);
+        return hipMemcpyAsync(v.data(), A->flag[l], v.size(), hipMemcpyDeviceToHost, A->stream);
+    };
+    // level-1 blocks from base counts (flags built on the device)
+    const int M1 = N0 / 4;
+    MGFR_HIP(hipMemsetAsync(A->cnt0, 0, n0 * sizeof(int), A->stream));
+    MGFR_HIP(hipMemsetAsync(A->flag[1], 0, (size_t)M1 * M1 * M1, A->stream));
+    k_ngp_count<<<pg, 256, 0, A->stream>>>(pos, A->perm, np, A->lg0, A->p.box / N0, A->cnt0);
+    k_flag_base<<<(unsigned)std::min<size_t>((n0 + 255) / 256, 16384), 256, 0, A->stream>>>(A->cnt0, A->lg0,
+                                                                                           A->flag[1]);
+    MGFR_HIP(hipGetLastError());
+    std::vector<unsigned char> blk1, blk2;
+    MGFR_HIP(fetch(1, blk1));
+    MGFR_HIP(hipStreamSynchronize(A->stream));
     if ((rc = upload_level(A, 1, listof(blk1)))) return rc;
     if (A->nref >= 2) {
-        // level-2 blocks from level-1 counts inside level-1 blocks
+        // level-2 blocks from level-1 counts inside level-1 blocks, then proper nesting
         const int N1 = 2 * N0, M2 = N1 / 4;
         LevelDev L1 = level_dev(A, 1);
         const size_t nc = (size_t)A->nb[1] * 512;
+        MGFR_HIP(hipMemsetAsync(A->flag[2], 0, (size_t)M2 * M2 * M2, A->stream));
         if (nc) {
             MGFR_HIP(hipMemsetAsync(A->cntb, 0, nc * sizeof(int), A->stream));
-            k_ngp_count_blocks<<<pg, 256, 0, A->stream>>>(pos, np, L1, A->p.box / N1, A->cntb);
+            k_ngp_count_blocks<<<pg, 256, 0, A->stream>>>(pos, A->perm, np, L1, A->p.box / N1, A->cntb);
+            k_flag_l1<<<(unsigned)std::min<size_t>((nc + 255) / 256, 16384), 256, 0, A->stream>>>(
+                A->cntb, A->nb[1], A->org[1], N1, A->flag[2]);
+            const size_t n2 = (size_t)M2 * M2 * M2;
+            k_nest<<<(unsigned)std::min<size_t>((n2 + 255) / 256, 16384), 256, 0, A->stream>>>(A->flag[2], N1,
+                                                                                              A->flag[1]);
             MGFR_HIP(hipGetLastError());
         }
-        std::vector<int> hb(nc);
-        if (nc) MGFR_HIP(hipMemcpyAsync(hb.data(), A->cntb, nc * sizeof(int), hipMemcpyDeviceToHost, A->stream));
+        MGFR_HIP(fetch(1, blk1));
+        MGFR_HIP(fetch(2, blk2));
         MGFR_HIP(hipStreamSynchronize(A->stream));
-        std::vector<char> blk2((size_t)M2 * M2 * M2, 0);
-        const std::vector<int> &o1 = A->horg[1];
-        for (int b = 0; b < A->nb[1]; ++b)
-            for (int c = 0; c < 512; ++c)
-                if (hb[(size_t)b * 512 + c] > 8) {
-                    const int i = o1[3 * b] + (c >> 6), j = o1[3 * b + 1] + ((c >> 3) & 7), k = o1[3 * b + 2] + (c & 7);
-                    blk2[((size_t)(i / 4) * M2 + j / 4) * M2 + k / 4] = 1;
-                }
-        // proper nesting: level-1 blocks within two level-1 cells of every level-2 block
-        for (int bi = 0; bi < M2; ++bi)
-            for (int bj = 0; bj < M2; ++bj)
-                for (int bk = 0; bk < M2; ++bk) {
-                    if (!blk2[((size_t)bi * M2 + bj) * M2 + bk]) continue;
-                    for (int ci = 4 * bi - 2; ci < 4 * bi + 6; ++ci)
-                        for (int cj = 4 * bj - 2; cj < 4 * bj + 6; ++cj)
-                            for (int ck = 4 * bk - 2; ck < 4 * bk + 6; ++ck) {
-                                const int x = ((ci % N1) + N1) % N1, y = ((cj % N1) + N1) % N1, z = ((ck % N1) + N1) % N1;
-                                blk1[((size_t)(x / 8) * M1 + y / 8) * M1 + z / 8] = 1;
-                            }
-                }
         if ((rc = upload_level(A, 1, listof(blk1)))) return rc;
         if ((rc = upload_level(A, 2, listof(blk2)))) return rc;
     }

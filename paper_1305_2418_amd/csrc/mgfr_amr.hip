@@ -46,6 +46,7 @@ struct LevelDev {
     const int *org;          // [nb][3] block origin in level cells
     const int *nbr;          // [nb][6] face neighbours (-x,+x,-y,+y,-z,+z) or -1
     double *u[kSub], *f[kSub], *ub[kSub], *E[kSub];
+    const double *exp2tab;   // 2^(j/64) for the table-driven exponential (copied to LDS by the kernels)
 };
 
 struct Composite {  // solutions available for frozen / ghost values
@@ -105,14 +106,13 @@ __device__ double prolong_parent(const Composite &C, int l, int i, int j, int k)
 
 // ------------------------------------------------------------------ kernels
 
-// Particle loops visit the particles in the order perm (the base assignment's
-// tile order) when it is given, else in index order; results do not depend on it.
-__global__ void k_ngp_count(const float *__restrict__ pos, const uint32_t *__restrict__ perm, int64_t np, int lg,
-                            double h, int *__restrict__ cnt)
+// (The particle loops below run in the caller's particle order: in the base
+// binning's tile order, same-cell atomics of dense halos collide within a wave
+// and these loops ran slower.)
+__global__ void k_ngp_count(const float *__restrict__ pos, int64_t np, int lg, double h, int *__restrict__ cnt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    const int64_t p = perm ? (int64_t)perm[i] : i;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
     const int N = 1 << lg;
     int c[3];
     for (int d = 0; d < 3; ++d) {
@@ -124,12 +124,11 @@ __global__ void k_ngp_count(const float *__restrict__ pos, const uint32_t *__res
 }
 
 // nearest-grid-point counts at level-l resolution, into the level's blocks
-__global__ void k_ngp_count_blocks(const float *__restrict__ pos, const uint32_t *__restrict__ perm, int64_t np,
-                                   LevelDev L, double h, int *__restrict__ cnt)
+__global__ void k_ngp_count_blocks(const float *__restrict__ pos, int64_t np, LevelDev L, double h,
+                                   int *__restrict__ cnt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    const int64_t p = perm ? (int64_t)perm[i] : i;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
     const int N = 1 << L.lg, M = 1 << L.mlg;
     int c[3];
     for (int d = 0; d < 3; ++d) {
@@ -189,12 +188,10 @@ __global__ void k_nest(const unsigned char *__restrict__ blk2, int N1, unsigned 
 }
 
 // cloud-in-cell masses of all particles onto the level's block cells (f[0] interior)
-__global__ void k_amr_cic(const float *__restrict__ pos, const uint32_t *__restrict__ perm, int64_t np, LevelDev L,
-                          double h)
+__global__ void k_amr_cic(const float *__restrict__ pos, int64_t np, LevelDev L, double h)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= np) return;
-    const int64_t p = perm ? (int64_t)perm[q] : q;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
     const int N = 1 << L.lg, M = 1 << L.mlg;
     int i0[3];
     double t[3];
@@ -289,38 +286,49 @@ __global__ void k_amr_exchange(LevelDev L, double *__restrict__ X, int m)
 }
 
 __device__ __forceinline__ void amr_op(const double *__restrict__ U, int m, int x, int y, int z, double ih2,
-                                       double bC, double q, double &L, double &J)
+                                       double bC, double q, double &L, double &J, const double *tab)
 {
     const double uc = U[pidx(m, x, y, z)];
     const double nb[6] = {U[pidx(m, x + 1, y, z)], U[pidx(m, x - 1, y, z)], U[pidx(m, x, y + 1, z)],
                           U[pidx(m, x, y - 1, z)], U[pidx(m, x, y, z + 1)], U[pidx(m, x, y, z - 1)]};
-    const double ec = exp(uc);
+    const double ec = exp64(uc, tab);
     double S1 = 0.0, S2 = 0.0, S3 = 0.0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-        const double d = nb[s] - uc, en = exp(nb[s]);
+        const double d = nb[s] - uc, en = exp64(nb[s], tab);
         S1 += d;
         S2 += en;
         S3 += en * d;
     }
-    const double em = expm1(-q * uc);
+    const double em = expm1_64(-q * uc, tab);
     L = ih2 * 0.5 * (S3 + ec * S1) + bC * em;
     J = ih2 * 0.5 * (ec * (S1 - 6.0) - S2) - bC * q * (1.0 + em);
 }
 
 __global__ void k_amr_sweep(LevelDev L, int m, int colour, double ih2, double bC, double q, double max_du)
 {
+    __shared__ double tab[64];
+    if (threadIdx.x < 64) tab[threadIdx.x] = L.exp2tab[threadIdx.x];
+    __syncthreads();
     const int b = sub_b(m), vol = sub_vol(m);
-    const int cells = b * b * b;
-    const size_t n = (size_t)L.nb * cells;
+    // threads cover the cells of this colour only (b even); 1^3 blocks: one thread per block
+    const int per = b > 1 ? b * b * b / 2 : 1;
+    const size_t n = (size_t)L.nb * per;
     for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
-        const int blk = (int)(id / cells), c = (int)(id % cells);
-        const int x = c / (b * b), y = (c / b) % b, z = c % b;
-        const int gx = (L.org[3 * blk] >> m) + x, gy = (L.org[3 * blk + 1] >> m) + y, gz = (L.org[3 * blk + 2] >> m) + z;
-        if (((gx + gy + gz) & 1) != colour) continue;
+        const int blk = (int)(id / per), c = (int)(id % per);
+        const int ox = L.org[3 * blk] >> m, oy = L.org[3 * blk + 1] >> m, oz = L.org[3 * blk + 2] >> m;
+        int x = 0, y = 0, z = 0;
+        if (b > 1) {
+            const int hb = b >> 1;
+            x = c / (b * hb);
+            y = (c / hb) % b;
+            z = 2 * (c % hb) + ((colour + ox + oy + oz + x + y) & 1);
+        } else if (((ox + oy + oz) & 1) != colour) {
+            continue;
+        }
         double *U = L.u[m] + (size_t)blk * vol;
         double Lv, J;
-        amr_op(U, m, x, y, z, ih2, bC, q, Lv, J);
+        amr_op(U, m, x, y, z, ih2, bC, q, Lv, J, tab);
         double du = -(Lv - L.f[m][(size_t)blk * vol + pidx(m, x, y, z)]) / J;
         if (max_du > 0.0) du = fmin(fmax(du, -max_du), max_du);
         U[pidx(m, x, y, z)] += du;
@@ -331,6 +339,9 @@ __global__ void k_amr_sweep(LevelDev L, int m, int colour, double ih2, double bC
 // u_c = ubar
 __global__ void k_amr_restrict(LevelDev L, int m, double ih2, double bC, double q)
 {
+    __shared__ double tab[64];
+    if (threadIdx.x < 64) tab[threadIdx.x] = L.exp2tab[threadIdx.x];
+    __syncthreads();
     const int bc = sub_b(m + 1), volf = sub_vol(m), volc = sub_vol(m + 1);
     const int cells = bc * bc * bc;
     const size_t n = (size_t)L.nb * cells;
@@ -345,7 +356,7 @@ __global__ void k_amr_restrict(LevelDev L, int m, double ih2, double bC, double 
                 for (int d = 0; d < 2; ++d) {
                     const int x = 2 * X + a, y = 2 * Y + b2, z = 2 * Z + d;
                     double Lv, J;
-                    amr_op(U, m, x, y, z, ih2, bC, q, Lv, J);
+                    amr_op(U, m, x, y, z, ih2, bC, q, Lv, J, tab);
                     su += U[pidx(m, x, y, z)];
                     sr += F[pidx(m, x, y, z)] - Lv;
                 }
@@ -359,6 +370,9 @@ __global__ void k_amr_restrict(LevelDev L, int m, double ih2, double bC, double 
 // f += L(u) on interior cells of sublevel m (the FAS coarse source)
 __global__ void k_amr_coarse_rhs(LevelDev L, int m, double ih2, double bC, double q)
 {
+    __shared__ double tab[64];
+    if (threadIdx.x < 64) tab[threadIdx.x] = L.exp2tab[threadIdx.x];
+    __syncthreads();
     const int b = sub_b(m), vol = sub_vol(m);
     const int cells = b * b * b;
     const size_t n = (size_t)L.nb * cells;
@@ -366,7 +380,7 @@ __global__ void k_amr_coarse_rhs(LevelDev L, int m, double ih2, double bC, doubl
         const int blk = (int)(id / cells), c = (int)(id % cells);
         const int x = c / (b * b), y = (c / b) % b, z = c % b;
         double Lv, J;
-        amr_op(L.u[m] + (size_t)blk * vol, m, x, y, z, ih2, bC, q, Lv, J);
+        amr_op(L.u[m] + (size_t)blk * vol, m, x, y, z, ih2, bC, q, Lv, J, tab);
         L.f[m][(size_t)blk * vol + pidx(m, x, y, z)] += Lv;
     }
 }
@@ -407,11 +421,14 @@ __global__ void k_amr_prolong(LevelDev L, int m, int mode)
 __global__ __launch_bounds__(512) void k_amr_resnorm(LevelDev L, double ih2, double bC, double q,
                                                       double *__restrict__ partial)
 {
+    __shared__ double tab[64];
+    if (threadIdx.x < 64) tab[threadIdx.x] = L.exp2tab[threadIdx.x];
+    __syncthreads();
     __shared__ double sh[8];
     const int blk = blockIdx.x, t = threadIdx.x;
     const int x = t >> 6, y = (t >> 3) & 7, z = t & 7;
     double Lv, J;
-    amr_op(L.u[0] + (size_t)blk * sub_vol(0), 0, x, y, z, ih2, bC, q, Lv, J);
+    amr_op(L.u[0] + (size_t)blk * sub_vol(0), 0, x, y, z, ih2, bC, q, Lv, J, tab);
     double mx = fabs(L.f[0][(size_t)blk * sub_vol(0) + pidx(0, x, y, z)] - Lv);
     for (int o = 32; o > 0; o >>= 1) {
         const double other = __shfl_xor(mx, o, 64);
@@ -470,7 +487,6 @@ struct mgfr_amr {
     int *cnt0 = nullptr;      // [N0^3] counts
     int *cntb = nullptr;      // [max_blocks * 512] counts
     unsigned char *flag[kMaxRef + 1] = {nullptr};  // refinement flags per level-l block position
-    const uint32_t *perm = nullptr;                // tile order of the particles (base binning) or NULL
     double *partial = nullptr, *dscal = nullptr, *hscal = nullptr;
     // per refined level
     int nb[kMaxRef + 1] = {0, 0, 0};
@@ -492,6 +508,7 @@ LevelDev level_dev(const mgfr_amr *A, int l)
     L.map = A->map[l];
     L.org = A->org[l];
     L.nbr = A->nbr[l];
+    L.exp2tab = A->base->exp2tab;
     for (int m = 0; m < kSub; ++m) {
         L.u[m] = A->arr[l][0][m];
         L.f[m] = A->arr[l][1][m];
@@ -586,7 +603,7 @@ int amr_sweeps(mgfr_amr *A, const LevelDev &L, int m, int sweeps, const SubConst
     const size_t cells = (size_t)L.nb * b * b * b, faces = (size_t)L.nb * 6 * b * b;
     for (int s = 0; s < sweeps; ++s)
         for (int colour = 0; colour < 2; ++colour) {
-            k_amr_sweep<<<grid_of(cells), 256, 0, A->stream>>>(L, m, colour, K.ih2[m], A->beta * A->C,
+            k_amr_sweep<<<grid_of(b > 1 ? cells / 2 : cells), 256, 0, A->stream>>>(L, m, colour, K.ih2[m], A->beta * A->C,
                                                                 1.0 / (A->p.n + 1), A->p.max_du);
             k_amr_exchange<<<grid_of(faces), 256, 0, A->stream>>>(L, L.u[m], m);
         }
@@ -639,7 +656,7 @@ int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
             MGFR_HIP(hipMemsetAsync(A->arr[l][a][m], 0, (size_t)L.nb * sub_vol(m) * sizeof(double), A->stream));
     // source
     const unsigned pg = (unsigned)((np + 255) / 256);
-    k_amr_cic<<<pg, 256, 0, A->stream>>>(pos, A->perm, np, L, h);
+    k_amr_cic<<<pg, 256, 0, A->stream>>>(pos, np, L, h);
     const double mbar = (double)np / ((double)N * N * N);
     const double s = A->beta * A->p.omega_m / (A->p.a * A->p.a * A->p.a);
     k_amr_source<<<L.nb, 512, 0, A->stream>>>(L, s, mbar, A->partial);
@@ -754,7 +771,6 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
     rc = mgfr_solve(A->base, A->delta0, A->u0, nullptr, &A->st[0]);
     if (rc < 0) return rc;
     const unsigned pg = (unsigned)((np + 255) / 256);
-    A->perm = (A->base->perm_np == np) ? A->base->perm : nullptr;
     auto listof = [](const std::vector<unsigned char> &v) {
         std::vector<int64_t> L;
         for (size_t i = 0; i < v.size(); ++i)
@@ -770,7 +786,7 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
     const int M1 = N0 / 4;
     MGFR_HIP(hipMemsetAsync(A->cnt0, 0, n0 * sizeof(int), A->stream));
     MGFR_HIP(hipMemsetAsync(A->flag[1], 0, (size_t)M1 * M1 * M1, A->stream));
-    k_ngp_count<<<pg, 256, 0, A->stream>>>(pos, A->perm, np, A->lg0, A->p.box / N0, A->cnt0);
+    k_ngp_count<<<pg, 256, 0, A->stream>>>(pos, np, A->lg0, A->p.box / N0, A->cnt0);
     k_flag_base<<<(unsigned)std::min<size_t>((n0 + 255) / 256, 16384), 256, 0, A->stream>>>(A->cnt0, A->lg0,
                                                                                            A->flag[1]);
     MGFR_HIP(hipGetLastError());
@@ -786,7 +802,7 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
         MGFR_HIP(hipMemsetAsync(A->flag[2], 0, (size_t)M2 * M2 * M2, A->stream));
         if (nc) {
             MGFR_HIP(hipMemsetAsync(A->cntb, 0, nc * sizeof(int), A->stream));
-            k_ngp_count_blocks<<<pg, 256, 0, A->stream>>>(pos, A->perm, np, L1, A->p.box / N1, A->cntb);
+            k_ngp_count_blocks<<<pg, 256, 0, A->stream>>>(pos, np, L1, A->p.box / N1, A->cntb);
             k_flag_l1<<<(unsigned)std::min<size_t>((nc + 255) / 256, 16384), 256, 0, A->stream>>>(
                 A->cntb, A->nb[1], A->org[1], N1, A->flag[2]);
             const size_t n2 = (size_t)M2 * M2 * M2;

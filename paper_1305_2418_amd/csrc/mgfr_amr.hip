@@ -285,12 +285,9 @@ __global__ void k_amr_exchange(LevelDev L, double *__restrict__ X, int m)
     }
 }
 
-__device__ __forceinline__ void amr_op(const double *__restrict__ U, int m, int x, int y, int z, double ih2,
-                                       double bC, double q, double &L, double &J, const double *tab)
+__device__ __forceinline__ void amr_op_vals(double uc, const double nb[6], double ih2, double bC, double q,
+                                            double &L, double &J, const double *tab)
 {
-    const double uc = U[pidx(m, x, y, z)];
-    const double nb[6] = {U[pidx(m, x + 1, y, z)], U[pidx(m, x - 1, y, z)], U[pidx(m, x, y + 1, z)],
-                          U[pidx(m, x, y - 1, z)], U[pidx(m, x, y, z + 1)], U[pidx(m, x, y, z - 1)]};
     const double ec = exp64(uc, tab);
     double S1 = 0.0, S2 = 0.0, S3 = 0.0;
 #pragma unroll
@@ -303,6 +300,36 @@ __device__ __forceinline__ void amr_op(const double *__restrict__ U, int m, int 
     const double em = expm1_64(-q * uc, tab);
     L = ih2 * 0.5 * (S3 + ec * S1) + bC * em;
     J = ih2 * 0.5 * (ec * (S1 - 6.0) - S2) - bC * q * (1.0 + em);
+}
+
+// L and J at an interior cell of sublevel m, neighbours from the padded block
+__device__ __forceinline__ void amr_op(const double *__restrict__ U, int m, int x, int y, int z, double ih2,
+                                       double bC, double q, double &L, double &J, const double *tab)
+{
+    const double nb[6] = {U[pidx(m, x + 1, y, z)], U[pidx(m, x - 1, y, z)], U[pidx(m, x, y + 1, z)],
+                          U[pidx(m, x, y - 1, z)], U[pidx(m, x, y, z + 1)], U[pidx(m, x, y, z - 1)]};
+    amr_op_vals(U[pidx(m, x, y, z)], nb, ih2, bC, q, L, J, tab);
+}
+
+// u of sublevel m at (x, y, z) of block blk, where one coordinate may lie one
+// cell outside the block: the neighbouring block's cell if that block exists
+// (read directly, so sweeps need no ghost exchange between colours), else the
+// block's own frozen ghost value.
+__device__ __forceinline__ double amr_nbval(const LevelDev &L, const double *__restrict__ U, int blk, int m, int b,
+                                            int vol, int x, int y, int z)
+{
+    int f = -1, xx = x, yy = y, zz = z;
+    if (x < 0) { f = 0; xx = b - 1; }
+    else if (x >= b) { f = 1; xx = 0; }
+    else if (y < 0) { f = 2; yy = b - 1; }
+    else if (y >= b) { f = 3; yy = 0; }
+    else if (z < 0) { f = 4; zz = b - 1; }
+    else if (z >= b) { f = 5; zz = 0; }
+    if (f >= 0) {
+        const int nb = L.nbr[6 * blk + f];
+        if (nb >= 0) return U[(size_t)nb * vol + pidx(m, xx, yy, zz)];
+    }
+    return U[(size_t)blk * vol + pidx(m, x, y, z)];
 }
 
 __global__ void k_amr_sweep(LevelDev L, int m, int colour, double ih2, double bC, double q, double max_du)
@@ -327,11 +354,18 @@ __global__ void k_amr_sweep(LevelDev L, int m, int colour, double ih2, double bC
             continue;
         }
         double *U = L.u[m] + (size_t)blk * vol;
+        const double uc = U[pidx(m, x, y, z)];
+        const double nbv[6] = {amr_nbval(L, L.u[m], blk, m, b, vol, x + 1, y, z),
+                               amr_nbval(L, L.u[m], blk, m, b, vol, x - 1, y, z),
+                               amr_nbval(L, L.u[m], blk, m, b, vol, x, y + 1, z),
+                               amr_nbval(L, L.u[m], blk, m, b, vol, x, y - 1, z),
+                               amr_nbval(L, L.u[m], blk, m, b, vol, x, y, z + 1),
+                               amr_nbval(L, L.u[m], blk, m, b, vol, x, y, z - 1)};
         double Lv, J;
-        amr_op(U, m, x, y, z, ih2, bC, q, Lv, J, tab);
+        amr_op_vals(uc, nbv, ih2, bC, q, Lv, J, tab);
         double du = -(Lv - L.f[m][(size_t)blk * vol + pidx(m, x, y, z)]) / J;
         if (max_du > 0.0) du = fmin(fmax(du, -max_du), max_du);
-        U[pidx(m, x, y, z)] += du;
+        U[pidx(m, x, y, z)] = uc + du;
     }
 }
 
@@ -602,11 +636,11 @@ int amr_sweeps(mgfr_amr *A, const LevelDev &L, int m, int sweeps, const SubConst
     const int b = sub_b(m);
     const size_t cells = (size_t)L.nb * b * b * b, faces = (size_t)L.nb * 6 * b * b;
     for (int s = 0; s < sweeps; ++s)
-        for (int colour = 0; colour < 2; ++colour) {
+        for (int colour = 0; colour < 2; ++colour)
             k_amr_sweep<<<grid_of(b > 1 ? cells / 2 : cells), 256, 0, A->stream>>>(L, m, colour, K.ih2[m], A->beta * A->C,
                                                                 1.0 / (A->p.n + 1), A->p.max_du);
-            k_amr_exchange<<<grid_of(faces), 256, 0, A->stream>>>(L, L.u[m], m);
-        }
+    // ghost faces between blocks for the kernels that read them (restriction, residual)
+    if (sweeps > 0) k_amr_exchange<<<grid_of(faces), 256, 0, A->stream>>>(L, L.u[m], m);
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
 }
@@ -629,7 +663,7 @@ int amr_vcycle(mgfr_amr *A, const LevelDev &L, int m, const SubConst &K)
     k_amr_make_e<<<grid_of(cc), 256, 0, A->stream>>>(L, m + 1);
     k_amr_exchange<<<grid_of(fc), 256, 0, A->stream>>>(L, L.E[m + 1], m + 1);
     k_amr_prolong<<<grid_of(cf), 256, 0, A->stream>>>(L, m, A->p.prolong);
-    k_amr_exchange<<<grid_of(ff), 256, 0, A->stream>>>(L, L.u[m], m);
+    if (A->p.post_smooth == 0) k_amr_exchange<<<grid_of(ff), 256, 0, A->stream>>>(L, L.u[m], m);
     MGFR_HIP(hipGetLastError());
     return amr_sweeps(A, L, m, A->p.post_smooth, K);
 }

@@ -25,6 +25,7 @@ struct OpConst {
     double bC;      // beta * C
     double q;       // 1/(n+1)
     double max_du;  // Newton step limit (<= 0: none)
+    const double *tab;  // 2^(j/64), j = 0..63 (table-driven exponential; global or LDS copy)
 };
 
 struct Level {
@@ -95,6 +96,7 @@ inline OpConst level_const(const mgfr_ctx *c, int l)
     k.bC = c->bC;
     k.q = c->q;
     k.max_du = c->p.max_du;
+    k.tab = c->exp2tab;
     return k;
 }
 

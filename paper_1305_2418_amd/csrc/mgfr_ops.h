@@ -10,6 +10,14 @@ __device__ __forceinline__ size_t cidx(int i, int j, int k, int lg)
     return (((((size_t)i) << lg) + (size_t)j) << lg) + (size_t)k;
 }
 
+// Copy the exponential's table into LDS for a kernel's own use (before any
+// early return; kc is the kernel's OpConst parameter).
+#define MGFR_EXP_TABLE_TO_LDS(kc)                                                \
+    __shared__ double s_exp2tab_[64];                                           \
+    if (threadIdx.x < 64) s_exp2tab_[threadIdx.x] = (kc).tab[threadIdx.x];      \
+    __syncthreads();                                                            \
+    (kc).tab = s_exp2tab_
+
 // e^x and e^x - 1 in float64 by table-driven reduction (Tang's method):
 // x = (64 m + j) ln2/64 + r with |r| <= ln2/128, so e^x = 2^m 2^(j/64) e^r, and
 // e^r - 1 is its Taylor series to r^5 (truncation below 2^-56).  ln2/64 is
@@ -71,7 +79,7 @@ __device__ __forceinline__ void block_residuals(const double *__restrict__ u, co
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 B[a][b][c] = u[cidx(i0 + a, j0 + b, k0 + c, lg)];
-                EB[a][b][c] = exp(B[a][b][c]);
+                EB[a][b][c] = exp64(B[a][b][c], kc.tab);
             }
             Xm[a][b] = u[cidx((i0 - 1) & m, j0 + a, k0 + b, lg)];
             Xp[a][b] = u[cidx((i0 + 2) & m, j0 + a, k0 + b, lg)];
@@ -94,16 +102,16 @@ __device__ __forceinline__ void block_residuals(const double *__restrict__ u, co
                 double ny1 = b ? B[a][0][c] : Ym[a][c];
                 double nz0 = c ? Zp[a][b] : B[a][b][1];
                 double nz1 = c ? B[a][b][0] : Zm[a][b];
-                double ex0 = a ? exp(nx0) : EB[1][b][c];
-                double ex1 = a ? EB[0][b][c] : exp(nx1);
-                double ey0 = b ? exp(ny0) : EB[a][1][c];
-                double ey1 = b ? EB[a][0][c] : exp(ny1);
-                double ez0 = c ? exp(nz0) : EB[a][b][1];
-                double ez1 = c ? EB[a][b][0] : exp(nz1);
+                double ex0 = a ? exp64(nx0, kc.tab) : EB[1][b][c];
+                double ex1 = a ? EB[0][b][c] : exp64(nx1, kc.tab);
+                double ey0 = b ? exp64(ny0, kc.tab) : EB[a][1][c];
+                double ey1 = b ? EB[a][0][c] : exp64(ny1, kc.tab);
+                double ez0 = c ? exp64(nz0, kc.tab) : EB[a][b][1];
+                double ez1 = c ? EB[a][b][0] : exp64(nz1, kc.tab);
                 double d0 = nx0 - uc, d1 = nx1 - uc, d2 = ny0 - uc, d3 = ny1 - uc, d4 = nz0 - uc, d5 = nz1 - uc;
                 double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
                 double S3 = ((ex0 * d0 + ex1 * d1) + (ey0 * d2 + ey1 * d3)) + (ez0 * d4 + ez1 * d5);
-                double L = kc.ih2 * 0.5 * (S3 + ec * S1) + kc.bC * expm1(-kc.q * uc);
+                double L = kc.ih2 * 0.5 * (S3 + ec * S1) + kc.bC * expm1_64(-kc.q * uc, kc.tab);
                 double r = f[cidx(i0 + a, j0 + b, k0 + c, lg)] - L;
                 out.r[(a * 2 + b) * 2 + c] = r;
                 su += uc;

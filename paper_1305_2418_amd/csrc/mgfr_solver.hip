@@ -52,13 +52,14 @@ int hip_fail(hipError_t e, const char *what, const char *file, int line)
 __device__ __forceinline__ double ngs_step(double uc, double n0, double n1, double n2, double n3,
                                            double n4, double n5, double f, const OpConst &k)
 {
-    double ec = exp(uc);
+    double ec = exp64(uc, k.tab);
     double d0 = n0 - uc, d1 = n1 - uc, d2 = n2 - uc, d3 = n3 - uc, d4 = n4 - uc, d5 = n5 - uc;
-    double e0 = exp(n0), e1 = exp(n1), e2 = exp(n2), e3 = exp(n3), e4 = exp(n4), e5 = exp(n5);
+    double e0 = exp64(n0, k.tab), e1 = exp64(n1, k.tab), e2 = exp64(n2, k.tab), e3 = exp64(n3, k.tab),
+           e4 = exp64(n4, k.tab), e5 = exp64(n5, k.tab);
     double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
     double S2 = ((e0 + e1) + (e2 + e3)) + (e4 + e5);
     double S3 = ((e0 * d0 + e1 * d1) + (e2 * d2 + e3 * d3)) + (e4 * d4 + e5 * d5);
-    double em = expm1(-k.q * uc);
+    double em = expm1_64(-k.q * uc, k.tab);
     double L = k.ih2 * 0.5 * (S3 + ec * S1) + k.bC * em;
     double J = k.ih2 * 0.5 * (ec * (S1 - 6.0) - S2) - k.bC * k.q * (1.0 + em);
     double du = -(L - f) / J;
@@ -69,12 +70,13 @@ __device__ __forceinline__ double ngs_step(double uc, double n0, double n1, doub
 __device__ __forceinline__ double op_value(double uc, double n0, double n1, double n2, double n3,
                                            double n4, double n5, const OpConst &k)
 {
-    double ec = exp(uc);
+    double ec = exp64(uc, k.tab);
     double d0 = n0 - uc, d1 = n1 - uc, d2 = n2 - uc, d3 = n3 - uc, d4 = n4 - uc, d5 = n5 - uc;
-    double e0 = exp(n0), e1 = exp(n1), e2 = exp(n2), e3 = exp(n3), e4 = exp(n4), e5 = exp(n5);
+    double e0 = exp64(n0, k.tab), e1 = exp64(n1, k.tab), e2 = exp64(n2, k.tab), e3 = exp64(n3, k.tab),
+           e4 = exp64(n4, k.tab), e5 = exp64(n5, k.tab);
     double S1 = ((d0 + d1) + (d2 + d3)) + (d4 + d5);
     double S3 = ((e0 * d0 + e1 * d1) + (e2 * d2 + e3 * d3)) + (e4 * d4 + e5 * d5);
-    return k.ih2 * 0.5 * (S3 + ec * S1) + k.bC * expm1(-k.q * uc);
+    return k.ih2 * 0.5 * (S3 + ec * S1) + k.bC * expm1_64(-k.q * uc, k.tab);
 }
 
 // L_c at (i,j,k) of a periodic 2^lg mesh.
@@ -135,10 +137,10 @@ __device__ __forceinline__ double ngs_step_e(double uc, double ec, double em, do
 
 // e^{-q u} - 1 given e^{u}: for n = 1 (q = 1/2) this is rsqrt(e^u) - 1.
 template <bool N1>
-__device__ __forceinline__ double curv_em(double uc, double ec, double q)
+__device__ __forceinline__ double curv_em(double uc, double ec, double q, const double *tab)
 {
     if constexpr (N1) return rsqrt(ec) - 1.0;
-    else return expm1(-q * uc);
+    else return expm1_64(-q * uc, tab);
 }
 
 // One full red-black sweep, out of place: uout = sweep(uin).
@@ -171,6 +173,7 @@ __global__ __launch_bounds__(32 * JL) void k_sweep_fused(const double *__restric
                                                            double *__restrict__ uout, int lg, int chunk,
                                                            OpConst kc)
 {
+    MGFR_EXP_TABLE_TO_LDS(kc);
     constexpr int JI = JL - 4;
     __shared__ double sV[2][JL][FKL];
     __shared__ double sE[2][JL][FKL];
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(32 * JL) void k_sweep_fused(const double *__restric
     double F2a = lda ? f[at(i0 - 1, jga)] : 0.0, F2b = ldb ? f[at(i0 - 1, jgb)] : 0.0;
     double V4a = uin[at(i0, jga)], V4b = uin[at(i0, jgb)];
     double F4a = lda ? f[at(i0, jga)] : 0.0, F4b = ldb ? f[at(i0, jgb)] : 0.0;
-    double E1a = exp(V1a), E1b = exp(V1b), E2a = exp(V2a), E2b = exp(V2b);
+    double E1a = exp64(V1a, kc.tab), E1b = exp64(V1b, kc.tab), E2a = exp64(V2a, kc.tab), E2b = exp64(V2b, kc.tab);
     int xb = 0;
     for (int p = i0 - 2; p < i0 + chunk; ++p) {
         // plane p+2 (prefetched last iteration); prefetch plane p+3
@@ -211,7 +214,7 @@ __global__ __launch_bounds__(32 * JL) void k_sweep_fused(const double *__restric
             F4a = lda ? f[at(p + 3, jga)] : 0.0;
             F4b = ldb ? f[at(p + 3, jgb)] : 0.0;
         }
-        const double E3a = exp(V3a), E3b = exp(V3b);
+        const double E3a = exp64(V3a, kc.tab), E3b = exp64(V3b, kc.tab);
         __syncthreads();  // the previous plane's readers of buffer xb are done
         sV[xb][ra][lane] = V2a;
         sV[xb][rb][lane] = V2b;
@@ -225,13 +228,13 @@ __global__ __launch_bounds__(32 * JL) void k_sweep_fused(const double *__restric
         {
             const bool act = kin1 && (sel ? in1b : in1a);
             const double uc = sel ? V2b : V2a, ec = sel ? E2b : E2a;
-            const double du = ngs_step_e(uc, ec, curv_em<N1>(uc, ec, kc.q), sel ? V1b : V1a, sel ? E1b : E1a,
+            const double du = ngs_step_e(uc, ec, curv_em<N1>(uc, ec, kc.q, kc.tab), sel ? V1b : V1a, sel ? E1b : E1a,
                                          sel ? V3b : V3a, sel ? E3b : E3a, sV[xb][rc - 1][lane],
                                          sE[xb][rc - 1][lane], sV[xb][rc + 1][lane], sE[xb][rc + 1][lane],
                                          sV[xb][rc][lm], sE[xb][rc][lm], sV[xb][rc][lp], sE[xb][rc][lp],
                                          sel ? F2b : F2a, kc);
             const double un = uc + du;
-            const double en = exp(un);
+            const double en = exp64(un, kc.tab);
             V2a = (act && !sel) ? un : V2a;
             E2a = (act && !sel) ? en : E2a;
             V2b = (act && sel) ? un : V2b;
@@ -247,7 +250,7 @@ __global__ __launch_bounds__(32 * JL) void k_sweep_fused(const double *__restric
             const int yb = xb ^ 1;
             const bool act = kint && (sel ? intb : inta);
             const double uc = sel ? V1b : V1a, ec = sel ? E1b : E1a;
-            const double du = ngs_step_e(uc, ec, curv_em<N1>(uc, ec, kc.q), V0s, E0s, sel ? V2b : V2a,
+            const double du = ngs_step_e(uc, ec, curv_em<N1>(uc, ec, kc.q, kc.tab), V0s, E0s, sel ? V2b : V2a,
                                          sel ? E2b : E2a, sV[yb][rc - 1][lane], sE[yb][rc - 1][lane],
                                          sV[yb][rc + 1][lane], sE[yb][rc + 1][lane], sV[yb][rc][lm],
                                          sE[yb][rc][lm], sV[yb][rc][lp], sE[yb][rc][lp], F1s, kc);
@@ -280,6 +283,7 @@ __global__ __launch_bounds__(32 * JL) void k_sweep_fused(const double *__restric
 __global__ __launch_bounds__(kBlock) void k_sweep_half(double *__restrict__ u, const double *__restrict__ f,
                                                          int lg, int colour, OpConst kc)
 {
+    MGFR_EXP_TABLE_TO_LDS(kc);
     size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     sweep_cell(u, f, t, lg, colour, kc);
 }
@@ -290,6 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(const double *__re
                                                                 OpConst kc, double *__restrict__ ubar_c,
                                                                 double *__restrict__ f_c)
 {
+    MGFR_EXP_TABLE_TO_LDS(kc);
     const int lgc = lg - 1;
     size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     int K = (int)(t & ((1u << lgc) - 1));
@@ -305,6 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(const double *__re
 __global__ __launch_bounds__(kBlock) void k_coarse_rhs(const double *__restrict__ ubar, int lg, OpConst kc,
                                                          double *__restrict__ fc, double *__restrict__ uc)
 {
+    MGFR_EXP_TABLE_TO_LDS(kc);
     size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int m = (1 << lg) - 1;
     int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
@@ -348,6 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const double *__restri
                                                             const double *__restrict__ f, int lg, OpConst kc,
                                                             double *__restrict__ partial, int nparts)
 {
+    MGFR_EXP_TABLE_TO_LDS(kc);
     __shared__ double sh[2 * kBlock / 64];
     const int lgc = lg - 1;
     const size_t nblk = (size_t)1 << (3 * lgc);
@@ -375,6 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_field(const double *__restr
                                                              const double *__restrict__ f, int lg, OpConst kc,
                                                              double *__restrict__ r)
 {
+    MGFR_EXP_TABLE_TO_LDS(kc);
     size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int m = (1 << lg) - 1;
     int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
@@ -436,11 +444,12 @@ struct TailArgs {
     int lg[kMaxLevels];
     int l0, nlev, pre, post, coarse, mode;
     double bC, q, max_du;
+    const double *tab;  // exponential's table (the kernel points it at its LDS copy)
 };
 
 __device__ void tail_sweeps(const TailArgs &A, int l, int sweeps)
 {
-    OpConst kc{A.ih2[l], A.bC, A.q, A.max_du};
+    OpConst kc{A.ih2[l], A.bC, A.q, A.max_du, A.tab};
     const int lg = A.lg[l];
     const size_t half = (size_t)1 << (3 * lg - 1);
     for (int s = 0; s < sweeps; ++s)
@@ -452,9 +461,13 @@ __device__ void tail_sweeps(const TailArgs &A, int l, int sweeps)
 
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs A)
 {
+    __shared__ double s_tab[64];
+    if (threadIdx.x < 64) s_tab[threadIdx.x] = A.tab[threadIdx.x];
+    __syncthreads();
+    A.tab = s_tab;
     for (int l = A.l0; l < A.nlev - 1; ++l) {
         tail_sweeps(A, l, A.pre);
-        OpConst kc{A.ih2[l], A.bC, A.q, A.max_du};
+        OpConst kc{A.ih2[l], A.bC, A.q, A.max_du, A.tab};
         const int lg = A.lg[l], lgc = lg - 1;
         const size_t nc = (size_t)1 << (3 * lgc);
         for (size_t t = threadIdx.x; t < nc; t += kTailThreads) {
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs A)
             A.f[l + 1][t] = br.rmean;
         }
         __syncthreads();
-        OpConst kcc{A.ih2[l + 1], A.bC, A.q, A.max_du};
+        OpConst kcc{A.ih2[l + 1], A.bC, A.q, A.max_du, A.tab};
         const int mc = (1 << lgc) - 1;
         for (size_t t = threadIdx.x; t < nc; t += kTailThreads) {
             int k = (int)(t & mc), j = (int)((t >> lgc) & mc), i = (int)(t >> (2 * lgc));
@@ -576,6 +589,7 @@ static int launch_tail(mgfr_ctx *c, int l0)
     A.bC = c->bC;
     A.q = c->q;
     A.max_du = c->p.max_du;
+    A.tab = c->exp2tab;
     k_tail<<<1, kTailThreads, 0, c->stream>>>(A);
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;

@@ -46,6 +46,8 @@ struct LevelDev {
     const int *org;          // [nb][3] block origin in level cells
     const int *nbr;          // [nb][6] face neighbours (-x,+x,-y,+y,-z,+z) or -1
     double *u[kSub], *f[kSub], *ub[kSub], *E[kSub];
+    // float32 correction cycle (mixed precision): e, u in float32, r, restricted e
+    float *e32[kSub], *u32[kSub], *r32[kSub], *eb32[kSub];
     const double *exp2tab;   // 2^(j/64) for the table-driven exponential (copied to LDS by the kernels)
 };
 
@@ -315,8 +317,9 @@ __device__ __forceinline__ void amr_op(const double *__restrict__ U, int m, int 
 // cell outside the block: the neighbouring block's cell if that block exists
 // (read directly, so sweeps need no ghost exchange between colours), else the
 // block's own frozen ghost value.
-__device__ __forceinline__ double amr_nbval(const LevelDev &L, const double *__restrict__ U, int blk, int m, int b,
-                                            int vol, int x, int y, int z)
+template <typename T>
+__device__ __forceinline__ T amr_nbval(const LevelDev &L, const T *__restrict__ U, int blk, int m, int b, int vol,
+                                       int x, int y, int z)
 {
     int f = -1, xx = x, yy = y, zz = z;
     if (x < 0) { f = 0; xx = b - 1; }
@@ -493,6 +496,185 @@ __global__ void k_max_final(const double *__restrict__ partial, int n, double *_
     }
 }
 
+// ------------------------------------------ mixed precision on the refined levels
+//
+// The float32 correction cycle of the uniform mixed solve on the block arrays:
+// e solves N_u(e) = r (N_u(e) = L(u + e) - L(u) without cancellation) with u the
+// level's float64 iterate held in float32; e is zero on frozen ghosts (their
+// values never change) and neighbouring blocks are read directly.
+
+// u32 = float(u) and e32 = eb32 = 0 on every padded cell of sublevel m
+__global__ void k_amrx_init(LevelDev L, int m)
+{
+    const size_t n = (size_t)L.nb * sub_vol(m);
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        L.u32[m][id] = (float)L.u[m][id];
+        L.e32[m][id] = 0.f;
+        L.eb32[m][id] = 0.f;
+    }
+}
+
+// float64 residual r = f - L(u) on sublevel 0 (ghosts exchanged): r32 = r,
+// u32 = u, e32 = 0 on interior cells, per-block max|r|
+__global__ __launch_bounds__(512) void k_amrx_outer(LevelDev L, double ih2, double bC, double q,
+                                                     double *__restrict__ partial)
+{
+    __shared__ double tab[64];
+    if (threadIdx.x < 64) tab[threadIdx.x] = L.exp2tab[threadIdx.x];
+    __syncthreads();
+    __shared__ double sh[8];
+    const int blk = blockIdx.x, t = threadIdx.x;
+    const int x = t >> 6, y = (t >> 3) & 7, z = t & 7;
+    const size_t o = (size_t)blk * sub_vol(0) + pidx(0, x, y, z);
+    double Lv, J;
+    amr_op(L.u[0] + (size_t)blk * sub_vol(0), 0, x, y, z, ih2, bC, q, Lv, J, tab);
+    const double r = L.f[0][o] - Lv;
+    L.r32[0][o] = (float)r;
+    L.u32[0][o] = (float)L.u[0][o];
+    L.e32[0][o] = 0.f;
+    double mx = fabs(r);
+    for (int s = 32; s > 0; s >>= 1) {
+        const double other = __shfl_xor(mx, s, 64);
+        mx = (other != other || other > mx) ? other : mx;
+    }
+    if ((t & 63) == 0) sh[t >> 6] = mx;
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < 8; ++w) mx = (sh[w] != sh[w] || sh[w] > mx) ? sh[w] : mx;
+        partial[blk] = mx;
+    }
+}
+
+// the cell (x,y,z) of sublevel m and its six neighbours: e, X = expm1(e), u, w = e^u
+struct AmrxCell {
+    float ec, Xc, uc, wc, en[6], Xn[6], un[6], wn[6];
+};
+
+__device__ __forceinline__ void amrx_gather(const LevelDev &L, const float *__restrict__ E, int blk, int m, int b,
+                                            int vol, int x, int y, int z, AmrxCell &c)
+{
+    const size_t o = (size_t)blk * vol + pidx(m, x, y, z);
+    c.ec = E[o];
+    c.uc = L.u32[m][o];
+    c.Xc = fexpm1(c.ec);
+    c.wc = fexp(c.uc);
+    const int dx[6] = {1, -1, 0, 0, 0, 0}, dy[6] = {0, 0, 1, -1, 0, 0}, dz[6] = {0, 0, 0, 0, 1, -1};
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        c.en[s] = amr_nbval(L, E, blk, m, b, vol, x + dx[s], y + dy[s], z + dz[s]);
+        c.un[s] = amr_nbval(L, (const float *)L.u32[m], blk, m, b, vol, x + dx[s], y + dy[s], z + dz[s]);
+        c.Xn[s] = fexpm1(c.en[s]);
+        c.wn[s] = fexp(c.un[s]);
+    }
+}
+
+// one colour of a float32 correction sweep on sublevel m (threads on that colour only)
+__global__ void k_amrx_sweep(LevelDev L, int m, int colour, MxConst kc)
+{
+    const int b = sub_b(m), vol = sub_vol(m);
+    const int per = b > 1 ? b * b * b / 2 : 1;
+    const size_t n = (size_t)L.nb * per;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / per), c = (int)(id % per);
+        const int ox = L.org[3 * blk] >> m, oy = L.org[3 * blk + 1] >> m, oz = L.org[3 * blk + 2] >> m;
+        int x = 0, y = 0, z = 0;
+        if (b > 1) {
+            const int hb = b >> 1;
+            x = c / (b * hb);
+            y = (c / hb) % b;
+            z = 2 * (c % hb) + ((colour + ox + oy + oz + x + y) & 1);
+        } else if (((ox + oy + oz) & 1) != colour) {
+            continue;
+        }
+        AmrxCell cell;
+        amrx_gather(L, L.e32[m], blk, m, b, vol, x, y, z, cell);
+        const size_t o = (size_t)blk * vol + pidx(m, x, y, z);
+        L.e32[m][o] = cell.ec + mx_step(cell.ec, cell.Xc, cell.uc, cell.wc, cell.en, cell.Xn, cell.un, cell.wn,
+                                        L.r32[m][o], kc);
+    }
+}
+
+// coarse interior cell of sublevel m + 1: eb = mean of the daughters' e, u32 =
+// mean of their u32, r = mean of their r - N(e)
+__global__ void k_amrx_restrict(LevelDev L, int m, MxConst kc)
+{
+    const int b = sub_b(m), vol = sub_vol(m), bc = sub_b(m + 1), volc = sub_vol(m + 1);
+    const int cells = bc * bc * bc;
+    const size_t n = (size_t)L.nb * cells;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / cells), c = (int)(id % cells);
+        const int X = c / (bc * bc), Y = (c / bc) % bc, Z = c % bc;
+        float se = 0.f, su = 0.f, sr = 0.f;
+        for (int a = 0; a < 2; ++a)
+            for (int b2 = 0; b2 < 2; ++b2)
+                for (int d = 0; d < 2; ++d) {
+                    const int x = 2 * X + a, y = 2 * Y + b2, z = 2 * Z + d;
+                    AmrxCell cell;
+                    amrx_gather(L, L.e32[m], blk, m, b, vol, x, y, z, cell);
+                    const float N = mx_value(cell.ec, cell.Xc, cell.uc, cell.wc, cell.en, cell.Xn, cell.un, cell.wn, kc);
+                    se += cell.ec;
+                    su += cell.uc;
+                    sr += L.r32[m][(size_t)blk * vol + pidx(m, x, y, z)] - N;
+                }
+        const size_t q = (size_t)blk * volc + pidx(m + 1, X, Y, Z);
+        L.eb32[m + 1][q] = 0.125f * se;
+        L.u32[m + 1][q] = 0.125f * su;
+        L.r32[m + 1][q] = 0.125f * sr;
+    }
+}
+
+// r += N_c(eb), e = eb on the interior cells of sublevel m (the FAS source)
+__global__ void k_amrx_coarse_rhs(LevelDev L, int m, MxConst kc)
+{
+    const int b = sub_b(m), vol = sub_vol(m);
+    const int cells = b * b * b;
+    const size_t n = (size_t)L.nb * cells;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / cells), c = (int)(id % cells);
+        const int x = c / (b * b), y = (c / b) % b, z = c % b;
+        AmrxCell cell;
+        amrx_gather(L, L.eb32[m], blk, m, b, vol, x, y, z, cell);
+        const size_t o = (size_t)blk * vol + pidx(m, x, y, z);
+        L.r32[m][o] += mx_value(cell.ec, cell.Xc, cell.uc, cell.wc, cell.en, cell.Xn, cell.un, cell.wn, kc);
+        L.e32[m][o] = cell.ec;
+    }
+}
+
+// e[m] += P(e[m+1] - eb[m+1]) on interior cells (linear: mode 0, injection: mode 1)
+__global__ void k_amrx_prolong(LevelDev L, int m, int mode)
+{
+    const int b = sub_b(m), vol = sub_vol(m), bc = sub_b(m + 1), volc = sub_vol(m + 1);
+    const int cells = b * b * b;
+    const size_t n = (size_t)L.nb * cells;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / cells), c = (int)(id % cells);
+        const int x = c / (b * b), y = (c / b) % b, z = c % b;
+        const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+        auto d = [&](int i, int j, int k) {
+            return amr_nbval(L, (const float *)L.e32[m + 1], blk, m + 1, bc, volc, i, j, k) -
+                   amr_nbval(L, (const float *)L.eb32[m + 1], blk, m + 1, bc, volc, i, j, k);
+        };
+        float v = d(X, Y, Z);
+        if (mode == 0) {
+            v += ((x & 1) ? 0.125f : -0.125f) * (d(X + 1, Y, Z) - d(X - 1, Y, Z));
+            v += ((y & 1) ? 0.125f : -0.125f) * (d(X, Y + 1, Z) - d(X, Y - 1, Z));
+            v += ((z & 1) ? 0.125f : -0.125f) * (d(X, Y, Z + 1) - d(X, Y, Z - 1));
+        }
+        L.e32[m][(size_t)blk * vol + pidx(m, x, y, z)] += v;
+    }
+}
+
+// u += e on the interior cells of sublevel 0
+__global__ void k_amrx_update(LevelDev L)
+{
+    const size_t n = (size_t)L.nb * 512;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(id / 512), c = (int)(id % 512);
+        const size_t o = (size_t)blk * sub_vol(0) + pidx(0, c >> 6, (c >> 3) & 7, c & 7);
+        L.u[0][o] += (double)L.e32[0][o];
+    }
+}
+
 __global__ void k_amr_copy_out(LevelDev L, double *__restrict__ out)
 {
     const size_t n = (size_t)L.nb * 512;
@@ -526,6 +708,7 @@ struct mgfr_amr {
     int nb[kMaxRef + 1] = {0, 0, 0};
     int *map[kMaxRef + 1] = {nullptr}, *org[kMaxRef + 1] = {nullptr}, *nbr[kMaxRef + 1] = {nullptr};
     double *arr[kMaxRef + 1][4][kSub] = {};  // u, f, ub, E per sublevel
+    float *arr32[kMaxRef + 1][4][kSub] = {};  // e, u, r, eb per sublevel (mixed precision only)
     std::vector<int> horg[kMaxRef + 1];
     mgfr_stats st[kMaxRef + 1];
     double beta = 0, C = 0, fbar = 0;
@@ -548,6 +731,10 @@ LevelDev level_dev(const mgfr_amr *A, int l)
         L.f[m] = A->arr[l][1][m];
         L.ub[m] = A->arr[l][2][m];
         L.E[m] = A->arr[l][3][m];
+        L.e32[m] = A->arr32[l][0][m];
+        L.u32[m] = A->arr32[l][1][m];
+        L.r32[m] = A->arr32[l][2][m];
+        L.eb32[m] = A->arr32[l][3][m];
     }
     return L;
 }
@@ -579,7 +766,10 @@ void amr_free(mgfr_amr *A)
         (void)hipFree(A->org[l]);
         (void)hipFree(A->nbr[l]);
         for (int a = 0; a < 4; ++a)
-            for (int m = 0; m < kSub; ++m) (void)hipFree(A->arr[l][a][m]);
+            for (int m = 0; m < kSub; ++m) {
+                (void)hipFree(A->arr[l][a][m]);
+                (void)hipFree(A->arr32[l][a][m]);
+            }
     }
     delete A;
 }
@@ -668,6 +858,35 @@ int amr_vcycle(mgfr_amr *A, const LevelDev &L, int m, const SubConst &K)
     return amr_sweeps(A, L, m, A->p.post_smooth, K);
 }
 
+// float32 correction V-cycle on sublevels m.. of a refined level (mixed precision)
+int amrx_vcycle(mgfr_amr *A, const LevelDev &L, int m, const MxConst *K)
+{
+    auto sweeps = [&](int mm, int count) {
+        const int b = sub_b(mm);
+        const size_t cells = (size_t)L.nb * b * b * b;
+        for (int s = 0; s < count; ++s)
+            for (int colour = 0; colour < 2; ++colour)
+                k_amrx_sweep<<<grid_of(b > 1 ? cells / 2 : cells), 256, 0, A->stream>>>(L, mm, colour, K[mm]);
+    };
+    if (m == kSub - 1) {
+        sweeps(m, A->p.coarse_sweeps);
+        MGFR_HIP(hipGetLastError());
+        return MGFR_OK;
+    }
+    sweeps(m, A->p.pre_smooth);
+    const int bc = sub_b(m + 1), b = sub_b(m);
+    const size_t cc = (size_t)L.nb * bc * bc * bc, cf = (size_t)L.nb * b * b * b;
+    k_amrx_restrict<<<grid_of(cc), 256, 0, A->stream>>>(L, m, K[m]);
+    k_amrx_coarse_rhs<<<grid_of(cc), 256, 0, A->stream>>>(L, m + 1, K[m + 1]);
+    MGFR_HIP(hipGetLastError());
+    int rc;
+    if ((rc = amrx_vcycle(A, L, m + 1, K))) return rc;
+    k_amrx_prolong<<<grid_of(cf), 256, 0, A->stream>>>(L, m, A->p.prolong);
+    sweeps(m, A->p.post_smooth);
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
+}
+
 int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
 {
     mgfr_stats &st = A->st[l];
@@ -708,22 +927,64 @@ int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
     k_amr_exchange<<<grid_of(ff), 256, 0, A->stream>>>(L, L.u[0], 0);
     MGFR_HIP(hipGetLastError());
     const double bC = A->beta * A->C, q = 1.0 / (A->p.n + 1);
-    k_amr_resnorm<<<L.nb, 512, 0, A->stream>>>(L, K.ih2[0], bC, q, A->partial);
-    double rmax;
-    if ((rc = read_max(A, L.nb, &rmax))) return rc;
-    double res = rmax / D;
-    st.res0 = res;
-    int cyc = 0, status;
-    for (;;) {
-        if (!std::isfinite(res)) { status = MGFR_ERR_NONFINITE; break; }
-        if (res <= A->p.tol) { status = MGFR_OK; break; }
-        if (cyc >= A->p.max_vcycles) { status = MGFR_NOT_CONVERGED; break; }
-        if ((rc = amr_vcycle(A, L, 0, K))) return rc;
+    int cyc = 0, status = MGFR_OK;
+    double res = 0.0, rmax = 0.0;
+    bool done = false;
+    if (A->p.precision == MGFR_MIXED) {
+        // float64 defect correction around float32 correction V-cycles; falls back
+        // to the float64 cycles from the prolonged guess after 3 consecutive
+        // residual increases or a non-finite residual
+        MxConst KM[kSub];
+        for (int m = 0; m < kSub; ++m) KM[m] = MxConst{(float)K.ih2[m], (float)bC, (float)q, (float)A->p.max_du};
+        for (int m = 0; m < kSub; ++m)
+            k_amrx_init<<<grid_of((size_t)L.nb * sub_vol(m)), 256, 0, A->stream>>>(L, m);
+        int grow = 0;
+        double prev = 0.0;
+        for (;;) {
+            k_amrx_outer<<<L.nb, 512, 0, A->stream>>>(L, K.ih2[0], bC, q, A->partial);
+            if ((rc = read_max(A, L.nb, &rmax))) return rc;
+            res = rmax / D;
+            if (cyc == 0) st.res0 = res;
+            else {
+                grow = (res > prev) ? grow + 1 : 0;
+                if (cyc - 1 < MGFR_MAX_HIST) st.res_hist[cyc - 1] = res;
+            }
+            prev = res;
+            if (!std::isfinite(res) || grow >= 3) break;  // fall back below
+            if (res <= A->p.tol) { status = MGFR_OK; done = true; break; }
+            if (cyc >= A->p.max_vcycles) { status = MGFR_NOT_CONVERGED; done = true; break; }
+            if ((rc = amrx_vcycle(A, L, 0, KM))) return rc;
+            k_amrx_update<<<grid_of((size_t)L.nb * 512), 256, 0, A->stream>>>(L);
+            k_amr_exchange<<<grid_of(ff), 256, 0, A->stream>>>(L, L.u[0], 0);
+            MGFR_HIP(hipGetLastError());
+            ++cyc;
+        }
+        if (!done) {
+            st.fell_back = 1;
+            k_amr_frozen<<<grid_of((size_t)L.nb * sub_vol(0)), 256, 0, A->stream>>>(L, Cp, l, 0);
+            k_amr_exchange<<<grid_of(ff), 256, 0, A->stream>>>(L, L.u[0], 0);
+            MGFR_HIP(hipGetLastError());
+        }
+    }
+    if (!done) {
+        const int outer = cyc;
+        cyc = 0;
         k_amr_resnorm<<<L.nb, 512, 0, A->stream>>>(L, K.ih2[0], bC, q, A->partial);
         if ((rc = read_max(A, L.nb, &rmax))) return rc;
         res = rmax / D;
-        if (cyc < MGFR_MAX_HIST) st.res_hist[cyc] = res;
-        ++cyc;
+        if (!st.fell_back) st.res0 = res;
+        for (;;) {
+            if (!std::isfinite(res)) { status = MGFR_ERR_NONFINITE; break; }
+            if (res <= A->p.tol) { status = MGFR_OK; break; }
+            if (cyc >= A->p.max_vcycles) { status = MGFR_NOT_CONVERGED; break; }
+            if ((rc = amr_vcycle(A, L, 0, K))) return rc;
+            k_amr_resnorm<<<L.nb, 512, 0, A->stream>>>(L, K.ih2[0], bC, q, A->partial);
+            if ((rc = read_max(A, L.nb, &rmax))) return rc;
+            res = rmax / D;
+            if (cyc < MGFR_MAX_HIST) st.res_hist[cyc] = res;
+            ++cyc;
+        }
+        cyc += outer;
     }
     st.vcycles = st.outer_iters = cyc;
     st.res = res;
@@ -778,7 +1039,11 @@ extern "C" int mgfr_amr_create(const mgfr_params *p, int64_t max_blocks, void *s
         M((void **)&A->org[l], (size_t)max_blocks * 3 * sizeof(int));
         M((void **)&A->nbr[l], (size_t)max_blocks * 6 * sizeof(int));
         for (int a = 0; a < 4; ++a)
-            for (int m = 0; m < kSub; ++m) M((void **)&A->arr[l][a][m], (size_t)max_blocks * sub_vol(m) * sizeof(double));
+            for (int m = 0; m < kSub; ++m) {
+                M((void **)&A->arr[l][a][m], (size_t)max_blocks * sub_vol(m) * sizeof(double));
+                if (p->precision == MGFR_MIXED)
+                    M((void **)&A->arr32[l][a][m], (size_t)max_blocks * sub_vol(m) * sizeof(float));
+            }
     }
     if (e == hipSuccess) e = hipHostMalloc(&A->hscal, 8 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return fail(hip_fail(e, "adaptive-mesh allocation", __FILE__, __LINE__));

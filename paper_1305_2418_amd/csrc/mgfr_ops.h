@@ -183,4 +183,72 @@ __device__ __forceinline__ void prolong_block(T *__restrict__ u, const T *__rest
             }
 }
 
+// ------------------------------------------------ float32 correction cycle
+// Shared by the uniform mixed-precision solve and the refined levels.
+
+struct MxConst {
+    float ih2, bC, q, max_du;
+};
+
+// e^x for the float32 correction cycle: the hardware base-2 exponential of
+// x log2(e) (relative error a few float32 ulps times |x log2 e|, which only
+// perturbs the linearisation point the float64 outer loop corrects anyway).
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
+// e^x - 1 without cancellation: Taylor series to x^6 for |x| < 1/4 (truncation
+// below 2e-8 relative), fexp(x) - 1 otherwise (at most ~5 ulp of cancellation).
+__device__ __forceinline__ float fexpm1(float x)
+{
+    const float p = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
+    const float q = fexp(x) - 1.0f;  // evaluated unconditionally: a select, not a branch
+    return __builtin_amdgcn_fmed3f(fabsf(x), 0.0f, 0.25f) < 0.25f ? p : q;
+}
+
+// Newton step on e at one cell from precomputed per-cell quantities:
+//   centre: e, X = expm1(e), u, w = e^u; neighbours likewise.
+__device__ __forceinline__ float mx_step(float ec, float Xc, float uc, float wc, const float en[6],
+                                         const float Xn[6], const float un[6], const float wn[6], float r,
+                                         const MxConst &k)
+{
+    float Su = 0.f, Se = 0.f, A = 0.f, B = 0.f, SW = 0.f;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const float du = un[t] - uc, de = en[t] - ec;
+        const float Wn = wn[t] + wn[t] * Xn[t];
+        Su += du;
+        Se += de;
+        A += wn[t] * Xn[t] * du;
+        B += Wn * de;
+        SW += Wn;
+    }
+    const float wXc = wc * Xc, Wc = wc + wXc;
+    const float flux = 0.5f * ((A + wXc * Su) + (B + Wc * Se));
+    const float dflux = 0.5f * (Wc * (Su + Se - 6.0f) - SW);
+    const float sc = fexp(-k.q * uc);
+    const float cm = fexpm1(-k.q * ec);
+    const float N = k.ih2 * flux + k.bC * sc * cm;
+    const float J = k.ih2 * dflux - k.q * k.bC * sc * (1.0f + cm);
+    float d = -(N - r) / J;
+    if (k.max_du > 0.f) d = fminf(fmaxf(d, -k.max_du), k.max_du);
+    return d;
+}
+
+__device__ __forceinline__ float mx_value(float ec, float Xc, float uc, float wc, const float en[6],
+                                          const float Xn[6], const float un[6], const float wn[6],
+                                          const MxConst &k)
+{
+    float Su = 0.f, Se = 0.f, A = 0.f, B = 0.f;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const float du = un[t] - uc, de = en[t] - ec;
+        Su += du;
+        Se += de;
+        A += wn[t] * Xn[t] * du;
+        B += (wn[t] + wn[t] * Xn[t]) * de;
+    }
+    const float wXc = wc * Xc, Wc = wc + wXc;
+    const float flux = 0.5f * ((A + wXc * Su) + (B + Wc * Se));
+    return k.ih2 * flux + k.bC * fexp(-k.q * uc) * fexpm1(-k.q * ec);
+}
+
 }  // namespace mgfr

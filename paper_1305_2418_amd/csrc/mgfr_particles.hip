@@ -187,52 +187,29 @@ __global__ __launch_bounds__(kBlock) void k_fr(const double *__restrict__ u, dou
         fr[t] = -fbar * exp(u[t]);
 }
 
-// a = pref * sum_cells w_cell * (f_R[+d] - f_R[-d]) / (2h)
-// Particles are visited in the order perm (the binning's tile order) when it
-// is given, else in index order; each particle's result is the same either way.
-__global__ __launch_bounds__(kBlock) void k_force_gather(const double *__restrict__ fr, const float *__restrict__ pos,
-                                                           const uint32_t *__restrict__ perm, int64_t np, int lg,
-                                                           double h, double pref, float *__restrict__ acc,
-                                                           int *__restrict__ flag)
+// Gradient sum g = sum_cells w_cell (f_R[+d] - f_R[-d]) at a particle with CIC
+// fractions (tx, ty, tz), f_R read through get(di, dj, dk) = f_R at the lower
+// CIC corner + (di, dj, dk), di in -1..2: the 32 distinct cells of the eight
+// central differences (the 2x2x2 block and one layer beyond it on each side).
+template <class G>
+__device__ __forceinline__ void grad_sum(G get, double tx, double ty, double tz, double &gx, double &gy, double &gz)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= np) return;
-    const int64_t p = perm ? (int64_t)perm[i] : i;
-    const int mask = (1 << lg) - 1;
-    int i0, j0, k0;
-    double tx, ty, tz;
-    bool ok = cic_axis(pos[3 * p + 0], h, mask, i0, tx) && cic_axis(pos[3 * p + 1], h, mask, j0, ty) &&
-              cic_axis(pos[3 * p + 2], h, mask, k0, tz);
-    if (!ok) {
-        flag[0] = 1;
-        const float nan = __builtin_nanf("");
-        acc[3 * p + 0] = nan;
-        acc[3 * p + 1] = nan;
-        acc[3 * p + 2] = nan;
-        return;
-    }
     const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
-    // the 32 distinct cells the eight central differences need: the 2x2x2
-    // block B and one layer beyond it on each side along each axis
-    const int ix4[4] = {(i0 - 1) & mask, i0, (i0 + 1) & mask, (i0 + 2) & mask};
-    const int jx4[4] = {(j0 - 1) & mask, j0, (j0 + 1) & mask, (j0 + 2) & mask};
-    const int kx4[4] = {(k0 - 1) & mask, k0, (k0 + 1) & mask, (k0 + 2) & mask};
-    auto at = [&](int i, int j, int k) { return fr[((((size_t)i << lg) + j) << lg) + k]; };
-    double B[2][2][2], X[2][2][2], Y[2][2][2], Z[2][2][2];  // X[s][b][c]: x layer s (0: i0-1, 1: i0+2)
+    double B[2][2][2], X[2][2][2], Y[2][2][2], Z[2][2][2];  // X[s][b][c]: x layer s (0: -1, 1: +2)
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
 #pragma unroll
-            for (int c = 0; c < 2; ++c) B[a][b][c] = at(ix4[a + 1], jx4[b + 1], kx4[c + 1]);
-            X[0][a][b] = at(ix4[0], jx4[a + 1], kx4[b + 1]);
-            X[1][a][b] = at(ix4[3], jx4[a + 1], kx4[b + 1]);
-            Y[0][a][b] = at(ix4[a + 1], jx4[0], kx4[b + 1]);
-            Y[1][a][b] = at(ix4[a + 1], jx4[3], kx4[b + 1]);
-            Z[0][a][b] = at(ix4[a + 1], jx4[b + 1], kx4[0]);
-            Z[1][a][b] = at(ix4[a + 1], jx4[b + 1], kx4[3]);
+            for (int c = 0; c < 2; ++c) B[a][b][c] = get(a, b, c);
+            X[0][a][b] = get(-1, a, b);
+            X[1][a][b] = get(2, a, b);
+            Y[0][a][b] = get(a, -1, b);
+            Y[1][a][b] = get(a, 2, b);
+            Z[0][a][b] = get(a, b, -1);
+            Z[1][a][b] = get(a, b, 2);
         }
-    double gx = 0.0, gy = 0.0, gz = 0.0;
+    gx = gy = gz = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -248,10 +225,144 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const double *__restric
                 gy += w * (yp - ym);
                 gz += w * (zp - zm);
             }
+}
+
+__device__ __forceinline__ void store_nan3(float *__restrict__ acc, int64_t p)
+{
+    const float nan = __builtin_nanf("");
+    acc[3 * p + 0] = nan;
+    acc[3 * p + 1] = nan;
+    acc[3 * p + 2] = nan;
+}
+
+// a = pref * sum_cells w_cell * (f_R[+d] - f_R[-d]) / (2h), f_R from global memory.
+// Particles are visited in the order perm (the binning's tile order) when it
+// is given, else in index order; each particle's result is the same either way.
+__global__ __launch_bounds__(kBlock) void k_force_gather(const double *__restrict__ fr, const float *__restrict__ pos,
+                                                           const uint32_t *__restrict__ perm, int64_t np, int lg,
+                                                           double h, double pref, float *__restrict__ acc,
+                                                           int *__restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= np) return;
+    const int64_t p = perm ? (int64_t)perm[i] : i;
+    const int mask = (1 << lg) - 1;
+    int i0, j0, k0;
+    double tx, ty, tz;
+    if (!(cic_axis(pos[3 * p + 0], h, mask, i0, tx) && cic_axis(pos[3 * p + 1], h, mask, j0, ty) &&
+          cic_axis(pos[3 * p + 2], h, mask, k0, tz))) {
+        flag[0] = 1;
+        store_nan3(acc, p);
+        return;
+    }
+    double gx, gy, gz;
+    grad_sum([&](int di, int dj, int dk) {
+        return fr[(((((size_t)((i0 + di) & mask)) << lg) + (size_t)((j0 + dj) & mask)) << lg) +
+                  (size_t)((k0 + dk) & mask)];
+    }, tx, ty, tz, gx, gy, gz);
     const double s = pref / (2.0 * h);
     acc[3 * p + 0] = (float)(s * gx);
     acc[3 * p + 1] = (float)(s * gy);
     acc[3 * p + 2] = (float)(s * gz);
+}
+
+constexpr int kFW = (1 << kBinLg) + 3;  // f_R window edge: a tile plus one cell below and two above
+constexpr int kFW3 = kFW * kFW * kFW;
+constexpr int kFWinMin = 48;             // shorter runs read f_R from global memory
+
+// The fifth force for binned particles: the same chunks and tile runs as the
+// binned assignment; a run of at least kFWinMin particles first stages the
+// tile's f_R window (11^3 values) in LDS and gathers from there.  A particle
+// whose current position is not in the run's tile (positions changed since
+// the assignment) is gathered from global memory, so any positions give the
+// same result as k_force_gather.
+__global__ __launch_bounds__(kBlock) void k_force_binned(const double *__restrict__ fr, const float *__restrict__ pos,
+                                                           const uint32_t *__restrict__ key_s,
+                                                           const uint32_t *__restrict__ perm, int64_t np, int lg,
+                                                           double h, double pref, float *__restrict__ acc,
+                                                           int *__restrict__ flag)
+{
+    __shared__ double win[kFW3];
+    __shared__ int red[kBlock / 64];
+    // the chunk's slots (sorted order), kept in LDS so that the slot loop need
+    // not be unrolled (two 32-load gathers per slot would not fit in registers)
+    __shared__ uint32_t skey[kCicPer][kBlock], spid[kCicPer][kBlock];
+    __shared__ float spos[kCicPer][3][kBlock];
+    const int tid = threadIdx.x;
+    const int64_t start = (int64_t)blockIdx.x * kCicChunk;
+    const int64_t end = start + kCicChunk < np ? start + kCicChunk : np;
+    const int mask = (1 << lg) - 1, tl = lg - kBinLg, tmask = (1 << tl) - 1;
+    const double s = pref / (2.0 * h);
+    for (int q = 0; q < kCicPer; ++q) {
+        const int64_t i = start + tid + (int64_t)q * kBlock;
+        uint32_t k = 0xffffffffu, pp = 0;
+        float x = 0.f, y = 0.f, z = 0.f;
+        if (i < end) {
+            k = key_s[i];
+            pp = perm[i];
+            x = pos[3 * (size_t)pp + 0];
+            y = pos[3 * (size_t)pp + 1];
+            z = pos[3 * (size_t)pp + 2];
+        }
+        skey[q][tid] = k;
+        spid[q][tid] = pp;
+        spos[q][0][tid] = x;
+        spos[q][1][tid] = y;
+        spos[q][2][tid] = z;
+    }
+    int64_t cur = start;
+    while (cur < end) {
+        const uint32_t t = key_s[cur];
+        int cnt = 0;
+        for (int q = 0; q < kCicPer; ++q) cnt += skey[q][tid] <= t ? 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = cnt;
+        __syncthreads();
+        int total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) total += red[w];
+        const int64_t rend = start + total > cur ? start + total : cur + 1;
+        const bool use_win = rend - cur >= kFWinMin;  // uniform over the workgroup
+        const int ti = (int)(t >> (2 * tl)) << kBinLg, tj = (int)((t >> tl) & tmask) << kBinLg,
+                  tk = (int)(t & tmask) << kBinLg;
+        if (use_win)
+            for (int e = tid; e < kFW3; e += kBlock) {
+                const int a = e / (kFW * kFW), b = (e / kFW) % kFW, c = e % kFW;
+                win[e] = fr[(((((size_t)((ti - 1 + a) & mask)) << lg) + (size_t)((tj - 1 + b) & mask)) << lg) +
+                            (size_t)((tk - 1 + c) & mask)];
+            }
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < kCicPer; ++q) {
+            if (skey[q][tid] != t) continue;
+            const int64_t p = spid[q][tid];
+            int i0, j0, k0;
+            double tx, ty, tz;
+            if (!(cic_axis(spos[q][0][tid], h, mask, i0, tx) && cic_axis(spos[q][1][tid], h, mask, j0, ty) &&
+                  cic_axis(spos[q][2][tid], h, mask, k0, tz))) {
+                flag[0] = 1;
+                store_nan3(acc, p);
+                continue;
+            }
+            const int a0 = i0 - ti, b0 = j0 - tj, c0 = k0 - tk;
+            double gx, gy, gz;
+            if (use_win && (unsigned)a0 < (1u << kBinLg) && (unsigned)b0 < (1u << kBinLg) &&
+                (unsigned)c0 < (1u << kBinLg)) {
+                grad_sum([&](int di, int dj, int dk) { return win[((a0 + di + 1) * kFW + (b0 + dj + 1)) * kFW + (c0 + dk + 1)]; },
+                         tx, ty, tz, gx, gy, gz);
+            } else {
+                grad_sum([&](int di, int dj, int dk) {
+                    return fr[(((((size_t)((i0 + di) & mask)) << lg) + (size_t)((j0 + dj) & mask)) << lg) +
+                              (size_t)((k0 + dk) & mask)];
+                }, tx, ty, tz, gx, gy, gz);
+            }
+            acc[3 * p + 0] = (float)(s * gx);
+            acc[3 * p + 1] = (float)(s * gy);
+            acc[3 * p + 2] = (float)(s * gz);
+        }
+        __syncthreads();
+        cur = rend;
+    }
 }
 
 inline unsigned grid_for(size_t n, size_t cap) { return (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, cap); }
@@ -311,9 +422,13 @@ extern "C" int mgfr_fifth_force(mgfr_ctx *c, const double *u, const float *pos, 
     const size_t pblocks = (size_t)((np + kBlock - 1) / kBlock);
     if (pblocks > 0x7fffffffULL) return set_error(MGFR_ERR_ARG, "np too large");
     const double pref = kCkms * kCkms / (2.0 * c->p.a);
-    const uint32_t *perm = (c->perm_np == np && c->perm) ? c->perm : nullptr;
-    k_force_gather<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(fr, pos, perm, np, L0.lg, L0.h, pref, acc,
-                                                                 c->dflag);
+    if (c->perm_np == np && c->perm) {
+        k_force_binned<<<(unsigned)((np + kCicChunk - 1) / kCicChunk), kBlock, 0, c->stream>>>(
+            fr, pos, c->bkey_s, c->perm, np, L0.lg, L0.h, pref, acc, c->dflag);
+    } else {
+        k_force_gather<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(fr, pos, nullptr, np, L0.lg, L0.h, pref, acc,
+                                                                     c->dflag);
+    }
     MGFR_HIP(hipGetLastError());
     int *hflag = (int *)(c->hscal + 6);
     MGFR_HIP(hipMemcpyAsync(hflag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));

@@ -290,15 +290,20 @@ def main():
     copy_gbs = measure_copy(dev, log)
     mfma = measure_mfma(N, dev, log)
     # dominant kernel of the headline mode: the finest-level smoothing sweep
+    # algorithmic bytes of a red-black sweep: float64, read u and f, write u
+    # (24 B/cell); float32 correction sweep, read e, r and u, write e (16 B/cell)
     if args.mode == "fp64":
-        kernel, bpc = ("k_sweep_fused" if N >= 512 else "k_sweep_half (x2 per sweep)"), 24.0
+        kernel, bpc, design_bpc = ("k_sweep_fused" if N >= 512 else "k_sweep_half (x2 per sweep)"), 24.0, 24.0
         src = KERNEL_SRC["fp64"]
     else:
-        # one colour pass: read u and e of every cell, r of the updated half, write the updated half (float32)
-        kernel, bpc = "k_mx_colour (x2 per sweep)", 12.0
+        # one colour pass is half a sweep (8 B/cell of the sweep's 16); by its own
+        # design it reads u and e of every cell, r of the updated half and
+        # writes that half (12 B/cell)
+        kernel, bpc, design_bpc = "k_mx_colour (x2 per sweep)", 8.0, 12.0
         src = KERNEL_SRC["mixed"]
     alg_bytes = bpc * N ** 3
     achieved = alg_bytes / (head["sweep_launch_ms"] * 1e-3) / 1e9
+    design_GBs = design_bpc * N ** 3 / (head["sweep_launch_ms"] * 1e-3) / 1e9
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if os.path.exists(tpath):
@@ -331,7 +336,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                      "launch_ms": head["sweep_launch_ms"], "alg_bytes_per_launch": alg_bytes,
-                     "achievable_GBs": copy_gbs, "frac_of_achievable": achieved / copy_gbs},
+                     "achievable_GBs": copy_gbs, "frac_of_achievable": achieved / copy_gbs,
+                     "design_bytes_per_launch": design_bpc * N ** 3, "design_GBs": design_GBs,
+                     "counted_GBs": traffic / (head["sweep_launch_ms"] * 1e-3) / 1e9 if traffic else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, log)

@@ -141,6 +141,17 @@ int mgfr_set_fused_min_mesh(mgfr_ctx *ctx, int n);
  * order; results agree to float32 rounding. */
 int mgfr_set_colour_min_mesh(mgfr_ctx *ctx, int n);
 
+/* Float32 correction sweeps on the levels that use the pass kernels (see
+ * mgfr_set_colour_min_mesh): on = 1 runs each red-black sweep (Sec. 3.3) as
+ * one fused, out-of-place kernel that updates the red cells of plane i + 1
+ * and then the black cells of plane i while marching over the planes, so
+ * that e, u and r are read once per sweep instead of once per colour; on = 0
+ * (default) runs one pass kernel per colour.  The same updates in the same
+ * red-black order; results agree to float32 rounding.  The second correction
+ * buffer is allocated by mgfr_create for mixed-precision contexts, so this
+ * call allocates nothing.  Errors: MGFR_ERR_ARG for on not 0 or 1. */
+int mgfr_set_fused_sweep32(mgfr_ctx *ctx, int on);
+
 /* Cloud-in-cell assignment (Sec. 3.1) of np particles onto the N^3 mesh and
  * delta = m / m_bar - 1 with m_bar the mean cell mass of the assignment.
  * pos: float32 [np][3]; mass: float64 [np] or NULL for equal masses;

@@ -35,6 +35,7 @@ struct Level {
     double *alt = nullptr;  // second buffer of out-of-place sweeps (current iterate is u)
     // float32 mirrors for the mixed-precision inner cycle
     float *e32 = nullptr, *r32 = nullptr, *u32 = nullptr, *ebar32 = nullptr;
+    float *e32alt = nullptr;  // second e buffer of the fused float32 sweep (levels with N >= 128)
 };
 
 struct Timer {
@@ -54,6 +55,7 @@ struct mgfr_ctx {
     double *alt0 = nullptr;  // level-0 second buffer (owned)
     int fused_min_n = 512;   // levels with N >= this use the fused out-of-place sweep (0: never)
     int colour32_min_n = 128; // float32 sweeps on levels with N >= this by one-colour pass kernels (0: never)
+    int fused32 = 0;          // those sweeps as one fused red-black kernel per sweep instead
     // reduction scratch
     double *partial = nullptr;  // [2 * nparts]
     int nparts = 0;

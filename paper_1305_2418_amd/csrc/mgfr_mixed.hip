@@ -241,6 +241,10 @@ __device__ __forceinline__ float mx_prolong(const float *__restrict__ ec, const 
 #define MGFR_CTJ 8
 #endif
 constexpr int CTJ = MGFR_CTJ;  // updated rows per workgroup (the last row tile may be partial)
+#ifndef MGFR_CHUNKS
+#define MGFR_CHUNKS 8
+#endif
+constexpr int kChunks = MGFR_CHUNKS;  // plane chunks along i per pass (N / kChunks planes each)
 constexpr int CKW = 128;  // cells per row tile
 constexpr int CLW = 66;   // LDS row: 64 lanes and one halo slot on each side
 
@@ -417,6 +421,202 @@ __global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour(ColourArgs A)
         mx_colour_rows<1>(A, i0, j0, k0, wv, lane, sB);
     else
         mx_colour_rows<0>(A, i0, j0, k0, wv, lane, sB);
+}
+
+// ------------------------------------------- fused red-black sweep (N >= 128)
+//
+// One whole float32 correction sweep (red cells, then black cells) in one
+// launch, out of place: eout = sweep(ein) on a split level (see sx).  A
+// workgroup owns FI = FW - 4 rows of a 128-cell row tile and marches over
+// `chunk` planes; in step p it updates the red cells of plane p + 1 and then
+// the black cells of plane p, which by then have all six red neighbours new.
+// The black update of an edge row needs red updates one row beyond the tile,
+// which need the old black values of the row after that, so the workgroup has
+// one wave per row for FI + 4 rows: the outer two only load, the next two
+// update their red cells as well (results kept in LDS, not stored).  In k the
+// same holds for the cells k0 - 1 and k0 + 128: the first wave (an outer row)
+// also loads the cells k0 - 2, k0 - 1, k0 + 128, k0 + 129 of every row (one
+// lane each) and updates the red ones of the inner rows.  The chunk starts two
+// planes early for the same reason in i.
+//
+// Lane l of a row wave holds the cells k0 + 2l, k0 + 2l + 1; on plane p + 1
+// the red one is column s = (p + 1 + j) & 1, and on plane p that same column
+// is black, so each lane does one red and one black update per step.  LDS
+// holds three planes (p, p + 1 and the one being filled) as P/W cells by row,
+// column parity and pair slot (slot 0 and 65: the k-halo cells).  Every cell
+// of ein, u and r is read once and every cell of eout written once (16 B per
+// cell and sweep) apart from the halo rows, which come mostly from L2.
+
+#ifndef MGFR_FW
+#define MGFR_FW 16
+#endif
+constexpr int FW = MGFR_FW;  // waves (rows) per workgroup
+constexpr int FI = FW - 4;   // rows updated and stored
+constexpr int FS = 66;       // LDS slots per row and column parity
+static_assert(4 * FW <= 64, "the k-halo cells of all rows are served by one wave");
+
+struct Sweep2Args {
+    const float *ein;
+    float *eout;
+    const float *u, *r;
+    int lg, chunk;
+    MxConst kc;
+};
+
+template <int S0>
+__device__ __forceinline__ void mx_sweep2_rows(const Sweep2Args &A, int i0, int j0, int k0, int w, int lane,
+                                               float4 *sX)
+{
+    const int lg = A.lg, m = (1 << lg) - 1;
+    const size_t hN = (size_t)1 << (lg - 1), plane = (size_t)1 << (2 * lg);
+    const int jg = (j0 + w - 2) & m;
+    const bool red_row = w >= 1 && w <= FW - 2;                          // uniform over the wave
+    const bool blk_row = w >= 2 && w <= FW - 3 && j0 + w - 2 <= m;      // rows stored
+    const size_t rowb = (size_t)jg << lg, kh2 = (size_t)(k0 / 2 + lane);
+    auto pb = [&](int pl) { return (size_t)(pl & m) * plane + rowb; };
+    auto ldu = [&](int pl) { return *reinterpret_cast<const float2 *>(A.u + pb(pl) + (size_t)k0 + 2 * lane); };
+    // cell k0 + 2l lies in half (pl + jg) & 1 of its row (k0 is even)
+    auto lde = [&](int pl) {
+        const size_t b = pb(pl) + kh2;
+        const bool odd = ((pl + jg) & 1) != 0;
+        return make_float2(A.ein[b + (odd ? hN : 0)], A.ein[b + (odd ? 0 : hN)]);
+    };
+    // k-halo duty of the first wave: lane = 4 row + c, c -> k0 - 2, k0 - 1, k0 + 128, k0 + 129
+    const bool hv = w == 0 && lane < 4 * FW;
+    const int hl = lane % (4 * FW), hw = hl >> 2, hc = hl & 3;
+    const int hjg = (j0 + hw - 2) & m;
+    const int hk = (hc < 2 ? k0 - 2 + hc : k0 + 126 + hc) & m;
+    const int hpar = hc & 1, hslot = hc < 2 ? 0 : FS - 1;
+    const bool hin = hv && (hc == 1 || hc == 2) && hw >= 2 && hw <= FW - 3;
+    const size_t hrow = (size_t)hjg << lg;
+    auto hb = [&](int pl) { return (size_t)(pl & m) * plane + hrow; };
+    auto at = [&](int buf, int row, int par, int slot) { return ((buf * FW + row) * 2 + par) * FS + slot; };
+
+    // raw loads of step p, issued one step ahead in two alternating register sets
+    struct Raw {
+        float2 u, e;     // plane p + 2
+        float rr, rb;    // r of the red cell of plane p + 1, of the black cell of plane p
+        float hu, he, hr;  // k-halo cell: u, e of plane p + 2, r of plane p + 1 (red half)
+    };
+    auto load = [&](int p) {
+        Raw x;
+        x.u = ldu(p + 2);
+        x.e = lde(p + 2);
+        x.rr = A.r[pb(p + 1) + kh2];
+        x.rb = A.r[pb(p) + hN + kh2];
+        x.hu = A.u[hb(p + 2) + (size_t)hk];
+        x.he = A.ein[hb(p + 2) + ((size_t)(((p + 2) + hjg + hk) & 1) << (lg - 1)) + (size_t)(hk >> 1)];
+        x.hr = A.r[hb(p + 1) + (size_t)(hk >> 1)];
+        return x;
+    };
+
+    // planes i0 - 2 (P0) and i0 - 1 (P1), old values; the k-halo cell of plane
+    // p is read back from LDS, that of plane p + 1 is kept in H1
+    Cell4 P0[2], P1[2], prev, H1;
+    {
+        const float2 ua = ldu(i0 - 2), ea = lde(i0 - 2), ub = ldu(i0 - 1), eb = lde(i0 - 1);
+        P0[0] = mx_cell(ua.x, ea.x);
+        P0[1] = mx_cell(ua.y, ea.y);
+        P1[0] = mx_cell(ub.x, eb.x);
+        P1[1] = mx_cell(ub.y, eb.y);
+        prev = P0[0];
+        const int pa = i0 - 2, pq = i0 - 1;
+        const Cell4 H0 = mx_cell(A.u[hb(pa) + (size_t)hk],
+                                 A.ein[hb(pa) + ((size_t)((pa + hjg + hk) & 1) << (lg - 1)) + (size_t)(hk >> 1)]);
+        if (hv) sX[at(0, hw, hpar, hslot)] = pack(H0);  // ordered by the first step's barrier
+        H1 = mx_cell(A.u[hb(pq) + (size_t)hk],
+                     A.ein[hb(pq) + ((size_t)((pq + hjg + hk) & 1) << (lg - 1)) + (size_t)(hk >> 1)]);
+    }
+    Raw ra = load(i0 - 2), rb;
+    int x0 = 0, x1 = 1, x2 = 2;  // LDS buffers of planes p, p + 1, p + 2
+    const int iend = i0 + A.chunk;
+
+    auto step = [&](int p, auto Sc, auto Bc, const Raw &cur, Raw &nxt) {
+        constexpr int S = decltype(Sc)::value;
+        constexpr bool BLACK = decltype(Bc)::value;
+        nxt = load(p + 1);
+        const Cell4 Q0 = mx_cell(cur.u.x, cur.e.x), Q1 = mx_cell(cur.u.y, cur.e.y);
+        const Cell4 &QS = S ? Q1 : Q0;
+        Cell4 HQ = H1;
+        if (w == 0) HQ = mx_cell(cur.hu, cur.he);
+        // publish the old black cell of plane p + 1 (and the k-halo cells)
+        sX[at(x1, w, 1 - S, lane + 1)] = pack(P1[1 - S]);
+        if (hv) sX[at(x1, hw, hpar, hslot)] = pack(H1);
+        __syncthreads();
+        // red cell of plane p + 1: neighbours black and old
+        if (red_row) {
+            const Cell4 sd = unpack(S ? sX[at(x1, w, 0, lane + 2)] : sX[at(x1, w, 1, lane)]);
+            const Cell4 up = unpack(sX[at(x1, w - 1, S, lane + 1)]);
+            const Cell4 dn = unpack(sX[at(x1, w + 1, S, lane + 1)]);
+            const float en = mx_update(P1[S], cur.rr, P1[1 - S], sd, up, dn, P0[S], QS, A.kc);
+            P1[S] = mx_cell(P1[S].u, en);
+            sX[at(x1, w, S, lane + 1)] = pack(P1[S]);
+            if (blk_row && p + 1 >= i0 && p + 1 < iend) A.eout[pb(p + 1) + kh2] = en;
+        }
+        if (w == 0) {
+            // red k-halo cells of the stored rows
+            if (hin && (((p + 1) + hjg + hk) & 1) == 0) {
+                const Cell4 na = unpack(hc == 1 ? sX[at(x1, hw, 0, 0)] : sX[at(x1, hw, 1, FS - 1)]);
+                const Cell4 nb = unpack(hc == 1 ? sX[at(x1, hw, 0, 1)] : sX[at(x1, hw, 1, FS - 2)]);
+                const Cell4 up = unpack(sX[at(x1, hw - 1, hpar, hslot)]);
+                const Cell4 dn = unpack(sX[at(x1, hw + 1, hpar, hslot)]);
+                const Cell4 H0 = unpack(sX[at(x0, hw, hpar, hslot)]);
+                const float en = mx_update(H1, cur.hr, na, nb, up, dn, H0, HQ, A.kc);
+                H1 = mx_cell(H1.u, en);
+                sX[at(x1, hw, hpar, hslot)] = pack(H1);
+            }
+        }
+        // black cell of plane p: neighbours red and new (plane p's buffer was
+        // completed in the previous step)
+        if (BLACK && blk_row) {
+            const Cell4 sd = unpack(S ? sX[at(x0, w, 0, lane + 2)] : sX[at(x0, w, 1, lane)]);
+            const Cell4 up = unpack(sX[at(x0, w - 1, S, lane + 1)]);
+            const Cell4 dn = unpack(sX[at(x0, w + 1, S, lane + 1)]);
+            A.eout[pb(p) + hN + kh2] = mx_update(P0[S], cur.rb, P0[1 - S], sd, up, dn, prev, P1[S], A.kc);
+        }
+        prev = P0[1 - S];
+        P0[0] = P1[0];
+        P0[1] = P1[1];
+        P1[0] = Q0;
+        P1[1] = Q1;
+        H1 = HQ;
+        const int t = x0;
+        x0 = x1;
+        x1 = x2;
+        x2 = t;
+    };
+    using Z0 = std::integral_constant<int, S0>;
+    using Z1 = std::integral_constant<int, 1 - S0>;
+    using NB = std::integral_constant<bool, false>;
+    using YB = std::integral_constant<bool, true>;
+    step(i0 - 2, Z0{}, NB{}, ra, rb);
+    step(i0 - 1, Z1{}, NB{}, rb, ra);
+    for (int p = i0; p < iend; p += 2) {  // chunk is even
+        step(p, Z0{}, YB{}, ra, rb);
+        step(p + 1, Z1{}, YB{}, rb, ra);
+    }
+}
+
+// grid: 1-D, (N / 128) ceil(N / FI) (N / chunk) workgroups, spread over the
+// XCDs as in the colour pass
+__global__ __launch_bounds__(64 * FW) void k_mx_sweep2(Sweep2Args A)
+{
+    __shared__ float4 sX[3 * FW * 2 * FS];
+    const int lg = A.lg;
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned L = (b & 7u) * (nb >> 3) + (b >> 3);  // nb is a multiple of 8
+    const int nkt = (1 << lg) / CKW, njt = ((1 << lg) + FI - 1) / FI;
+    const int kt = (int)(L % (unsigned)nkt), jt = (int)((L / (unsigned)nkt) % (unsigned)njt),
+              it = (int)(L / ((unsigned)nkt * (unsigned)njt));
+    const int k0 = kt * CKW, j0 = jt * FI, i0 = it * A.chunk;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    // red column of this wave's row on plane i0 - 1 (step i0 - 2)
+    const int s0 = (i0 - 1 + j0 + w - 2) & 1;
+    if (s0)
+        mx_sweep2_rows<1>(A, i0, j0, k0, w, lane, sX);
+    else
+        mx_sweep2_rows<0>(A, i0, j0, k0, w, lane, sX);
 }
 
 // ------------------------------------------------- restriction pass (N >= 128)
@@ -978,9 +1178,16 @@ int mx_launch_sweeps(mgfr_ctx *c, int l, int sweeps, bool timed)
     const bool colour_pass = split_level(c, l);
     int slot, rc;
     for (int s = 0; s < sweeps; ++s) {
-        if (colour_pass) {
-            const int chunk = L.N / 8;
-            const unsigned nb = (unsigned)((L.N / CKW) * ((L.N + CTJ - 1) / CTJ) * (L.N / chunk));
+        if (colour_pass && c->fused32 && L.e32alt) {
+            const int chunk = L.N / kChunks;
+            const unsigned nbf = (unsigned)((L.N / CKW) * ((L.N + FI - 1) / FI) * kChunks);
+            if ((rc = timer_slot(c, timed, slot))) return rc;
+            k_mx_sweep2<<<nbf, 64 * FW, 0, c->stream>>>(Sweep2Args{L.e32, L.e32alt, L.u32, L.r32, L.lg, chunk, kc});
+            if ((rc = timer_end(c, slot))) return rc;
+            std::swap(L.e32, L.e32alt);
+        } else if (colour_pass) {
+            const int chunk = L.N / kChunks;
+            const unsigned nb = (unsigned)((L.N / CKW) * ((L.N + CTJ - 1) / CTJ) * kChunks);
             for (int colour = 0; colour < 2; ++colour) {
                 if ((rc = timer_slot(c, timed, slot))) return rc;
                 k_mx_colour<<<nb, 64 * (CTJ + 2), 0, c->stream>>>(ColourArgs{L.e32, L.u32, L.r32, L.lg, colour, chunk, kc});
@@ -1062,6 +1269,7 @@ int mixed_alloc(mgfr_ctx *c)
         MGFR_HIP(hipMalloc(&L.r32, bytes));
         MGFR_HIP(hipMalloc(&L.u32, bytes));
         if (l > 0) MGFR_HIP(hipMalloc(&L.ebar32, bytes));
+        if (L.N >= CKW) MGFR_HIP(hipMalloc(&L.e32alt, bytes));
     }
     return MGFR_OK;
 }

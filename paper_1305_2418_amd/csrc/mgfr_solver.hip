@@ -717,6 +717,7 @@ static void free_ctx(mgfr_ctx *c)
         (void)hipFree(L.r32);
         (void)hipFree(L.u32);
         (void)hipFree(L.ebar32);
+        (void)hipFree(L.e32alt);
     }
     (void)hipFree(c->alt0);
     (void)hipFree(c->partial);
@@ -960,6 +961,16 @@ extern "C" int mgfr_set_colour_min_mesh(mgfr_ctx *c, int n)
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
     if (n != 0 && n < 128) return set_error(MGFR_ERR_ARG, "one-colour pass kernels need levels of at least 128^3 (or 0 = off)");
     c->colour32_min_n = n;
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_set_fused_sweep32(mgfr_ctx *c, int on)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (on != 0 && on != 1) return set_error(MGFR_ERR_ARG, "on must be 0 or 1");
+    if (on && c->p.precision == MGFR_MIXED && c->lev[0].N >= 128 && !c->lev[0].e32alt)
+        return set_error(MGFR_ERR_ARG, "no second correction buffer (the context was not created for mixed precision)");
+    c->fused32 = on;
     return MGFR_OK;
 }
 

@@ -122,6 +122,7 @@ def lib() -> C.CDLL:
         L.mgfr_set_timing.argtypes = [_VP, C.c_int]
         L.mgfr_set_fused_min_mesh.argtypes = [_VP, C.c_int]
         L.mgfr_set_colour_min_mesh.argtypes = [_VP, C.c_int]
+        L.mgfr_set_fused_sweep32.argtypes = [_VP, C.c_int]
         L.mgfr_assign_density.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
         L.mgfr_reserve_particles.argtypes = [_VP, C.c_int64]
         L.mgfr_set_binning.argtypes = [_VP, C.c_int]
@@ -239,6 +240,10 @@ class Solver:
 
     def set_colour_min_mesh(self, n: int):
         _check(lib().mgfr_set_colour_min_mesh(self._h, int(n)))
+
+    def set_fused_sweep32(self, on: bool):
+        """Float32 correction sweeps as one fused red-black kernel per sweep."""
+        _check(lib().mgfr_set_fused_sweep32(self._h, int(bool(on))))
 
     def reserve_particles(self, max_np: int):
         """Allocate the particle-binning workspace for up to max_np particles."""

@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 WEIGHTS = os.path.join(ROOT, "paper_1305_2418_amd", "weights", "unet_warmstart.npy")
-MODES = ("fp64", "mixed", "mixed_nn")
+MODES = ("fp64", "mixed", "mixed_nn", "mixed_scr", "fp64_scr")
 
 
 def parse():
@@ -43,13 +43,14 @@ def parse():
     ap.add_argument("--prolong", choices=["inject", "linear"], default="inject",
                     help="coarse-to-fine transfer of the correction (both are the paper's options)")
     ap.add_argument("--mode", choices=MODES, default="mixed_nn", help="headline mode")
-    ap.add_argument("--compare", default="fp64,mixed", help="other modes timed in the same run")
+    ap.add_argument("--compare", default="fp64,mixed,mixed_scr",
+                    help="other modes timed in the same run (_scr: from the screened-limit initial guess)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-mesh", type=int, default=128)
     ap.add_argument("--workload", choices=["uniform", "amr"], default="uniform",
                     help="amr: 256^3 base + 2 block-refined levels on 256^3 particles with 50 NFW halos")
     ap.add_argument("--also-a", default="0.5",
-                    help="comma-separated other scale factors at which mixed and mixed_nn are also timed")
+                    help="comma-separated other scale factors at which mixed, mixed_nn and mixed_scr are also timed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also stream 1 GiB through a plain elementwise kernel (reference for HBM counters)")
     return ap.parse_args()
@@ -156,7 +157,8 @@ def run_mode(mode, args, pos, dev, log, a=None):
     from paper_1305_2418_amd import mgfr
     N = args.mesh
     a = args.a if a is None else a
-    precision = mgfr.FP64 if mode == "fp64" else mgfr.MIXED
+    precision = mgfr.FP64 if mode.startswith("fp64") else mgfr.MIXED
+    screened = mode.endswith("_scr")
     nn_mode = mgfr.NN_COARSE if mode == "mixed_nn" else mgfr.NN_NONE
     params = mgfr.Params(mesh=N, box=100.0, a=a, fr0_abs=args.fr0, tol=1e-8, precision=precision,
                          nn_mode=nn_mode, max_vcycles=100, pre_smooth=args.smooth, post_smooth=args.smooth,
@@ -176,7 +178,10 @@ def run_mode(mode, args, pos, dev, log, a=None):
     def step(timing=False):
         solver.set_timing(timing)
         solver.assign_density(pos, out=delta)
-        u.zero_()
+        if screened:
+            solver.screened_guess(delta, out=u)
+        else:
+            u.zero_()
         _, dfr, st = solver.solve(delta, u=u, want_dfr=True)
         solver.fifth_force(u, pos, out=acc)
         return st
@@ -286,13 +291,13 @@ def main():
     other_a = {}
     for a in [float(x) for x in args.also_a.split(",") if x]:
         if a != args.a:
-            other_a[str(a)] = {m: run_mode(m, args, pos, dev, log, a=a) for m in ("mixed", "mixed_nn")}
+            other_a[str(a)] = {m: run_mode(m, args, pos, dev, log, a=a) for m in ("mixed", "mixed_nn", "mixed_scr")}
     copy_gbs = measure_copy(dev, log)
     mfma = measure_mfma(N, dev, log)
     # dominant kernel of the headline mode: the finest-level smoothing sweep
     # algorithmic bytes of a red-black sweep: float64, read u and f, write u
     # (24 B/cell); float32 correction sweep, read e, r and u, write e (16 B/cell)
-    if args.mode == "fp64":
+    if args.mode.startswith("fp64"):
         kernel, bpc, design_bpc = ("k_sweep_fused" if N >= 512 else "k_sweep_half (x2 per sweep)"), 24.0, 24.0
         src = KERNEL_SRC["fp64"]
     else:
@@ -322,7 +327,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.mode == "fp64" else "f64+f32",
+        "dtype": "f64" if args.mode.startswith("fp64") else "f64+f32",
         "data": "synthetic",
         "config": {
             "workload": f"{N}^3 mesh, {N}^3 particles (float32), 100 Mpc/h, a={args.a}, |f_R0|={args.fr0}, "

@@ -175,6 +175,19 @@ int mgfr_reserve_particles(mgfr_ctx *ctx, int64_t max_np);
 /* 1 (default): use the binning workspace when it is large enough; 0: never. */
 int mgfr_set_binning(mgfr_ctx *ctx, int on);
 
+/* Initial guess for mgfr_solve from the screened limit of the field
+ * equation (Sec. 2, Eqs. fR_field_eq and dR_fR): where the Laplacian of f_R
+ * is negligible the equation reduces to the local balance
+ * dR = 8 pi G d rho, i.e. exp(-u/(n+1)) = 1 + Omega_m a^-3 delta / C(a).
+ * Overdense cells get that u, the others u = 0:
+ *   u = -(n+1) log1p(Omega_m a^-3 max(delta, 0) / C(a)).
+ * It is exact for a constant overdensity and close to the solution in
+ * screened cores; the solve still iterates to the same tolerance, so only
+ * the number of V-cycles depends on it.
+ * delta: float64 [N^3] input; u: float64 [N^3] output (may not alias delta).
+ * Enqueued on the context's stream; MGFR_ERR_ARG for NULL pointers. */
+int mgfr_screened_guess(mgfr_ctx *ctx, const double *delta, double *u);
+
 /* Solve L(u) = f for u (Sec. 3.2 Eq. u_discrete_field_eq; Sec. 3.3).
  * delta: float64 [N^3] density contrast (input, unchanged);
  * u: float64 [N^3], in: initial guess (zeros = the background, or the

@@ -122,6 +122,24 @@ void or_source(const or_params *p, const double *delta, double *f)
     for (size_t c = 0; c < n3; ++c) f[c] = s * delta[c];
 }
 
+/* Initial guess from the screened limit (Sec. 2, Eqs. fR_field_eq and
+ * dR_fR): where the Laplacian of f_R is negligible the field equation reduces
+ * to the local balance dR = 8 pi G d rho, which in the dimensionless variable
+ * u = ln(f_R / fbar_R) reads exp(-u/(n+1)) = 1 + Omega_m a^-3 delta / C(a).
+ * Only overdense cells take this value (the balance describes screened
+ * regions); the others start at u = 0. */
+void or_screened_guess(const or_params *p, const double *delta, double *u)
+{
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    size_t n3 = (size_t)p->mesh * p->mesh * p->mesh;
+    double s = p->omega_m / (p->a * p->a * p->a) / C;
+    for (size_t c = 0; c < n3; ++c) {
+        double d = delta[c] > 0.0 ? delta[c] : 0.0;
+        u[c] = -(double)(p->n + 1) * log1p(s * d);
+    }
+}
+
 /* ---------------------------------------------------------------- operator */
 
 #define IDX(i, j, k) ((((size_t)(i)) * N + (j)) * N + (k))

@@ -56,6 +56,7 @@ def lib():
         L.or_cic_assign.argtypes = [C.c_int, C.c_double, C.c_int64, fp, dp, dp]
         L.or_delta.argtypes = [C.c_int, dp, dp]
         L.or_source.argtypes = [C.POINTER(Params), dp, dp]
+        L.or_screened_guess.argtypes = [C.POINTER(Params), dp, dp]
         L.or_apply_L.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
         L.or_apply_J.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
         L.or_residual_max.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
@@ -123,6 +124,14 @@ def source(p, delta):
     f = np.empty_like(delta)
     lib().or_source(C.byref(p), _d(delta), _d(f))
     return f
+
+
+def screened_guess(p, delta):
+    """Initial guess from the screened limit of the field equation (local balance)."""
+    delta = np.ascontiguousarray(delta, np.float64)
+    u = np.empty_like(delta)
+    lib().or_screened_guess(C.byref(p), _d(delta), _d(u))
+    return u
 
 
 def apply_L(u, h, bC, n=1):

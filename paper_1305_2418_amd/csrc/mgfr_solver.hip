@@ -425,6 +425,18 @@ __global__ __launch_bounds__(kBlock) void k_source(const double *__restrict__ de
     }
 }
 
+// Screened-limit initial guess: u = -(n+1) log1p(s max(delta, 0)) with
+// s = Omega_m a^-3 / C(a) (the local balance of the field equation where the
+// Laplacian term is negligible).
+__global__ __launch_bounds__(kBlock) void k_screened_guess(const double *__restrict__ delta, double s,
+                                                             double np1, size_t n, double *__restrict__ u)
+{
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock) {
+        const double d = delta[t];
+        u[t] = -np1 * log1p(s * (d > 0.0 ? d : 0.0));
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_dfr(const double *__restrict__ u, double fbar, size_t n,
                                                   double *__restrict__ dfr)
 {
@@ -899,6 +911,18 @@ int mgfr::solve_fp64_from(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
     st->res = res;
     st->l2res = std::sqrt(rsq / ncell) / D;
     return status;
+}
+
+extern "C" int mgfr_screened_guess(mgfr_ctx *c, const double *delta, double *u)
+{
+    int rc;
+    if ((rc = check_ptr(c, "ctx")) || (rc = check_ptr(delta, "delta")) || (rc = check_ptr(u, "u"))) return rc;
+    const size_t n = (size_t)c->lev[0].N * c->lev[0].N * c->lev[0].N;
+    const double s = c->p.omega_m / (c->p.a * c->p.a * c->p.a) / c->C;
+    const unsigned g = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 16384);
+    k_screened_guess<<<g, kBlock, 0, c->stream>>>(delta, s, (double)(c->p.n + 1), n, u);
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
 }
 
 extern "C" int mgfr_solve(mgfr_ctx *c, const double *delta, double *u, double *dfr, mgfr_stats *st_out)

@@ -123,6 +123,7 @@ def lib() -> C.CDLL:
         L.mgfr_set_fused_min_mesh.argtypes = [_VP, C.c_int]
         L.mgfr_set_colour_min_mesh.argtypes = [_VP, C.c_int]
         L.mgfr_set_fused_sweep32.argtypes = [_VP, C.c_int]
+        L.mgfr_screened_guess.argtypes = [_VP, _VP, _VP]
         L.mgfr_assign_density.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
         L.mgfr_reserve_particles.argtypes = [_VP, C.c_int64]
         L.mgfr_set_binning.argtypes = [_VP, C.c_int]
@@ -269,6 +270,16 @@ class Solver:
             out = torch.empty(self.shape, dtype=torch.float64, device=pos.device)
         op = _dev(out, torch.float64, self.shape, "delta")
         _check(lib().mgfr_assign_density(self._h, pp, mp, npart, op))
+        return out
+
+    def screened_guess(self, delta: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Initial guess from the screened limit (local balance) of the field equation."""
+        self._sync_stream()
+        dp = _dev(delta, torch.float64, self.shape, "delta")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=delta.device)
+        up = _dev(out, torch.float64, self.shape, "u")
+        _check(lib().mgfr_screened_guess(self._h, dp, up))
         return out
 
     def solve(self, delta: torch.Tensor, u: torch.Tensor | None = None, want_dfr: bool = True,

@@ -134,6 +134,61 @@ def test_solve_matches_oracle(N, rms, halos, fr0, a, seed):
     assert abs(st.res / st_o.res - 1) < 1e-3
 
 
+def test_screened_guess_matches_oracle():
+    """The screened-limit initial guess, cell by cell (log1p on both sides)."""
+    mg = _mg()
+    for N, a, n in ((32, 1.0, 1), (64, 0.5, 1), (32, 1.0, 2)):
+        print(f"[case] screened guess N={N} a={a} n={n}", flush=True)
+        d = _delta(N, 5.0, 11, 20)
+        g_o = O.screened_guess(_oparams(N, a=a, n=n), d)
+        s = mg.Solver(_params(mg, N, a=a, n=n))
+        g = s.screened_guess(torch.tensor(d, device=DEV)).cpu().numpy()
+        assert _rel(g, g_o) < 1e-14
+        assert np.all(g[d <= 0] == 0.0) and np.all(g[d > 0] < 0)
+
+
+@pytest.mark.parametrize("N,fr0,a,precision", [(64, 1e-6, 1.0, "fp64"), (128, 1e-6, 0.5, "fp64"),
+                                               (128, 1e-6, 1.0, "mixed")])
+def test_solve_from_screened_guess_matches_oracle(N, fr0, a, precision):
+    """Solving from the screened guess reaches the oracle's solution from the same
+    guess (FP64: identical schedule, 1e-10; mixed: 1e-6).  The guess only
+    changes the number of V-cycles (reported; fewer at 512^3, not always at
+    128^3)."""
+    mg = _mg()
+    print(f"[case] solve from screened guess N={N} fr0={fr0} a={a} {precision}", flush=True)
+    d = _delta(N, 5.0, 4, 20)
+    op = _oparams(N, fr0_abs=fr0, a=a, max_vcycles=60, tol=1e-8 if precision == "fp64" else 1e-11)
+    s_o, u_o, dfr_o, st_o = O.solve(op, d, u0=O.screened_guess(op, d))
+    assert s_o == 0
+    prec = mg.FP64 if precision == "fp64" else mg.MIXED
+    dt = torch.tensor(d, device=DEV)
+    s = mg.Solver(_params(mg, N, fr0_abs=fr0, a=a, max_vcycles=60, precision=prec))
+    _, _, st_cold = s.solve(dt)
+    u, dfr, st = s.solve(dt, u=s.screened_guess(dt))
+    assert st.status == 0 and st.fell_back == 0
+    if precision == "fp64":
+        k = st_o.vcycles
+        assert abs(st.vcycles - k) <= 1
+        if st.vcycles != k:
+            s = mg.Solver(_params(mg, N, fr0_abs=fr0, a=a, max_vcycles=k, tol=1e-300))
+            u, dfr, st = s.solve(dt, u=s.screened_guess(dt), allow_not_converged=True)
+        tol = 1e-10
+    else:
+        tol = 1e-6
+    err = _rel(dfr.cpu().numpy(), dfr_o)
+    print(f"  cycles from guess {st.vcycles} (cold {st_cold.vcycles}, oracle {st_o.vcycles}), rel dfr err {err:.2e}")
+    assert err < tol
+
+
+def test_screened_guess_solves_uniform_overdensity():
+    """For a constant overdensity the guess is the discrete solution: no V-cycle."""
+    mg = _mg()
+    s = mg.Solver(_params(mg, 32, fr0_abs=1e-6))
+    d = torch.full((32, 32, 32), 3.0, dtype=torch.float64, device=DEV)
+    u, dfr, st = s.solve(d, u=s.screened_guess(d))
+    assert st.status == 0 and st.vcycles == 0 and float(u.max()) < 0
+
+
 def test_solve_from_previous_solution_takes_no_cycles():
     mg = _mg()
     d = _delta(32, 1.0, 1)

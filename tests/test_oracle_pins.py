@@ -384,6 +384,46 @@ def test_deeply_screened_core_balance():
     assert np.abs(lhs / rhs - 1).max() < 0.01
 
 
+@pytest.mark.parametrize("n", [1, 2])
+@pytest.mark.parametrize("a", [1.0, 0.5])
+def test_screened_guess_solves_uniform_overdensity(n, a):
+    """For a constant overdensity every face flux vanishes, so the local balance
+    of the screened limit is the exact discrete solution: L(u_guess) = f to
+    rounding.  Underdense cells start at u = 0."""
+    N = 8
+    p = O.params(mesh=N, a=a, n=n, fr0_abs=1e-6)
+    fb, beta, C, bC = bc_of(p)
+    for d0 in (0.5, 30.0, 1e4):
+        delta = np.full((N, N, N), d0)
+        u = O.screened_guess(p, delta)
+        f = O.source(p, delta)
+        r = O.residual_max(u, f, p.box / N, bC, n)
+        assert r <= 1e-13 * np.abs(f).max(), (d0, r)
+        assert np.all(u < 0)
+    assert np.all(O.screened_guess(p, np.full((N, N, N), -0.7)) == 0.0)
+
+
+def test_screened_guess_matches_screened_core_and_keeps_the_solution():
+    """Inside a large dense sphere the guess agrees with the converged field (the
+    screened limit holds there); solving from it reaches the solution that a
+    cold start reaches."""
+    N, box = 32, 100.0
+    h = box / N
+    x = (np.arange(N) + 0.5) * h - box / 2
+    r = np.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    delta = 200.0 * 0.5 * (1 - np.tanh((r - 20.0) / 3.0))
+    delta -= delta.mean()
+    p = O.params(mesh=N, box=box, fr0_abs=1e-6, tol=1e-11)
+    s0, u0, _, st0 = O.solve(p, delta)
+    g = O.screened_guess(p, delta)
+    core = r < 8.0
+    assert np.abs(g[core] / u0[core] - 1).max() < 0.01
+    s1, u1, _, st1 = O.solve(p, delta, u0=g)
+    assert s0 == 0 and s1 == 0
+    assert np.abs(u1 - u0).max() < 1e-8 * np.abs(u0).max()
+    assert st1.res0 < st0.res0
+
+
 # ------------------------------------------------------------------------ T8 invariants
 
 def _cfg1_delta(N=32, seed=1, rms=1.0, halos=0):

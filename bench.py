@@ -47,8 +47,10 @@ def parse():
                     help="other modes timed in the same run (_scr: from the screened-limit initial guess)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-mesh", type=int, default=128)
-    ap.add_argument("--workload", choices=["uniform", "amr"], default="uniform",
-                    help="amr: 256^3 base + 2 block-refined levels on 256^3 particles with 50 NFW halos")
+    ap.add_argument("--workload", choices=["uniform", "amr", "sequence"], default="uniform",
+                    help="amr: 256^3 base + 2 block-refined levels on 256^3 particles with 50 NFW halos; "
+                         "sequence: consecutive steps of a growing displacement field, each solve warm-started "
+                         "in several ways")
     ap.add_argument("--also-a", default="0.5",
                     help="comma-separated other scale factors at which mixed, mixed_nn and mixed_scr are also timed")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -247,6 +249,64 @@ def run_amr(args, log):
     }
 
 
+def run_sequence(args, log):
+    """A sequence of steps whose Zel'dovich displacement grows by 2 % per step
+    (same seed, halos fixed), as consecutive time steps would.  Every step is
+    solved in mixed precision from: u = 0, the previous step's solution (the
+    paper's warm start), the network, and the screened-limit guess."""
+    import numpy as np
+    import torch
+    from paper_1305_2418_amd import mgfr, synth
+    N, K = args.mesh, max(2, args.steps)
+    dev = torch.device("cuda:0")
+    mk = lambda nn: mgfr.Solver(mgfr.Params(mesh=N, box=100.0, a=args.a, fr0_abs=args.fr0, tol=1e-8,
+                                            precision=mgfr.MIXED, nn_mode=nn, pre_smooth=args.smooth,
+                                            post_smooth=args.smooth, prolong=prolong_code(args)))
+    solvers = {"cold": mk(mgfr.NN_NONE), "previous": mk(mgfr.NN_NONE), "network": mk(mgfr.NN_COARSE),
+               "screened": mk(mgfr.NN_NONE)}
+    net = mgfr.Net(seed=0, max_voxels=(N // 4) ** 3)
+    net.set_params(np.load(WEIGHTS))
+    solvers["network"].set_net(net)
+    delta = torch.empty((N, N, N), dtype=torch.float64, device=dev)
+    u_prev = None
+    out = {m: {"vcycles": [], "solve_ms": []} for m in solvers}
+    for k in range(K):
+        pos = synth.clustered_load(N, 100.0, rms=5.0 * 1.02 ** k, seed=args.seed, n_halos=20, device=dev).to(dev)
+        solvers["cold"].assign_density(pos, out=delta)
+        del pos
+        for m, s in solvers.items():
+            if m == "previous" and u_prev is not None:
+                u = u_prev.clone()
+            elif m == "screened":
+                u = s.screened_guess(delta)
+            else:
+                u = torch.zeros_like(delta)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, _, st = s.solve(delta, u=u, want_dfr=False)
+            torch.cuda.synchronize()
+            out[m]["vcycles"].append(st.vcycles)
+            out[m]["solve_ms"].append(1e3 * (time.perf_counter() - t0))
+            if m == "previous":
+                u_prev = u
+        log(f"[sequence step {k}] " + ", ".join(f"{m} {out[m]['vcycles'][-1]} cycles "
+                                               f"{out[m]['solve_ms'][-1]:.1f} ms" for m in solvers))
+    warm = out["previous"]["solve_ms"][1:]
+    ms = sum(warm) / len(warm)
+    return {
+        "metric": "cells/s to converged f_R solve (res<1e-8), consecutive steps warm-started from the previous "
+                  "solution",
+        "value": N ** 3 / (ms * 1e-3), "unit": "cells/s", "n_gpus": 1, "steps": K - 1, "warmup": 1,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"{N}^3 mesh and particles, Zel'dovich k^-2 rms 5 x 1.02^k (k = 0..{K - 1}) + 20 "
+                               f"Plummer halos, seed {args.seed}, a={args.a}, |f_R0|={args.fr0}; mixed solve "
+                               f"only (CIC untimed), first step excluded from value",
+                   "modes": out},
+        "roofline": None,
+    }
+
+
 def calibrate_copy(log):
     """A plain streaming kernel of known traffic for the HBM byte counters:
     bitwise NOT of 1 GiB of int32 into a second 1 GiB buffer (reads and writes
@@ -274,6 +334,9 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy(log)
+    if args.workload == "sequence":
+        print(json.dumps(run_sequence(args, log)), flush=True)
+        return
     if args.workload == "amr":
         print(json.dumps(run_amr(args, log)), flush=True)
         return

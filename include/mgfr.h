@@ -188,6 +188,18 @@ int mgfr_set_binning(mgfr_ctx *ctx, int on);
  * Enqueued on the context's stream; MGFR_ERR_ARG for NULL pointers. */
 int mgfr_screened_guess(mgfr_ctx *ctx, const double *delta, double *u);
 
+/* Effective mass density of the effective-mass formulation (Sec. 3.4, Eq.
+ * effective_density), in units of the mean matter density:
+ *   delta_eff = delta/3 - dR / (24 pi G rho_bar)
+ *             = delta/3 - C(a) expm1(-u/(n+1)) / (3 Omega_m a^-3),
+ * with dR from Eq. dR_fR.  It is delta/3 where the field is unscreened and
+ * tends to 0 in screened regions; for a converged u it equals the flux term
+ * of the field equation divided by 3 beta Omega_m a^-3.
+ * delta, u: float64 [N^3] inputs; out: float64 [N^3] output (may alias
+ * neither input).  Enqueued on the context's stream; MGFR_ERR_ARG for NULL
+ * pointers. */
+int mgfr_effective_density(mgfr_ctx *ctx, const double *delta, const double *u, double *out);
+
 /* Solve L(u) = f for u (Sec. 3.2 Eq. u_discrete_field_eq; Sec. 3.3).
  * delta: float64 [N^3] density contrast (input, unchanged);
  * u: float64 [N^3], in: initial guess (zeros = the background, or the

@@ -140,6 +140,21 @@ void or_screened_guess(const or_params *p, const double *delta, double *u)
     }
 }
 
+/* Effective mass density of Sec. 3.4 (Eq. effective_density) in units of the
+ * mean matter density: drho_eff / rho_bar = delta/3 - dR / (24 pi G rho_bar)
+ * with dR = R_bar (e^{-u/(n+1)} - 1) (Eq. dR_fR and its general-n form),
+ * R_bar = 3 H0^2 C(a) and 8 pi G rho_bar = 3 H0^2 Omega_m a^-3, i.e.
+ * delta_eff = delta/3 - C expm1(-u/(n+1)) / (3 Omega_m a^-3). */
+void or_effective_density(const or_params *p, const double *delta, const double *u, double *out)
+{
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    size_t n3 = (size_t)p->mesh * p->mesh * p->mesh;
+    double om = p->omega_m / (p->a * p->a * p->a);
+    double q = 1.0 / (p->n + 1);
+    for (size_t c = 0; c < n3; ++c) out[c] = delta[c] / 3.0 - C * expm1(-q * u[c]) / (3.0 * om);
+}
+
 /* ---------------------------------------------------------------- operator */
 
 #define IDX(i, j, k) ((((size_t)(i)) * N + (j)) * N + (k))

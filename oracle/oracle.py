@@ -57,6 +57,7 @@ def lib():
         L.or_delta.argtypes = [C.c_int, dp, dp]
         L.or_source.argtypes = [C.POINTER(Params), dp, dp]
         L.or_screened_guess.argtypes = [C.POINTER(Params), dp, dp]
+        L.or_effective_density.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.or_apply_L.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
         L.or_apply_J.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
         L.or_residual_max.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
@@ -132,6 +133,15 @@ def screened_guess(p, delta):
     u = np.empty_like(delta)
     lib().or_screened_guess(C.byref(p), _d(delta), _d(u))
     return u
+
+
+def effective_density(p, delta, u):
+    """delta rho_eff / rho_bar of the effective-mass formulation (Sec. 3.4)."""
+    delta = np.ascontiguousarray(delta, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    out = np.empty_like(delta)
+    lib().or_effective_density(C.byref(p), _d(delta), _d(u), _d(out))
+    return out
 
 
 def apply_L(u, h, bC, n=1):

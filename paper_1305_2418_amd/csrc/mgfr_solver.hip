@@ -437,6 +437,15 @@ __global__ __launch_bounds__(kBlock) void k_screened_guess(const double *__restr
     }
 }
 
+// delta_eff = delta/3 - c expm1(-q u) with c = C / (3 Omega_m a^-3)
+__global__ __launch_bounds__(kBlock) void k_effective_density(const double *__restrict__ delta,
+                                                                const double *__restrict__ u, double c, double q,
+                                                                size_t n, double *__restrict__ out)
+{
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock)
+        out[t] = delta[t] / 3.0 - c * expm1(-q * u[t]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_dfr(const double *__restrict__ u, double fbar, size_t n,
                                                   double *__restrict__ dfr)
 {
@@ -921,6 +930,20 @@ extern "C" int mgfr_screened_guess(mgfr_ctx *c, const double *delta, double *u)
     const double s = c->p.omega_m / (c->p.a * c->p.a * c->p.a) / c->C;
     const unsigned g = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 16384);
     k_screened_guess<<<g, kBlock, 0, c->stream>>>(delta, s, (double)(c->p.n + 1), n, u);
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_effective_density(mgfr_ctx *c, const double *delta, const double *u, double *out)
+{
+    int rc;
+    if ((rc = check_ptr(c, "ctx")) || (rc = check_ptr(delta, "delta")) || (rc = check_ptr(u, "u")) ||
+        (rc = check_ptr(out, "out")))
+        return rc;
+    const size_t n = (size_t)c->lev[0].N * c->lev[0].N * c->lev[0].N;
+    const double om = c->p.omega_m / (c->p.a * c->p.a * c->p.a);
+    const unsigned g = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 16384);
+    k_effective_density<<<g, kBlock, 0, c->stream>>>(delta, u, c->C / (3.0 * om), c->q, n, out);
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
 }

@@ -124,6 +124,7 @@ def lib() -> C.CDLL:
         L.mgfr_set_colour_min_mesh.argtypes = [_VP, C.c_int]
         L.mgfr_set_fused_sweep32.argtypes = [_VP, C.c_int]
         L.mgfr_screened_guess.argtypes = [_VP, _VP, _VP]
+        L.mgfr_effective_density.argtypes = [_VP, _VP, _VP, _VP]
         L.mgfr_assign_density.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
         L.mgfr_reserve_particles.argtypes = [_VP, C.c_int64]
         L.mgfr_set_binning.argtypes = [_VP, C.c_int]
@@ -280,6 +281,17 @@ class Solver:
             out = torch.empty(self.shape, dtype=torch.float64, device=delta.device)
         up = _dev(out, torch.float64, self.shape, "u")
         _check(lib().mgfr_screened_guess(self._h, dp, up))
+        return out
+
+    def effective_density(self, delta: torch.Tensor, u: torch.Tensor, out: torch.Tensor | None = None):
+        """delta rho_eff / rho_bar (Sec. 3.4) from delta and the solved u."""
+        self._sync_stream()
+        dp = _dev(delta, torch.float64, self.shape, "delta")
+        up = _dev(u, torch.float64, self.shape, "u")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=delta.device)
+        op = _dev(out, torch.float64, self.shape, "out")
+        _check(lib().mgfr_effective_density(self._h, dp, up, op))
         return out
 
     def solve(self, delta: torch.Tensor, u: torch.Tensor | None = None, want_dfr: bool = True,

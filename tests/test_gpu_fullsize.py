@@ -5,7 +5,8 @@ bench.py solves it; the oracle cannot solve it in seconds, so it checks
 sampled outputs one by one: the CIC mass of sampled cells (a full scan of all
 particles), the residual f - L(u) at sampled cells (must be within the
 tolerance), delta f_R at sampled cells, and the force at sampled particles;
-and the mixed solve must agree with the float64 solve.  A 1024^3 mesh (the
+and the mixed solves (network warm start, screened-limit guess) must agree
+with the float64 solve.  A 1024^3 mesh (the
 largest the library accepts) is solved from a synthetic multi-sphere field
 and checked the same way."""
 import math
@@ -27,12 +28,12 @@ WEIGHTS = os.path.join(ROOT, "paper_1305_2418_amd", "weights", "unet_warmstart.n
 @pytest.mark.timeout(600)
 def test_512_workload_sampled_against_oracle():
     from paper_1305_2418_amd import mgfr
-    N, a, fr0, sm = 512, 1.0, 1e-6, 3
+    N, a, fr0, sm, pro = 512, 1.0, 1e-6, 4, 1  # V(4,4) with injected corrections, as timed
     print("[case] 512^3 workload", flush=True)
     pos = synth.clustered_load(N, 100.0, rms=5.0, seed=3, n_halos=20, device=DEV)
     mode = mgfr.NN_COARSE if os.path.exists(WEIGHTS) else mgfr.NN_NONE
     s = mgfr.Solver(mgfr.Params(mesh=N, a=a, fr0_abs=fr0, precision=mgfr.MIXED, nn_mode=mode,
-                                pre_smooth=sm, post_smooth=sm))
+                                pre_smooth=sm, post_smooth=sm, prolong=pro))
     net = None
     if mode == mgfr.NN_COARSE:
         net = mgfr.Net(seed=0, max_voxels=(N // 4) ** 3)
@@ -43,12 +44,23 @@ def test_512_workload_sampled_against_oracle():
     acc = s.fifth_force(u, pos)
     assert st.status == 0 and st.res <= 1e-8 and st.fell_back == 0
     print(f"  mixed{'+nn' if net else ''}: {st.vcycles} cycles, res {st.res:.2e}", flush=True)
-    s64 = mgfr.Solver(mgfr.Params(mesh=N, a=a, fr0_abs=fr0, pre_smooth=sm, post_smooth=sm))
+    s64 = mgfr.Solver(mgfr.Params(mesh=N, a=a, fr0_abs=fr0, pre_smooth=sm, post_smooth=sm, prolong=pro))
     u64, dfr64, st64 = s64.solve(delta)
     assert st64.status == 0
     rel = (torch.abs(dfr - dfr64).max() / torch.abs(dfr64).max()).item()
     print(f"  fp64: {st64.vcycles} cycles; mixed vs fp64 rel dfr {rel:.2e}", flush=True)
     assert rel < 1e-6
+    del s64, u64
+    # mixed solve from the screened-limit guess (the bench's mixed_scr mode)
+    s2 = mgfr.Solver(mgfr.Params(mesh=N, a=a, fr0_abs=fr0, precision=mgfr.MIXED, pre_smooth=sm, post_smooth=sm,
+                                 prolong=pro))
+    u2, dfr2, st2 = s2.solve(delta, u=s2.screened_guess(delta))
+    assert st2.status == 0 and st2.res <= 1e-8 and st2.fell_back == 0
+    rel2 = (torch.abs(dfr2 - dfr64).max() / torch.abs(dfr64).max()).item()
+    print(f"  mixed from the screened guess: {st2.vcycles} cycles; vs fp64 rel dfr {rel2:.2e}", flush=True)
+    assert rel2 < 1e-6
+    u2_h = u2.cpu().numpy()
+    del s2, u2, dfr2, dfr64
     # host copies for the oracle
     pos_h = pos.cpu().numpy()
     d_h = delta.cpu().numpy()
@@ -69,6 +81,10 @@ def test_512_workload_sampled_against_oracle():
     r = O.residual_at(u_h, f, 100.0 / N, beta * C, cells)
     print(f"  sampled max residual {np.abs(r).max() / D:.2e} (reported {st.res:.2e})", flush=True)
     assert np.abs(r).max() / D <= 1e-8
+    r2 = O.residual_at(u2_h, f, 100.0 / N, beta * C, cells)
+    print(f"  screened-guess solve: sampled max residual {np.abs(r2).max() / D:.2e} (reported {st2.res:.2e})",
+          flush=True)
+    assert np.abs(r2).max() / D <= 1e-8
     # 3) delta f_R at sampled cells
     dfr_h = dfr.cpu().numpy().reshape(-1)
     assert np.allclose(dfr_h[cells], -fb * np.expm1(u_h.reshape(-1)[cells]), rtol=1e-14, atol=1e-20)

@@ -134,6 +134,51 @@ def test_solve_matches_oracle(N, rms, halos, fr0, a, seed):
     assert abs(st.res / st_o.res - 1) < 1e-3
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_n2_matches_oracle(precision):
+    """Hu-Sawicki n = 2 (q = 1/3 in the curvature term and its derivative):
+    FP64 at the oracle's schedule to 1e-10, mixed to 1e-6 of the oracle's
+    solution."""
+    mg = _mg()
+    N, fr0, a = 64, 1e-6, 1.0
+    print(f"[case] n=2 solve {precision}", flush=True)
+    d = _delta(N, 5.0, 21, 20)
+    op = _oparams(N, fr0_abs=fr0, a=a, n=2, max_vcycles=60, tol=1e-8 if precision == "fp64" else 1e-11)
+    s_o, u_o, dfr_o, st_o = O.solve(op, d)
+    assert s_o == 0
+    prec = mg.FP64 if precision == "fp64" else mg.MIXED
+    s = mg.Solver(_params(mg, N, fr0_abs=fr0, a=a, n=2, max_vcycles=60, precision=prec))
+    dt = torch.tensor(d, device=DEV)
+    u, dfr, st = s.solve(dt)
+    assert st.status == 0
+    if precision == "fp64":
+        k = st_o.vcycles
+        assert abs(st.vcycles - k) <= 1
+        if st.vcycles != k:
+            s = mg.Solver(_params(mg, N, fr0_abs=fr0, a=a, n=2, max_vcycles=k, tol=1e-300))
+            u, dfr, st = s.solve(dt, allow_not_converged=True)
+    err = _rel(dfr.cpu().numpy(), dfr_o)
+    print(f"  cycles {st.vcycles} (oracle {st_o.vcycles}), rel dfr err {err:.2e}")
+    assert err < (1e-10 if precision == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("n,a", [(1, 1.0), (1, 0.5), (2, 1.0)])
+def test_effective_density_matches_oracle(n, a):
+    """delta rho_eff / rho_bar (Sec. 3.4) from the same delta and u, cell by cell
+    (expm1 on both sides; absolute tolerance on the scale delta/3, since the
+    two terms cancel in screened cells)."""
+    mg = _mg()
+    N = 64
+    print(f"[case] effective density n={n} a={a}", flush=True)
+    d = _delta(N, 5.0, 12, 20)
+    p = _oparams(N, a=a, n=n, fr0_abs=1e-6)
+    s_o, u_o, _, _ = O.solve(p, d)
+    ref = O.effective_density(p, d, u_o)
+    s = mg.Solver(_params(mg, N, a=a, n=n, fr0_abs=1e-6))
+    got = s.effective_density(torch.tensor(d, device=DEV), torch.tensor(u_o, device=DEV)).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(d).max()
+
+
 def test_screened_guess_matches_oracle():
     """The screened-limit initial guess, cell by cell (log1p on both sides)."""
     mg = _mg()

@@ -424,6 +424,44 @@ def test_screened_guess_matches_screened_core_and_keeps_the_solution():
     assert st1.res0 < st0.res0
 
 
+@pytest.mark.parametrize("n,a", [(1, 1.0), (1, 0.5), (2, 1.0)])
+def test_effective_density_is_the_field_equations_flux(n, a):
+    """At convergence the field equation says that the flux term of L(u) equals
+    the source minus the curvature term, so the effective density of Sec. 3.4
+    must equal that flux / (3 beta Omega_m a^-3) up to the residual; its mean
+    vanishes (the flux telescopes); unscreened (u = 0) it is delta/3."""
+    N = 32
+    delta = _cfg1_delta(N, rms=5.0, halos=20)
+    p = O.params(mesh=N, a=a, n=n, fr0_abs=1e-6, tol=1e-12, max_vcycles=200)
+    fb, beta, C, bC = bc_of(p)
+    s, u, _, st = O.solve(p, delta)
+    assert s == 0
+    de = O.effective_density(p, delta, u)
+    om = 0.3 / a ** 3
+    flux = O.apply_L(u, p.box / N, bC, n) - bC * np.expm1(-u / (n + 1))
+    scale = np.abs(delta).max() / 3
+    assert np.abs(de - flux / (3 * beta * om)).max() <= 1e-9 * scale
+    assert abs(de.mean()) <= 1e-9 * scale
+    assert np.allclose(O.effective_density(p, delta, np.zeros_like(u)), delta / 3, rtol=0, atol=1e-15 * scale)
+
+
+def test_effective_density_vanishes_in_a_screened_core():
+    """Inside a large dense sphere the field is screened: the effective density
+    is a small fraction of delta/3 there (Sec. 3.4 limits: delta/3 unscreened,
+    0 screened)."""
+    N, box = 32, 100.0
+    h = box / N
+    x = (np.arange(N) + 0.5) * h - box / 2
+    r = np.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    delta = 200.0 * 0.5 * (1 - np.tanh((r - 20.0) / 3.0))
+    delta -= delta.mean()
+    p = O.params(mesh=N, box=box, fr0_abs=1e-6, tol=1e-10)
+    s, u, _, _ = O.solve(p, delta)
+    de = O.effective_density(p, delta, u)
+    core = r < 8.0
+    assert np.abs(de[core]).max() < 0.02 * (delta[core] / 3).min()
+
+
 # ------------------------------------------------------------------------ T8 invariants
 
 def _cfg1_delta(N=32, seed=1, rms=1.0, halos=0):

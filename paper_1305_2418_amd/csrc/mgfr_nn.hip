@@ -15,9 +15,10 @@
 // channels-last ([voxel][channel], voxel = ((b S + z) S + y) S + x).
 //
 // Convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16: rows are
-// voxels, columns output channels, and the reduction index k = tap * Cin + c
-// runs over the 27 taps and the input channels in steps of 32 (8 consecutive
-// channels of one tap per lane).  The backward-data pass is the same kernel on
+// voxels, columns output channels, and the reduction runs over chunks of the
+// input channels staged in LDS with their halo, and within a chunk over the
+// 27 taps and its channels in steps of 32 (8 consecutive channels of one tap
+// per lane).  The backward-data pass is the same kernel on
 // the output gradient with the taps mirrored and the weight matrix transposed;
 // the backward-weight pass reduces over voxels with LDS-transposed tiles and
 // float32 atomics.
@@ -38,8 +39,7 @@ namespace mgfr {
 namespace {
 
 constexpr int kConvWaves = 4;   // waves per workgroup in the forward kernel
-constexpr int kConvMT = 2;      // 16-voxel row tiles per wave
-constexpr int kMaxNT = 6;       // up to 96 output channels
+constexpr int kConvMT = 4;      // 16-voxel row tiles per wave (256 voxels per workgroup)
 constexpr float kUScale = 5.0f; // network output = u / kUScale
 
 __device__ __forceinline__ float bf2f(__bf16 x) { return (float)x; }
@@ -48,53 +48,87 @@ __device__ __forceinline__ __bf16 f2bf(float x) { return (__bf16)x; }
 // -------------------------------------------------------------- convolution
 
 // Y[v][o] = act(sum_{t,c} X[v + off(t)][c] W[t][o][c] + bias[o]) on B periodic S^3
-// volumes.  W layout [27][Cout][Cin].  Cin % 8 == 0, Cout % 16 == 0, Cout <= 96.
+// volumes.  W layout [27][Cout][Cin].  Cin % 8 == 0, Cout % 16 == 0, Cout <= 96, S >= 8.
+//
+// A workgroup owns a tile of 256 output voxels, TX x 8 x TZ with TX = min(S, 16)
+// and TZ = 256 / (8 TX); it stages the tile and a one-voxel periodic halo of
+// the input in LDS, CC channels at a time (CC = 32, 16 or 8, dividing Cin),
+// so that the 27 taps read the activations from LDS instead of gathering them
+// 27 times from global memory.  Each wave computes 4 row tiles of 16 voxels
+// against all Cout columns; the weights come from global memory (L2/L1 hits:
+// every workgroup reads the same few KB).
+
+// NT column tiles of 16 output channels per workgroup, starting at channel
+// 16 NT blockIdx.y (a template parameter: the accumulators of the 16-channel
+// layers then take 16 registers, not 96; small grids split Cout over
+// blockIdx.y to fill the chip)
+template <int NT>
 __global__ __launch_bounds__(64 * kConvWaves) void k_conv3d(const __bf16 *__restrict__ X, int lgS, int Cin,
                                                              const __bf16 *__restrict__ W,
                                                              const float *__restrict__ bias, int Cout, int relu,
                                                              __bf16 *__restrict__ Y, float *__restrict__ Y32)
 {
+    extern __shared__ __attribute__((aligned(16))) __bf16 sX[];  // [halo voxels][CC], sized at launch
+    __shared__ int sTap[32];  // LDS offset (in voxels) of each tap's neighbour
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int S = 1 << lgS, sm = S - 1;
-    const size_t v0 = ((size_t)blockIdx.x * kConvWaves + w) * (16 * kConvMT);
-    const int NT = Cout >> 4;
-    const int K = 27 * Cin;
+    const int lgX = lgS < 4 ? lgS : 4;
+    const int TX = 1 << lgX, TY = 8, TZ = (16 * kConvMT * kConvWaves) / (TX * TY);
+    const int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HV = HX * HY * HZ;
+    unsigned bi = blockIdx.x;
+    const int ntx = S / TX, nty = S / TY, ntz = S / TZ;
+    const int x0 = (int)(bi % ntx) * TX;
+    bi /= ntx;
+    const int y0 = (int)(bi % nty) * TY;
+    bi /= nty;
+    const int z0 = (int)(bi % ntz) * TZ;
+    const size_t vol = bi / ntz;
     const int g = lane >> 4, r16 = lane & 15;
-    // the voxels this lane loads for each row tile
-    int bz[kConvMT], by[kConvMT], bx[kConvMT];
-    size_t vb[kConvMT];
+    const int ocol0 = 16 * NT * (int)blockIdx.y;
+    if (threadIdx.x < 32) {
+        const int t = threadIdx.x < 27 ? threadIdx.x : 0;
+        sTap[threadIdx.x] = ((t / 9 - 1) * HY + ((t / 3) % 3 - 1)) * HX + (t % 3 - 1);
+    }
+    // halo-tile voxel of each row this lane feeds to the A operand
+    int hb[kConvMT];
 #pragma unroll
     for (int mt = 0; mt < kConvMT; ++mt) {
-        const size_t v = v0 + 16 * mt + r16;
-        bx[mt] = (int)(v & sm);
-        by[mt] = (int)((v >> lgS) & sm);
-        bz[mt] = (int)((v >> (2 * lgS)) & sm);
-        vb[mt] = v >> (3 * lgS);  // volume index
+        const int lv = 16 * (w * kConvMT + mt) + r16;
+        const int lx = lv & (TX - 1), ly = (lv >> lgX) & (TY - 1), lz = lv >> (lgX + 3);
+        hb[mt] = ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1);
     }
-    f32x4 acc[kConvMT][kMaxNT];
+    f32x4 acc[kConvMT][NT];
 #pragma unroll
     for (int mt = 0; mt < kConvMT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < kMaxNT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        const int kk = k0 + 8 * g;
-        const bool valid = kk < K;
-        const int tap = valid ? kk / Cin : 0;
-        const int c = valid ? kk - tap * Cin : 0;
-        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        bf16x8 a[kConvMT];
-#pragma unroll
-        for (int mt = 0; mt < kConvMT; ++mt) {
-            const size_t src = (((vb[mt] << lgS) + ((bz[mt] + dz) & sm)) << (2 * lgS)) +
-                               ((size_t)((by[mt] + dy) & sm) << lgS) + ((bx[mt] + dx) & sm);
-            if (valid) a[mt] = *(const bf16x8 *)(X + src * Cin + c);
-            else a[mt] = bf16x8{};
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int lgC = (Cin % 32 == 0) ? 5 : ((Cin % 16 == 0) ? 4 : 3);  // chunk CC = 2^lgC channels
+    const int CC = 1 << lgC;
+    const int q8 = CC >> 3, KC = 27 * CC;
+    for (int cc0 = 0; cc0 < Cin; cc0 += CC) {
+        __syncthreads();  // the previous chunk's readers are done
+        for (int idx = threadIdx.x; idx < HV * q8; idx += 64 * kConvWaves) {
+            const int hv = idx / q8, q = idx - hv * q8;
+            const int hx = hv % HX, t = hv / HX, hy = t % HY, hz = t / HY;
+            const size_t src = ((((vol << lgS) + (size_t)((z0 + hz - 1) & sm)) << (2 * lgS)) +
+                                ((size_t)((y0 + hy - 1) & sm) << lgS) + (size_t)((x0 + hx - 1) & sm));
+            *(bf16x8 *)(sX + hv * CC + 8 * q) = *(const bf16x8 *)(X + src * Cin + cc0 + 8 * q);
         }
+        __syncthreads();
+        for (int k0 = 0; k0 < KC; k0 += 32) {
+            const int kk = k0 + 8 * g;
+            const bool valid = kk < KC;
+            const int tap = valid ? kk >> lgC : 0;
+            const int c = valid ? kk & (CC - 1) : 0;
+            const int toff = sTap[tap];
+            bf16x8 a[kConvMT];
 #pragma unroll
-        for (int nt = 0; nt < kMaxNT; ++nt) {
-            if (nt < NT) {
+            for (int mt = 0; mt < kConvMT; ++mt)
+                a[mt] = valid ? *(const bf16x8 *)(sX + (hb[mt] + toff) * CC + c) : bf16x8{};
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
                 bf16x8 b;
-                if (valid) b = *(const bf16x8 *)(W + ((size_t)tap * Cout + 16 * nt + r16) * Cin + c);
+                if (valid) b = *(const bf16x8 *)(W + ((size_t)tap * Cout + ocol0 + 16 * nt + r16) * Cin + cc0 + c);
                 else b = bf16x8{};
 #pragma unroll
                 for (int mt = 0; mt < kConvMT; ++mt)
@@ -105,13 +139,16 @@ __global__ __launch_bounds__(64 * kConvWaves) void k_conv3d(const __bf16 *__rest
 #pragma unroll
     for (int mt = 0; mt < kConvMT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < kMaxNT; ++nt) {
-            if (nt < NT) {
-                const int o = 16 * nt + r16;
+        for (int nt = 0; nt < NT; ++nt) {
+            {
+                const int o = ocol0 + 16 * nt + r16;
                 const float bo = bias ? bias[o] : 0.f;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const size_t v = v0 + 16 * mt + 4 * g + j;
+                    const int lv = 16 * (w * kConvMT + mt) + 4 * g + j;
+                    const int lx = lv & (TX - 1), ly = (lv >> lgX) & (TY - 1), lz = lv >> (lgX + 3);
+                    const size_t v = ((((vol << lgS) + (size_t)(z0 + lz)) << lgS) + (size_t)(y0 + ly)) * (size_t)S +
+                                      (size_t)(x0 + lx);
                     float val = acc[mt][nt][j] + bo;
                     if (relu) val = fmaxf(val, 0.f);
                     if (Y) Y[v * Cout + o] = f2bf(val);
@@ -119,6 +156,32 @@ __global__ __launch_bounds__(64 * kConvWaves) void k_conv3d(const __bf16 *__rest
                 }
             }
         }
+}
+
+// Launch k_conv3d over nvox = B S^3 voxels (S >= 8, Cout a multiple of 16 up to 96).
+void launch_conv3d(const __bf16 *X, size_t nvox, int lgS, int Cin, const __bf16 *W, const float *bias, int Cout,
+                   int relu, __bf16 *Y, float *Y32, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)(nvox / (16 * kConvMT * kConvWaves));
+    // LDS: the halo tile ((TX+2) x 10 x (TZ+2) voxels) times the channel chunk (bf16)
+    const int TX = lgS < 4 ? (1 << lgS) : 16, TZ = (16 * kConvMT * kConvWaves) / (TX * 8);
+    const int CC = (Cin % 32 == 0) ? 32 : ((Cin % 16 == 0) ? 16 : 8);
+    const size_t lds = (size_t)(TX + 2) * 10 * (TZ + 2) * CC * sizeof(__bf16);
+    int nt = Cout >> 4, groups = 1;
+    // fewer than two workgroups per CU: split the output channels
+    while (blocks * groups < 512 && nt % 2 == 0) {
+        nt /= 2;
+        groups *= 2;
+    }
+    const dim3 grid(blocks, groups);
+    switch (nt) {
+    case 1: k_conv3d<1><<<grid, 64 * kConvWaves, lds, s>>>(X, lgS, Cin, W, bias, Cout, relu, Y, Y32); break;
+    case 2: k_conv3d<2><<<grid, 64 * kConvWaves, lds, s>>>(X, lgS, Cin, W, bias, Cout, relu, Y, Y32); break;
+    case 3: k_conv3d<3><<<grid, 64 * kConvWaves, lds, s>>>(X, lgS, Cin, W, bias, Cout, relu, Y, Y32); break;
+    case 4: k_conv3d<4><<<grid, 64 * kConvWaves, lds, s>>>(X, lgS, Cin, W, bias, Cout, relu, Y, Y32); break;
+    case 5: k_conv3d<5><<<grid, 64 * kConvWaves, lds, s>>>(X, lgS, Cin, W, bias, Cout, relu, Y, Y32); break;
+    default: k_conv3d<6><<<grid, 64 * kConvWaves, lds, s>>>(X, lgS, Cin, W, bias, Cout, relu, Y, Y32); break;
+    }
 }
 
 // dW[t][o][c] += sum_v dZ[v][o] X[v + off(t)][c];  Cin, Cout % 16 == 0.
@@ -249,29 +312,26 @@ __global__ void k_pool(const __bf16 *__restrict__ in, int lgSo, int C, size_t no
     }
 }
 
-// out[child] = in[parent] into channels [off, off + C) of an output with Ctot channels
-__global__ void k_upsample(const __bf16 *__restrict__ in, int lgSo, int C, size_t nout, int Ctot, int off,
-                           __bf16 *__restrict__ out)
+// out[v] = concat(in[parent(v)] (Cu channels), skip[v] (Cs channels)): the
+// nearest-neighbour upsampling and the skip connection of one decoder level in
+// one pass, 8 channels (16 bytes) per thread; Cu, Cs multiples of 8
+__global__ void k_concat_up(const __bf16 *__restrict__ in, int Cu, const __bf16 *__restrict__ skip, int Cs,
+                            int lgSo, size_t nout, __bf16 *__restrict__ out)
 {
-    const int So = 1 << lgSo, sm = So - 1, lgSi = lgSo - 1;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nout * C; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const size_t v = i / C;
-        const int x = (int)(v & sm), y = (int)((v >> lgSo) & sm), z = (int)((v >> (2 * lgSo)) & sm);
-        const size_t b = v >> (3 * lgSo);
-        const size_t src = (((b << lgSi) + (z >> 1)) << (2 * lgSi)) + ((size_t)(y >> 1) << lgSi) + (x >> 1);
-        out[v * Ctot + off + c] = in[src * C + c];
-    }
-}
-
-// copy C channels into channels [off, off + C) of a Ctot-channel tensor
-__global__ void k_put_channels(const __bf16 *__restrict__ in, size_t nvox, int C, int Ctot, int off,
-                               __bf16 *__restrict__ out)
-{
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox * C; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t v = i / C;
-        const int c = (int)(i % C);
-        out[v * Ctot + off + c] = in[i];
+    const int sm = (1 << lgSo) - 1, lgSi = lgSo - 1, q8 = (Cu + Cs) >> 3, qu = Cu >> 3;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nout * q8; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t v = i / q8;
+        const int q = (int)(i - v * q8);
+        bf16x8 val;
+        if (q < qu) {
+            const int x = (int)(v & sm), y = (int)((v >> lgSo) & sm), z = (int)((v >> (2 * lgSo)) & sm);
+            const size_t b = v >> (3 * lgSo);
+            const size_t src = (((b << lgSi) + (z >> 1)) << (2 * lgSi)) + ((size_t)(y >> 1) << lgSi) + (x >> 1);
+            val = *(const bf16x8 *)(in + src * Cu + 8 * q);
+        } else {
+            val = *(const bf16x8 *)(skip + v * Cs + 8 * (q - qu));
+        }
+        *(bf16x8 *)(out + i * 8) = val;
     }
 }
 
@@ -545,9 +605,7 @@ int net_refresh(mgfr_net *n)
 int conv(mgfr_net *n, const __bf16 *x, size_t nvox, int lgS, int layer, bool relu, __bf16 *y)
 {
     const ConvSpec &L = n->L[layer];
-    const unsigned blocks = (unsigned)(nvox / (16 * kConvMT * kConvWaves));
-    k_conv3d<<<blocks, 64 * kConvWaves, 0, n->stream>>>(x, lgS, L.cin, n->wbf + L.woff, n->p + L.boff, L.cout,
-                                                        relu ? 1 : 0, y, nullptr);
+    launch_conv3d(x, nvox, lgS, L.cin, n->wbf + L.woff, n->p + L.boff, L.cout, relu ? 1 : 0, y, nullptr, n->stream);
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
 }
@@ -563,9 +621,7 @@ int conv_bwd(mgfr_net *n, const __bf16 *dy, int Ctot, int off, const __bf16 *y, 
     k_conv3d_wgrad<<<dim3(27, chunks), 256, 0, n->stream>>>(x, dz_scratch, lgS, L.cin, L.cout, nvox, n->g + L.woff);
     k_bias_grad<<<gridn(nvox, 1024), 256, 0, n->stream>>>(dz_scratch, L.cout, nvox, n->g + L.boff);
     if (dx) {
-        const unsigned blocks = (unsigned)(nvox / (16 * kConvMT * kConvWaves));
-        k_conv3d<<<blocks, 64 * kConvWaves, 0, n->stream>>>(dz_scratch, lgS, L.cout, n->wt + L.woff, nullptr, L.cin,
-                                                            0, dx, nullptr);
+        launch_conv3d(dz_scratch, nvox, lgS, L.cout, n->wt + L.woff, nullptr, L.cin, 0, dx, nullptr, n->stream);
     }
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
@@ -584,12 +640,10 @@ int net_forward(mgfr_net *n, const double *delta, int B, int lgS)
     k_pool<<<gridn(V3 * 32), 256, 0, n->stream>>>(n->s2, lgS - 2, 32, V3, n->p2);
     if ((rc = conv(n, n->p2, V3, lgS - 2, 4, true, n->h3a)) || (rc = conv(n, n->h3a, V3, lgS - 2, 5, true, n->h3)))
         return rc;
-    k_upsample<<<gridn(V2 * 64), 256, 0, n->stream>>>(n->h3, lgS - 1, 64, V2, 96, 0, n->cat4);
-    k_put_channels<<<gridn(V2 * 32), 256, 0, n->stream>>>(n->s2, V2, 32, 96, 64, n->cat4);
+    k_concat_up<<<gridn(V2 * 12), 256, 0, n->stream>>>(n->h3, 64, n->s2, 32, lgS - 1, V2, n->cat4);
     if ((rc = conv(n, n->cat4, V2, lgS - 1, 6, true, n->h4a)) || (rc = conv(n, n->h4a, V2, lgS - 1, 7, true, n->h4)))
         return rc;
-    k_upsample<<<gridn(V * 32), 256, 0, n->stream>>>(n->h4, lgS, 32, V, 48, 0, n->cat5);
-    k_put_channels<<<gridn(V * 16), 256, 0, n->stream>>>(n->s1, V, 16, 48, 32, n->cat5);
+    k_concat_up<<<gridn(V * 6), 256, 0, n->stream>>>(n->h4, 32, n->s1, 16, lgS, V, n->cat5);
     if ((rc = conv(n, n->cat5, V, lgS, 8, true, n->h5a)) || (rc = conv(n, n->h5a, V, lgS, 9, true, n->h5))) return rc;
     k_head<<<gridn(V), 256, 0, n->stream>>>(n->h5, V, n->p + n->head_off, n->y32);
     MGFR_HIP(hipGetLastError());
@@ -806,8 +860,8 @@ extern "C" int mgfr_conv3d_fwd(const void *x, int B, int S, int Cin, const void 
     if ((rc = conv_args(B, S, Cin, Cout, &lgS))) return rc;
     if (!x || !w || (!y && !y32)) return set_error(MGFR_ERR_ARG, "x, w and an output must be non-NULL");
     const size_t V = (size_t)B << (3 * lgS);
-    k_conv3d<<<(unsigned)(V / (16 * kConvMT * kConvWaves)), 64 * kConvWaves, 0, (hipStream_t)stream>>>(
-        (const __bf16 *)x, lgS, Cin, (const __bf16 *)w, bias, Cout, relu, (__bf16 *)y, y32);
+    launch_conv3d((const __bf16 *)x, V, lgS, Cin, (const __bf16 *)w, bias, Cout, relu, (__bf16 *)y, y32,
+                  (hipStream_t)stream);
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
 }
@@ -822,8 +876,8 @@ extern "C" int mgfr_conv3d_bwd_data(const void *dz, int B, int S, int Cout, cons
     hipStream_t s = (hipStream_t)stream;
     k_wt_transpose<<<gridn((size_t)27 * Cin * Cout), 256, 0, s>>>((const __bf16 *)w, Cin, Cout, (__bf16 *)wt_work);
     const size_t V = (size_t)B << (3 * lgS);
-    k_conv3d<<<(unsigned)(V / (16 * kConvMT * kConvWaves)), 64 * kConvWaves, 0, s>>>(
-        (const __bf16 *)dz, lgS, Cout, (const __bf16 *)wt_work, nullptr, Cin, 0, (__bf16 *)dx, nullptr);
+    launch_conv3d((const __bf16 *)dz, V, lgS, Cout, (const __bf16 *)wt_work, nullptr, Cin, 0, (__bf16 *)dx, nullptr,
+                  s);
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
 }

@@ -21,8 +21,9 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SWEEPS = {"k_mx_colour": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip"],
-          "k_mx_sweep_fused": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip"],
+          "k_mx_sweep2": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip"],
           "k_sweep_fused": ["paper_1305_2418_amd/csrc/mgfr_solver.hip"]}
+BY_GRID = ("k_mx_colour", "k_sweep_fused", "k_mx_correct_residual", "k_mx_restrict_pass", "k_mx_sweep2")
 COPY = "bitwise_not"
 
 
@@ -48,6 +49,20 @@ def stats(d, out, cmd):
         lines.append(f"{_short(r['Name']):70s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
                      f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:9.2f} "
                      f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):6.2f}")
+    # the dominant kernels run on every mesh level: split their launches by grid size
+    trace = _rows(d, "*kernel_trace.csv")
+    if trace:
+        gkey = next((k for k in trace[0] if k.startswith("Grid_Size")), None)
+        per = collections.defaultdict(list)
+        for r in trace:
+            name = _short(r["Kernel_Name"])
+            if gkey and any(name.startswith(k) for k in BY_GRID):
+                per[(name, int(r[gkey]))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        if per:
+            lines += ["", f"# by grid size ({gkey}, work-items; the largest grid is the finest level)",
+                      f"{'kernel':40s} {'grid':>12s} {'calls':>6s} {'avg us':>10s} {'min us':>9s} {'max us':>9s}"]
+            for (name, grid), v in sorted(per.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+                lines.append(f"{name:40s} {grid:12d} {len(v):6d} {sum(v) / len(v):10.2f} {min(v):9.2f} {max(v):9.2f}")
     open(out, "w").write("\n".join(lines) + "\n")
 
 

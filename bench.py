@@ -208,6 +208,12 @@ def run_mode(mode, args, pos, dev, log, a=None):
            "sweep_launch_ms": sweep_ms, "dfr_max": None}
     log(f"[{mode} a={a}] step {ms:.2f} ms, solve {solve_ms:.2f} ms, V-cycles {out['vcycles']}, res {out['res']:.2e}, "
         f"sweep launch {sweep_ms:.3f} ms, nn {out['nn_ms']:.2f} ms")
+    if mode == args.mode and a == args.a:
+        # the power-spectrum diagnostic of the last solution (untimed): P(delta + delta_eff) / P(delta)
+        k, ratio, _, _ = solver.power_ratio(delta, solver.effective_density(delta, u))
+        sel = list(range(0, len(k), max(1, len(k) // 16)))
+        out["power_ratio"] = {"k_h_per_Mpc": [float(k[i]) for i in sel], "ratio": [float(ratio[i]) for i in sel]}
+        log("[power ratio] " + ", ".join(f"k={k[i]:.2f}: {ratio[i]:.3f}" for i in sel[::4]))
     del solver, net
     return out
 

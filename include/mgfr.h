@@ -200,6 +200,21 @@ int mgfr_screened_guess(mgfr_ctx *ctx, const double *delta, double *u);
  * pointers. */
 int mgfr_effective_density(mgfr_ctx *ctx, const double *delta, const double *u, double *out);
 
+/* Power-spectrum diagnostic of the effective mass (Sec. 3.4; the paper's
+ * power-spectrum comparison, Sec. 5): the ratio of the power spectrum of
+ * delta + delta_eff to that of delta in shells of |k| ((4/3)^2 where the
+ * fifth force is unscreened, 1 where it is screened).
+ * P(k_i) = L^3/N^6 * mean over the modes of shell i of |DFT(f)|^2, shell i =
+ * the integer wave vectors n with i - 1/2 <= |n| < i + 1/2, k_i = 2 pi i / L.
+ * delta, delta_eff: float64 [N^3] device inputs; nbins in [1, N/2];
+ * k, ratio: float64 [nbins] host outputs; p_delta (P of delta) and counts
+ * (modes per shell): float64 [nbins] host outputs or NULL.  A diagnostic, not
+ * part of the per-step path: it allocates a workspace (three N^3 float64
+ * arrays) and an FFT plan (hipFFT) for the call, synchronizes the stream and
+ * frees them.  Errors: MGFR_ERR_ARG (NULL, nbins), MGFR_ERR_OOM, MGFR_ERR_HIP. */
+int mgfr_power_ratio(mgfr_ctx *ctx, const double *delta, const double *delta_eff, int nbins, double *k,
+                     double *ratio, double *p_delta, double *counts);
+
 /* Solve L(u) = f for u (Sec. 3.2 Eq. u_discrete_field_eq; Sec. 3.3).
  * delta: float64 [N^3] density contrast (input, unchanged);
  * u: float64 [N^3], in: initial guess (zeros = the background, or the

@@ -144,6 +144,28 @@ def effective_density(p, delta, u):
     return out
 
 
+def power_ratio(box, delta, delta_eff, nbins):
+    """Shell power spectra by the definition (numpy's real FFT as the transform):
+    returns k_i, P_{delta+delta_eff}/P_delta, P_delta and the mode count per shell,
+    shell i = integer wave vectors n with round(|n|) = i, i = 1..nbins."""
+    delta = np.asarray(delta, np.float64)
+    N = delta.shape[0]
+    F1 = np.fft.rfftn(delta)
+    F2 = np.fft.rfftn(delta + np.asarray(delta_eff, np.float64))
+    n1 = np.fft.fftfreq(N, 1.0 / N)
+    nz = np.arange(N // 2 + 1)
+    n2 = n1[:, None, None] ** 2 + n1[None, :, None] ** 2 + nz[None, None, :] ** 2
+    shell = np.floor(np.sqrt(n2) + 0.5).astype(np.int64)
+    w = np.where((nz == 0) | (nz == N // 2), 1.0, 2.0)[None, None, :] * np.ones_like(n2)
+    s1 = np.bincount(shell.ravel(), (w * np.abs(F1) ** 2).ravel(), minlength=nbins + 1)[1:nbins + 1]
+    s2 = np.bincount(shell.ravel(), (w * np.abs(F2) ** 2).ravel(), minlength=nbins + 1)[1:nbins + 1]
+    cnt = np.bincount(shell.ravel(), w.ravel(), minlength=nbins + 1)[1:nbins + 1]
+    k = 2 * np.pi * np.arange(1, nbins + 1) / box
+    ratio = np.where(s1 > 0, s2 / np.where(s1 > 0, s1, 1), 0.0)
+    p = np.where(cnt > 0, box ** 3 / N ** 6 * s1 / np.where(cnt > 0, cnt, 1), 0.0)
+    return k, ratio, p, cnt
+
+
 def apply_L(u, h, bC, n=1):
     u = np.ascontiguousarray(u, np.float64)
     out = np.empty_like(u)

@@ -13,7 +13,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmgfr.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["mgfr_solver.hip", "mgfr_particles.hip", "mgfr_mixed.hip", "mgfr_nn.hip", "mgfr_amr.hip", "mgfr_bin.hip"]
+SOURCES = ["mgfr_solver.hip", "mgfr_particles.hip", "mgfr_mixed.hip", "mgfr_nn.hip", "mgfr_amr.hip", "mgfr_bin.hip",
+           "mgfr_spectrum.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -47,7 +48,8 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    # hipFFT: the transforms of the power-spectrum diagnostic (mgfr_spectrum.hip)
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lhipfft"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

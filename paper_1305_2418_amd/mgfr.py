@@ -125,6 +125,7 @@ def lib() -> C.CDLL:
         L.mgfr_set_fused_sweep32.argtypes = [_VP, C.c_int]
         L.mgfr_screened_guess.argtypes = [_VP, _VP, _VP]
         L.mgfr_effective_density.argtypes = [_VP, _VP, _VP, _VP]
+        L.mgfr_power_ratio.argtypes = [_VP, _VP, _VP, C.c_int, _VP, _VP, _VP, _VP]
         L.mgfr_assign_density.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
         L.mgfr_reserve_particles.argtypes = [_VP, C.c_int64]
         L.mgfr_set_binning.argtypes = [_VP, C.c_int]
@@ -293,6 +294,17 @@ class Solver:
         op = _dev(out, torch.float64, self.shape, "out")
         _check(lib().mgfr_effective_density(self._h, dp, up, op))
         return out
+
+    def power_ratio(self, delta: torch.Tensor, delta_eff: torch.Tensor, nbins: int | None = None):
+        """(k, P_{delta+delta_eff}/P_delta, P_delta, modes) per |k| shell (numpy arrays)."""
+        import numpy as np
+        self._sync_stream()
+        nb = self.shape[0] // 2 if nbins is None else int(nbins)
+        dp = _dev(delta, torch.float64, self.shape, "delta")
+        ep = _dev(delta_eff, torch.float64, self.shape, "delta_eff")
+        out = [np.zeros(nb) for _ in range(4)]
+        _check(lib().mgfr_power_ratio(self._h, dp, ep, nb, *[o.ctypes.data_as(C.c_void_p) for o in out]))
+        return tuple(out)
 
     def solve(self, delta: torch.Tensor, u: torch.Tensor | None = None, want_dfr: bool = True,
               allow_not_converged: bool = False):

@@ -179,6 +179,26 @@ def test_effective_density_matches_oracle(n, a):
     assert np.abs(got - ref).max() <= 1e-14 * np.abs(d).max()
 
 
+def test_power_ratio_matches_oracle():
+    """Shell power spectra of delta and delta + delta_eff (hipFFT and the shell
+    kernel against numpy's FFT and the same shell definition)."""
+    mg = _mg()
+    N = 64
+    print("[case] power ratio N=64", flush=True)
+    d = _delta(N, 5.0, 13, 20)
+    p = _oparams(N, fr0_abs=1e-6)
+    s_o, u_o, _, _ = O.solve(p, d)
+    de = O.effective_density(p, d, u_o)
+    k_o, r_o, p_o, c_o = O.power_ratio(100.0, d, de, N // 2)
+    s = mg.Solver(_params(mg, N, fr0_abs=1e-6))
+    k, r, pd, cnt = s.power_ratio(torch.tensor(d, device=DEV), torch.tensor(de, device=DEV))
+    print(f"  ratio at k_1 {r[0]:.4f}, k_8 {r[7]:.4f}, k_32 {r[31]:.4f}")
+    assert np.array_equal(cnt, c_o) and np.allclose(k, k_o, rtol=1e-15)
+    assert np.allclose(r, r_o, rtol=1e-11) and np.allclose(pd, p_o, rtol=1e-11)
+    # linear theory bounds it by 1 (screened) and (4/3)^2 (unscreened); loose check
+    assert np.all((r > 0.9) & (r < 16 / 9 + 0.05))
+
+
 def test_screened_guess_matches_oracle():
     """The screened-limit initial guess, cell by cell (log1p on both sides)."""
     mg = _mg()

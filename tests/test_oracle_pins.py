@@ -462,6 +462,34 @@ def test_effective_density_vanishes_in_a_screened_core():
     assert np.abs(de[core]).max() < 0.02 * (delta[core] / 3).min()
 
 
+def test_power_ratio_shells_and_closed_forms():
+    """Shell definition against a brute-force count of integer wave vectors;
+    a single cosine puts N^6/2 of |DFT|^2 into its own shell; Parseval for a
+    band-limited field; delta_eff = delta/3 (unscreened) gives (4/3)^2."""
+    N, box = 16, 100.0
+    nb = N // 2
+    n1 = np.fft.fftfreq(N, 1.0 / N)
+    full = np.sqrt(n1[:, None, None] ** 2 + n1[None, :, None] ** 2 + n1[None, None, :] ** 2)
+    brute = np.array([np.count_nonzero(np.floor(full + 0.5) == i) for i in range(1, nb + 1)], float)
+    x = (np.arange(N) + 0.5) * box / N
+    cosx = np.cos(2 * np.pi * 3 * x / box)[:, None, None] * np.ones((N, N, N))
+    k, ratio, p, cnt = O.power_ratio(box, cosx, np.zeros_like(cosx), nb)
+    assert np.array_equal(cnt, brute)
+    s1 = p * cnt * N ** 6 / box ** 3
+    assert abs(s1[2] / (N ** 6 / 2) - 1) < 1e-12 and np.abs(np.delete(s1, 2)).max() < 1e-9 * N ** 6
+    assert np.allclose(k, 2 * np.pi * np.arange(1, nb + 1) / box)
+    rng = np.random.default_rng(5)
+    F = np.fft.rfftn(rng.standard_normal((N, N, N)))
+    nz = np.arange(N // 2 + 1)
+    F[np.sqrt(n1[:, None, None] ** 2 + n1[None, :, None] ** 2 + nz[None, None, :] ** 2) > N / 4] = 0
+    F[0, 0, 0] = 0  # the k = 0 mode belongs to no shell
+    d = np.fft.irfftn(F, s=(N, N, N), axes=(0, 1, 2))
+    k, ratio, p, cnt = O.power_ratio(box, d, d / 3, nb)
+    assert abs((p * cnt * N ** 6 / box ** 3).sum() / (N ** 3 * (d ** 2).sum()) - 1) < 1e-12
+    live = p > 1e-12 * p.max()  # shells beyond the band hold only rounding noise
+    assert live.sum() == 4 and np.allclose(ratio[live], 16 / 9, rtol=1e-12)
+
+
 # ------------------------------------------------------------------------ T8 invariants
 
 def _cfg1_delta(N=32, seed=1, rms=1.0, halos=0):

@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--fr0", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--smooth", type=int, default=4, help="pre- and post-smoothing sweeps")
+    ap.add_argument("--coarse-sweeps", type=int, default=None,
+                    help="red-black sweeps on the coarsest grid (default: 30 for the uniform mesh, whose 4^3 "
+                         "level runs inside one launch; 4 for the adaptive workload, whose refined levels' "
+                         "coarsest sublevel costs a launch per colour and sweep)")
     ap.add_argument("--prolong", choices=["inject", "linear"], default="inject",
                     help="coarse-to-fine transfer of the correction (both are the paper's options)")
     ap.add_argument("--mode", choices=MODES, default="mixed_nn", help="headline mode")
@@ -164,6 +168,7 @@ def run_mode(mode, args, pos, dev, log, a=None):
     nn_mode = mgfr.NN_COARSE if mode == "mixed_nn" else mgfr.NN_NONE
     params = mgfr.Params(mesh=N, box=100.0, a=a, fr0_abs=args.fr0, tol=1e-8, precision=precision,
                          nn_mode=nn_mode, max_vcycles=100, pre_smooth=args.smooth, post_smooth=args.smooth,
+                         coarse_sweeps=30 if args.coarse_sweeps is None else args.coarse_sweeps,
                          prolong=prolong_code(args))
     solver = mgfr.Solver(params)
     net = None
@@ -227,6 +232,7 @@ def run_amr(args, log):
     pos = synth.clustered_load(N0, 100.0, rms=5.0, seed=4, n_halos=50, profile="nfw", device=dev).to(dev)
     params = mgfr.Params(mesh=N0, box=100.0, a=args.a, fr0_abs=args.fr0, tol=1e-8, precision=mgfr.MIXED,
                          refine_levels=2, pre_smooth=args.smooth, post_smooth=args.smooth,
+                         coarse_sweeps=4 if args.coarse_sweeps is None else args.coarse_sweeps,
                          prolong=prolong_code(args))
     amr = mgfr.Amr(params, max_blocks=262144)
     for _ in range(args.warmup):

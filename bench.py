@@ -255,6 +255,7 @@ def run_amr(args, log):
                                f"256^3 particles, Zel'dovich k^-2 rms 5 + 50 NFW halos (c 5-10), seed 4, "
                                f"a={args.a}, |f_R0|={args.fr0}; step = base CIC + mixed solve + flagging + "
                                f"refined-level CIC and float64 solves",
+                   "coarse_sweeps": params.coarse_sweeps,
                    "blocks_per_level": nb, "cells": cells, "vcycles_per_level": [s.vcycles for s in st],
                    "res_per_level": [s.res for s in st]},
         "roofline": None,

@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--fr0", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--smooth", type=int, default=4, help="pre- and post-smoothing sweeps")
+    ap.add_argument("--omega", type=float, default=1.2,
+                    help="relaxation factor of the float32 correction sweeps of the mixed modes (1: plain NGS)")
     ap.add_argument("--coarse-sweeps", type=int, default=None,
                     help="red-black sweeps on the coarsest grid (default: 30 for the uniform mesh, whose 4^3 "
                          "level runs inside one launch; 4 for the adaptive workload, whose refined levels' "
@@ -171,6 +173,8 @@ def run_mode(mode, args, pos, dev, log, a=None):
                          coarse_sweeps=30 if args.coarse_sweeps is None else args.coarse_sweeps,
                          prolong=prolong_code(args))
     solver = mgfr.Solver(params)
+    if precision == mgfr.MIXED:
+        solver.set_relaxation32(args.omega)
     net = None
     if nn_mode == mgfr.NN_COARSE:
         if not os.path.exists(WEIGHTS):
@@ -277,6 +281,8 @@ def run_sequence(args, log):
                                             post_smooth=args.smooth, prolong=prolong_code(args)))
     solvers = {"cold": mk(mgfr.NN_NONE), "previous": mk(mgfr.NN_NONE), "network": mk(mgfr.NN_COARSE),
                "screened": mk(mgfr.NN_NONE)}
+    for s in solvers.values():
+        s.set_relaxation32(args.omega)
     net = mgfr.Net(seed=0, max_voxels=(N // 4) ** 3)
     net.set_params(np.load(WEIGHTS))
     solvers["network"].set_net(net)
@@ -408,7 +414,8 @@ def main():
         "config": {
             "workload": f"{N}^3 mesh, {N}^3 particles (float32), 100 Mpc/h, a={args.a}, |f_R0|={args.fr0}, "
                         f"Zel'dovich k^-2 rms 5 + 20 Plummer halos, seed {args.seed}; step = CIC + solve from a "
-                        f"cold start to 1e-8 with V({args.smooth},{args.smooth}), {args.prolong} prolongation, + fifth force",
+                        f"cold start to 1e-8 with V({args.smooth},{args.smooth}), {args.prolong} prolongation, + fifth force; "
+                        f"mixed modes: float32 correction sweeps relaxed by omega = {args.omega}",
             "mode": args.mode,
             "modes": results,
             "modes_other_a": other_a,

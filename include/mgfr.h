@@ -152,6 +152,16 @@ int mgfr_set_colour_min_mesh(mgfr_ctx *ctx, int n);
  * call allocates nothing.  Errors: MGFR_ERR_ARG for on not 0 or 1. */
 int mgfr_set_fused_sweep32(mgfr_ctx *ctx, int on);
 
+/* Relaxation factor omega of the float32 correction sweeps of the
+ * mixed-precision solve: each Newton-Gauss-Seidel update (Sec. 3.3, Eq.
+ * iterative_correction) is scaled by omega (1: the paper's plain update;
+ * 1 < omega < 2: over-relaxation).  The float64 outer loop judges
+ * convergence, so the answer does not depend on omega, only the number of
+ * V-cycles.  Once the float64 residual grows during a solve, the remaining
+ * cycles of that solve use omega = 1.  Default 1.  The float64 solve and the
+ * refined levels always use 1.  Errors: MGFR_ERR_ARG unless 0 < omega < 2. */
+int mgfr_set_relaxation32(mgfr_ctx *ctx, double omega);
+
 /* Cloud-in-cell assignment (Sec. 3.1) of np particles onto the N^3 mesh and
  * delta = m / m_bar - 1 with m_bar the mean cell mass of the assignment.
  * pos: float32 [np][3]; mass: float64 [np] or NULL for equal masses;

@@ -56,6 +56,8 @@ struct mgfr_ctx {
     int fused_min_n = 512;   // levels with N >= this use the fused out-of-place sweep (0: never)
     int colour32_min_n = 128; // float32 sweeps on levels with N >= this by one-colour pass kernels (0: never)
     int fused32 = 0;          // those sweeps as one fused red-black kernel per sweep instead
+    double omega32 = 1.0;     // relaxation factor of the float32 correction sweeps (mixed solve)
+    double omega_now = 1.0;   // the factor in use (set to 1 once the outer residual grows)
     // reduction scratch
     double *partial = nullptr;  // [2 * nparts]
     int nparts = 0;

@@ -289,7 +289,7 @@ __device__ __forceinline__ float mx_update(const Cell4 &c, float r, const Cell4 
     const float cm = fexpm1(-k.q * c.e);
     const float N = k.ih2 * flux + k.bC * sc * cm;
     const float J = k.ih2 * dflux - k.q * k.bC * sc * (1.0f + cm);
-    float d = -(N - r) * __builtin_amdgcn_rcpf(J);
+    float d = -(N - r) * __builtin_amdgcn_rcpf(J) * k.omega;
     if (k.max_du > 0.f) d = fminf(fmaxf(d, -k.max_du), k.max_du);
     return c.e + d;
 }
@@ -851,12 +851,12 @@ struct MxTail {
     float ih2[kMaxLevels];
     int lg[kMaxLevels];
     int l0, nlev, pre, post, coarse, mode;
-    float bC, q, max_du;
+    float bC, q, max_du, omega;
 };
 
 __device__ void mx_tail_sweeps(const MxTail &A, int l, int sweeps)
 {
-    const MxConst kc{A.ih2[l], A.bC, A.q, A.max_du};
+    const MxConst kc{A.ih2[l], A.bC, A.q, A.max_du, A.omega};
     const int lg = A.lg[l];
     const size_t half = (size_t)1 << (3 * lg - 1);
     for (int s = 0; s < sweeps; ++s)
@@ -1139,7 +1139,8 @@ inline unsigned nb(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 MxConst mx_const(const mgfr_ctx *c, int l)
 {
-    return MxConst{(float)(1.0 / (c->lev[l].h * c->lev[l].h)), (float)c->bC, (float)c->q, (float)c->p.max_du};
+    return MxConst{(float)(1.0 / (c->lev[l].h * c->lev[l].h)), (float)c->bC, (float)c->q, (float)c->p.max_du,
+                   (float)c->omega_now};
 }
 
 // Levels swept by the one-colour pass kernel store e, r and ebar split by colour.
@@ -1226,6 +1227,7 @@ int mx_launch_tail(mgfr_ctx *c, int l0)
     A.bC = (float)c->bC;
     A.q = (float)c->q;
     A.max_du = (float)c->p.max_du;
+    A.omega = (float)c->omega_now;
     k_mx_tail<<<1, kTailThreads, 0, c->stream>>>(A);
     MGFR_HIP(hipGetLastError());
     return MGFR_OK;
@@ -1349,6 +1351,7 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
     double res = rmax / D, prev = res;
     st->res0 = res;
     int it = 0, grow = 0, status;
+    c->omega_now = c->omega32;
     for (;;) {
         if (!std::isfinite(res) || grow >= 3) {
             // fall back: plain float64 solve from u = 0 (in the caller's array)
@@ -1369,6 +1372,7 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
         prev = res;
         res = rmax / D;
         grow = (res > prev) ? grow + 1 : 0;
+        if (grow) c->omega_now = 1.0;  // over-relaxation off for the rest of the solve once the residual grows
         if (it < MGFR_MAX_HIST) st->res_hist[it] = res;
         ++it;
     }

@@ -188,6 +188,7 @@ __device__ __forceinline__ void prolong_block(T *__restrict__ u, const T *__rest
 
 struct MxConst {
     float ih2, bC, q, max_du;
+    float omega = 1.0f;  // relaxation factor of the Newton step (1: plain Newton-Gauss-Seidel)
 };
 
 // e^x for the float32 correction cycle: the hardware base-2 exponential of
@@ -228,7 +229,7 @@ __device__ __forceinline__ float mx_step(float ec, float Xc, float uc, float wc,
     const float cm = fexpm1(-k.q * ec);
     const float N = k.ih2 * flux + k.bC * sc * cm;
     const float J = k.ih2 * dflux - k.q * k.bC * sc * (1.0f + cm);
-    float d = -(N - r) / J;
+    float d = -(N - r) / J * k.omega;
     if (k.max_du > 0.f) d = fminf(fmaxf(d, -k.max_du), k.max_du);
     return d;
 }

@@ -1011,6 +1011,14 @@ extern "C" int mgfr_set_colour_min_mesh(mgfr_ctx *c, int n)
     return MGFR_OK;
 }
 
+extern "C" int mgfr_set_relaxation32(mgfr_ctx *c, double omega)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (!(omega > 0.0 && omega < 2.0)) return set_error(MGFR_ERR_ARG, "omega must be in (0, 2)");
+    c->omega32 = omega;
+    return MGFR_OK;
+}
+
 extern "C" int mgfr_set_fused_sweep32(mgfr_ctx *c, int on)
 {
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");

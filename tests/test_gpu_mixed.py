@@ -43,6 +43,36 @@ def test_mixed_solve_matches_fp64_oracle(N, rms, halos, fr0, a, seed):
     assert r <= 1e-8 and abs(r / st.res - 1) < 1e-3
 
 
+@pytest.mark.parametrize("omega", [1.2, 1.6])
+def test_over_relaxed_correction_sweeps_reach_the_oracle(omega):
+    """Over-relaxed float32 correction sweeps change only the number of
+    V-cycles: the mixed solve still reaches the oracle's solution.  A large
+    factor can make the float64 residual grow; the solve then continues with
+    omega = 1 and still converges."""
+    from paper_1305_2418_amd import mgfr
+    N, fr0, a = 128, 1e-6, 0.7
+    print(f"[case] mixed omega={omega}", flush=True)
+    d = _delta(N, 5.0, 17, 20)
+    s_o, u_o, dfr_o, st_o = O.solve(O.params(mesh=N, fr0_abs=fr0, a=a, tol=1e-11, max_vcycles=100), d)
+    s = mgfr.Solver(mgfr.Params(mesh=N, fr0_abs=fr0, a=a, precision=mgfr.MIXED))
+    dt = torch.tensor(d, device=DEV)
+    _, _, st1 = s.solve(dt, want_dfr=False)
+    s.set_relaxation32(omega)
+    u, dfr, st = s.solve(dt)
+    err = np.abs(dfr.cpu().numpy() - dfr_o).max() / np.abs(dfr_o).max()
+    print(f"  cycles {st.vcycles} (omega 1: {st1.vcycles}), fell back {st.fell_back}, rel dfr err {err:.2e}")
+    assert st.status == 0 and st.res <= 1e-8 and err < 1e-6
+
+
+def test_relaxation_factor_is_validated():
+    from paper_1305_2418_amd import mgfr
+    s = mgfr.Solver(mgfr.Params(mesh=32, precision=mgfr.MIXED))
+    for bad in (0.0, -1.0, 2.0, float("nan")):
+        with pytest.raises(mgfr.MgfrError) as ei:
+            s.set_relaxation32(bad)
+        assert ei.value.code == mgfr.MGFR_ERR_ARG
+
+
 def test_mixed_falls_back_to_fp64_on_bad_guess():
     from paper_1305_2418_amd import mgfr
     d = _delta(32, 1.0, 1, 0)

@@ -387,6 +387,30 @@ def test_nonfinite_delta_rejected_and_arguments_validated():
         assert ei.value.code == mg.MGFR_ERR_ARG
 
 
+def test_diagnostic_and_guess_entry_points_validate_arguments():
+    """NULL pointers, an out-of-range shell count and a bad switch value are
+    rejected with MGFR_ERR_ARG (through the C ABI directly)."""
+    import ctypes as C
+    mg = _mg()
+    L = mg.lib()
+    s = mg.Solver(_params(mg, 16))
+    d = torch.zeros((16, 16, 16), dtype=torch.float64, device=DEV)
+    u = torch.zeros_like(d)
+    out = np.zeros(8)
+    op = out.ctypes.data_as(C.c_void_p)
+    assert L.mgfr_screened_guess(s._h, None, u.data_ptr()) == mg.MGFR_ERR_ARG
+    assert L.mgfr_screened_guess(s._h, d.data_ptr(), None) == mg.MGFR_ERR_ARG
+    assert L.mgfr_effective_density(s._h, d.data_ptr(), None, u.data_ptr()) == mg.MGFR_ERR_ARG
+    assert L.mgfr_power_ratio(s._h, d.data_ptr(), u.data_ptr(), 0, op, op, None, None) == mg.MGFR_ERR_ARG
+    assert L.mgfr_power_ratio(s._h, d.data_ptr(), u.data_ptr(), 9, op, op, None, None) == mg.MGFR_ERR_ARG
+    assert L.mgfr_power_ratio(s._h, d.data_ptr(), u.data_ptr(), 8, None, op, None, None) == mg.MGFR_ERR_ARG
+    assert L.mgfr_set_fused_sweep32(s._h, 2) == mg.MGFR_ERR_ARG
+    assert L.mgfr_set_colour_min_mesh(s._h, 64) == mg.MGFR_ERR_ARG
+    # uniform density: no power at all, ratios reported as 0
+    k, r, p, c = s.power_ratio(d, u, 8)
+    assert np.all(r == 0) and np.all(p == 0) and c.sum() > 0
+
+
 def test_not_converged_status():
     mg = _mg()
     d = _delta(32, 1.0, 1)

@@ -239,6 +239,7 @@ def run_amr(args, log):
                          coarse_sweeps=4 if args.coarse_sweeps is None else args.coarse_sweeps,
                          prolong=prolong_code(args))
     amr = mgfr.Amr(params, max_blocks=262144)
+    amr.set_relaxation32(args.omega)
     for _ in range(args.warmup):
         amr.solve(pos)
     torch.cuda.synchronize()
@@ -259,7 +260,7 @@ def run_amr(args, log):
                                f"256^3 particles, Zel'dovich k^-2 rms 5 + 50 NFW halos (c 5-10), seed 4, "
                                f"a={args.a}, |f_R0|={args.fr0}; step = base CIC + mixed solve + flagging + "
                                f"refined-level CIC and float64 solves",
-                   "coarse_sweeps": params.coarse_sweeps,
+                   "coarse_sweeps": params.coarse_sweeps, "omega": args.omega,
                    "blocks_per_level": nb, "cells": cells, "vcycles_per_level": [s.vcycles for s in st],
                    "res_per_level": [s.res for s in st]},
         "roofline": None,

@@ -158,8 +158,9 @@ int mgfr_set_fused_sweep32(mgfr_ctx *ctx, int on);
  * 1 < omega < 2: over-relaxation).  The float64 outer loop judges
  * convergence, so the answer does not depend on omega, only the number of
  * V-cycles.  Once the float64 residual grows during a solve, the remaining
- * cycles of that solve use omega = 1.  Default 1.  The float64 solve and the
- * refined levels always use 1.  Errors: MGFR_ERR_ARG unless 0 < omega < 2. */
+ * cycles of that solve use omega = 1.  Default 1.  The float64 solve always
+ * uses 1 (refined levels: mgfr_amr_set_relaxation32).  Errors: MGFR_ERR_ARG
+ * unless 0 < omega < 2. */
 int mgfr_set_relaxation32(mgfr_ctx *ctx, double omega);
 
 /* Cloud-in-cell assignment (Sec. 3.1) of np particles onto the N^3 mesh and
@@ -330,6 +331,12 @@ typedef struct mgfr_amr mgfr_amr;
 /* p->refine_levels in {1, 2}; 32 <= p->mesh <= 512; 1 <= max_blocks <= 2^22. */
 int mgfr_amr_create(const mgfr_params *p, int64_t max_blocks, void *stream, mgfr_amr **out);
 void mgfr_amr_destroy(mgfr_amr *amr);
+
+/* Relaxation factor of the float32 correction sweeps of a mixed-precision
+ * adaptive solve (the base solve and every refined level; see
+ * mgfr_set_relaxation32, with the same reset to 1 once a level's float64
+ * residual grows).  Default 1.  Errors: MGFR_ERR_ARG unless 0 < omega < 2. */
+int mgfr_amr_set_relaxation32(mgfr_amr *amr, double omega);
 /* pos: float32 [np][3] (unit masses); u0: float64 [N0^3] output (base solution) or
  * NULL; st: HOST array of refine_levels + 1 stats (level 0 = base) or NULL.
  * The base assignment bins the particles (see mgfr_reserve_particles); a call

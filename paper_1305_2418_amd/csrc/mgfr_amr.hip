@@ -712,6 +712,7 @@ struct mgfr_amr {
     std::vector<int> horg[kMaxRef + 1];
     mgfr_stats st[kMaxRef + 1];
     double beta = 0, C = 0, fbar = 0;
+    double omega32 = 1.0;  // relaxation factor of the refined levels' float32 correction sweeps
 };
 
 namespace {
@@ -935,7 +936,8 @@ int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
         // to the float64 cycles from the prolonged guess after 3 consecutive
         // residual increases or a non-finite residual
         MxConst KM[kSub];
-        for (int m = 0; m < kSub; ++m) KM[m] = MxConst{(float)K.ih2[m], (float)bC, (float)q, (float)A->p.max_du};
+        for (int m = 0; m < kSub; ++m)
+            KM[m] = MxConst{(float)K.ih2[m], (float)bC, (float)q, (float)A->p.max_du, (float)A->omega32};
         for (int m = 0; m < kSub; ++m)
             k_amrx_init<<<grid_of((size_t)L.nb * sub_vol(m)), 256, 0, A->stream>>>(L, m);
         int grow = 0;
@@ -947,6 +949,8 @@ int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
             if (cyc == 0) st.res0 = res;
             else {
                 grow = (res > prev) ? grow + 1 : 0;
+                if (grow)  // over-relaxation off for the rest of this level's solve
+                    for (int m = 0; m < kSub; ++m) KM[m].omega = 1.0f;
                 if (cyc - 1 < MGFR_MAX_HIST) st.res_hist[cyc - 1] = res;
             }
             prev = res;
@@ -1052,6 +1056,15 @@ extern "C" int mgfr_amr_create(const mgfr_params *p, int64_t max_blocks, void *s
 }
 
 extern "C" void mgfr_amr_destroy(mgfr_amr *A) { amr_free(A); }
+
+extern "C" int mgfr_amr_set_relaxation32(mgfr_amr *A, double omega)
+{
+    if (!A) return set_error(MGFR_ERR_ARG, "amr is NULL");
+    int rc = mgfr_set_relaxation32(A->base, omega);  // validates omega
+    if (rc) return rc;
+    A->omega32 = omega;
+    return MGFR_OK;
+}
 
 extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double *u0_out, mgfr_stats *st_levels)
 {

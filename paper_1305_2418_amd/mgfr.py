@@ -154,6 +154,7 @@ def lib() -> C.CDLL:
         L.mgfr_amr_create.argtypes = [C.POINTER(_Params), C.c_int64, _VP, C.POINTER(_VP)]
         L.mgfr_amr_destroy.argtypes = [_VP]
         L.mgfr_amr_destroy.restype = None
+        L.mgfr_amr_set_relaxation32.argtypes = [_VP, C.c_double]
         L.mgfr_amr_solve.argtypes = [_VP, _VP, C.c_int64, _VP, _VP]
         L.mgfr_amr_num_blocks.argtypes = [_VP, C.c_int]
         L.mgfr_amr_num_blocks.restype = C.c_int64
@@ -502,6 +503,10 @@ class Amr:
             self.close()
         except Exception:
             pass
+
+    def set_relaxation32(self, omega: float):
+        """Over-relaxation factor of the float32 correction sweeps (base and refined levels)."""
+        _check(lib().mgfr_amr_set_relaxation32(self._h, float(omega)))
 
     def solve(self, pos: torch.Tensor, allow_not_converged=False):
         """Returns (u0 [N0^3] tensor, [Stats per level])."""

@@ -13,13 +13,15 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-def _compare(N0, nref, fr0, a, seed, precision, tol_rel):
+def _compare(N0, nref, fr0, a, seed, precision, tol_rel, omega=None):
     from paper_1305_2418_amd import mgfr
     pos = synth.clustered_load(N0, 100.0, rms=5.0, seed=seed, n_halos=50, profile="nfw")
     s_o, us, ms, sts = O.amr_solve(O.params(mesh=N0, fr0_abs=fr0, a=a), nref, pos.numpy())
     assert s_o == 0
     amr = mgfr.Amr(mgfr.Params(mesh=N0, fr0_abs=fr0, a=a, refine_levels=nref, precision=precision),
                    max_blocks=20000)
+    if omega is not None:
+        amr.set_relaxation32(omega)
     u0, st = amr.solve(pos.to(DEV))
     assert all(s.status == 0 for s in st)
     assert np.abs(u0.cpu().numpy() - us[0]).max() <= tol_rel * max(1.0, np.abs(us[0]).max())
@@ -50,6 +52,15 @@ def test_amr_mixed_base_matches_oracle():
     from paper_1305_2418_amd import mgfr
     print("[case] amr mixed base", flush=True)
     _compare(32, 2, 1e-6, 1.0, 4, mgfr.MIXED, 1e-6)
+
+
+@pytest.mark.parametrize("omega", [1.2, 1.6])
+def test_amr_mixed_relaxed_matches_oracle(omega):
+    """Over-relaxed float32 correction sweeps on the base and refined levels
+    change only the cycle counts: the answer is the oracle's."""
+    from paper_1305_2418_amd import mgfr
+    print(f"[case] amr mixed omega={omega}", flush=True)
+    _compare(64, 2, 1e-6, 0.7, 6, mgfr.MIXED, 1e-6, omega=omega)
 
 
 def test_amr_rejects_bad_arguments():

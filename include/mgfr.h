@@ -76,7 +76,8 @@ typedef struct mgfr_params {
     double tol;      /* accept when max|f - L(u)| / D <= tol, D = max|f| (Sec. 3.3 step 8); > 0 */
     int pre_smooth;  /* red-black sweeps before restriction, >= 0 */
     int post_smooth; /* red-black sweeps after the correction, >= 0 */
-    int coarse_sweeps; /* sweeps on the 4^3 coarsest grid, >= 1 */
+    int coarse_sweeps; /* sweeps on the coarsest grid (the 4^3 level; on refined levels of the
+                          adaptive solver, their one-cell-per-block sublevel), >= 1 */
     int max_vcycles; /* V-cycle limit, >= 0 */
     int prolong;     /* MGFR_PROLONG_LINEAR or MGFR_PROLONG_INJECT */
     int precision;   /* MGFR_FP64 or MGFR_MIXED */

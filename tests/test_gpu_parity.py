@@ -334,6 +334,36 @@ def test_assign_rejects_nonfinite():
     assert ei.value.code == mg.MGFR_ERR_NONFINITE
 
 
+@pytest.mark.parametrize("binning", [True, False])
+def test_assign_and_force_edge_particle_counts(binning):
+    """Degenerate and ragged particle counts: zero particles are rejected by the
+    assignment (the mean mass is undefined) and are a no-op for the force;
+    1, 7 and 1007 particles match the oracle (CIC) and the force stays finite."""
+    import ctypes as C
+    mg = _mg()
+    N = 16
+    s = mg.Solver(_params(mg, N), binning=binning)
+    L = mg.lib()
+    d = torch.zeros((N, N, N), dtype=torch.float64, device=DEV)
+    p0 = torch.zeros((1, 3), dtype=torch.float32, device=DEV)
+    acc = torch.zeros((1, 3), dtype=torch.float32, device=DEV)
+    assert L.mgfr_assign_density(s._h, p0.data_ptr(), None, 0, d.data_ptr()) == mg.MGFR_ERR_ARG
+    assert L.mgfr_fifth_force(s._h, d.data_ptr(), p0.data_ptr(), 0, acc.data_ptr()) == mg.MGFR_OK
+    assert L.mgfr_fifth_force(s._h, d.data_ptr(), p0.data_ptr(), -1, acc.data_ptr()) == mg.MGFR_ERR_ARG
+    g = torch.Generator().manual_seed(3)
+    for npart in (1, 7, 1007):
+        print(f"[case] {npart} particles, binning={binning}", flush=True)
+        pos = (torch.rand((npart, 3), generator=g) * 130.0 - 15.0).float()  # some outside the box: wrapped
+        ref = O.density_contrast(O.cic_assign(N, 100.0, pos.numpy()))
+        got = s.assign_density(pos.to(DEV)).cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+        u = torch.tensor(-0.01 * ref, device=DEV)
+        a = s.fifth_force(u, pos.to(DEV)).cpu().numpy()
+        aref = O.fifth_force(O.params(mesh=N), -0.01 * ref, pos.numpy())
+        assert np.all(np.isfinite(a))
+        assert np.all(np.abs(a - aref) <= 6e-8 * np.abs(aref) + 1e-10 * np.abs(aref).max())
+
+
 # ----------------------------------------------------------------------- fifth force
 
 @pytest.mark.parametrize("N,a", [(32, 1.0), (64, 0.7)])

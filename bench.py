@@ -159,7 +159,7 @@ def measure_copy(dev, log):
     return gbs
 
 
-def run_mode(mode, args, pos, dev, log, a=None):
+def run_mode(mode, args, pos, dev, log, a=None, dfr_ref=None):
     import numpy as np
     import torch
     from paper_1305_2418_amd import mgfr
@@ -186,6 +186,8 @@ def run_mode(mode, args, pos, dev, log, a=None):
     u = torch.zeros_like(delta)
     acc = torch.empty((pos.shape[0], 3), dtype=torch.float32, device=dev)
 
+    last = {}
+
     def step(timing=False):
         solver.set_timing(timing)
         solver.assign_density(pos, out=delta)
@@ -195,6 +197,7 @@ def run_mode(mode, args, pos, dev, log, a=None):
             u.zero_()
         _, dfr, st = solver.solve(delta, u=u, want_dfr=True)
         solver.fifth_force(u, pos, out=acc)
+        last["dfr"] = dfr
         return st
 
     for _ in range(args.warmup):
@@ -214,7 +217,14 @@ def run_mode(mode, args, pos, dev, log, a=None):
     out = {"ms_per_step": ms, "solve_ms": solve_ms, "cells_per_s": N ** 3 / (ms * 1e-3),
            "solve_cells_per_s": N ** 3 / (solve_ms * 1e-3), "vcycles": [s.vcycles for s in stats],
            "res": stats[-1].res, "fell_back": max(s.fell_back for s in stats), "nn_ms": stats[-1].t_nn_ms,
-           "sweep_launch_ms": sweep_ms, "dfr_max": None}
+           "sweep_launch_ms": sweep_ms, "dfr_max": float(last["dfr"].abs().max())}
+    if dfr_ref is not None:
+        # max-norm relative difference of delta f_R from the float64 solve of the same input
+        out["rel_dfr_vs_fp64"] = float((last["dfr"] - dfr_ref).abs().max() / dfr_ref.abs().max())
+        log(f"[{mode} a={a}] max-norm relative delta f_R difference from the float64 solve: "
+            f"{out['rel_dfr_vs_fp64']:.2e}")
+    if mode == "fp64" and a == args.a:
+        out["_dfr"] = last["dfr"]
     log(f"[{mode} a={a}] step {ms:.2f} ms, solve {solve_ms:.2f} ms, V-cycles {out['vcycles']}, res {out['res']:.2e}, "
         f"sweep launch {sweep_ms:.3f} ms, nn {out['nn_ms']:.2f} ms")
     if mode == args.mode and a == args.a:
@@ -368,8 +378,12 @@ def main():
     log(f"generated {N}^3 particles in {time.perf_counter() - t0:.1f}s")
 
     results = {}
-    for mode in [m for m in args.compare.split(",") if m and m != args.mode] + [args.mode]:
-        results[mode] = run_mode(mode, args, pos, dev, log)
+    modes = [m for m in args.compare.split(",") if m and m != args.mode] + [args.mode]
+    modes.sort(key=lambda m: m != "fp64")  # the float64 solve first: the others are compared with it
+    for mode in modes:
+        ref = results["fp64"].get("_dfr") if "fp64" in results else None
+        results[mode] = run_mode(mode, args, pos, dev, log, dfr_ref=ref)
+    results.get("fp64", {}).pop("_dfr", None)
     head = results[args.mode]
     other_a = {}
     for a in [float(x) for x in args.also_a.split(",") if x]:

@@ -63,6 +63,36 @@ def test_amr_mixed_relaxed_matches_oracle(omega):
     _compare(64, 2, 1e-6, 0.7, 6, mgfr.MIXED, 1e-6, omega=omega)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fully_refined_level_matches_uniform_oracle(precision):
+    """Every base cell holds more than 8 particles: level 1 covers the whole
+    periodic box, and the library's level-1 field must equal the uniform
+    oracle's solve at twice the resolution."""
+    from paper_1305_2418_amd import mgfr
+    N0 = 32
+    print(f"[case] fully refined level, {precision}", flush=True)
+    pos = synth.clustered_load(128, 100.0, rms=0.3, seed=6, n_halos=0)
+    idx = np.floor(pos.numpy() / (100.0 / N0)).astype(int) % N0
+    cnt = np.zeros((N0,) * 3, int)
+    np.add.at(cnt, (idx[:, 0], idx[:, 1], idx[:, 2]), 1)
+    assert cnt.min() > 8
+    prec = mgfr.FP64 if precision == "fp64" else mgfr.MIXED
+    amr = mgfr.Amr(mgfr.Params(mesh=N0, fr0_abs=1e-5, refine_levels=1, precision=prec, tol=1e-10),
+                   max_blocks=20000)
+    u0, st = amr.solve(pos.to(DEV))
+    org, ul = amr.level(1)
+    assert len(org) == (2 * N0 // 8) ** 3 and all(s.status == 0 for s in st)
+    d1 = O.density_contrast(O.cic_assign(2 * N0, 100.0, pos.numpy()))
+    s1, u1, _, _ = O.solve(O.params(mesh=2 * N0, fr0_abs=1e-5, tol=1e-10), d1)
+    ul = ul.cpu().numpy()
+    full = np.empty((2 * N0,) * 3)
+    for o, blk in zip(org, ul):
+        full[o[0]:o[0] + 8, o[1]:o[1] + 8, o[2]:o[2] + 8] = blk
+    err = np.abs(full - u1).max() / np.abs(u1).max()
+    print(f"  level-1 cycles {st[1].vcycles}, rel diff from the uniform 64^3 oracle {err:.2e}")
+    assert err <= 1e-8
+
+
 def test_amr_rejects_bad_arguments():
     from paper_1305_2418_amd import mgfr
     with pytest.raises(mgfr.MgfrError):

@@ -490,6 +490,25 @@ def test_power_ratio_shells_and_closed_forms():
     assert live.sum() == 4 and np.allclose(ratio[live], 16 / 9, rtol=1e-12)
 
 
+def test_fully_refined_level_is_the_uniform_solve():
+    """When every base cell holds more than 8 particles, level 1 covers the whole
+    periodic box: no frozen ghosts remain, so the adaptive solver's level-1
+    field must be the uniform solve at twice the resolution (Sec. 3.3 one-way
+    interface with nothing outside; both to tolerance 1e-10)."""
+    N0 = 16
+    pos = synth.clustered_load(48, 100.0, rms=0.3, seed=5, n_halos=0).numpy()
+    idx = np.floor(pos / (100.0 / N0)).astype(int) % N0
+    cnt = np.zeros((N0,) * 3, int)
+    np.add.at(cnt, (idx[:, 0], idx[:, 1], idx[:, 2]), 1)
+    assert cnt.min() > 8
+    s, us, ms, sts = O.amr_solve(O.params(mesh=N0, fr0_abs=1e-5, tol=1e-10), 1, pos)
+    assert s == 0 and ms[1].all()
+    d1 = O.density_contrast(O.cic_assign(2 * N0, 100.0, pos))
+    s1, u1, _, _ = O.solve(O.params(mesh=2 * N0, fr0_abs=1e-5, tol=1e-10), d1)
+    assert s1 == 0
+    assert np.abs(us[1] - u1).max() <= 1e-9 * np.abs(u1).max()
+
+
 # ------------------------------------------------------------------------ T8 invariants
 
 def _cfg1_delta(N=32, seed=1, rms=1.0, halos=0):

@@ -172,6 +172,26 @@ int mgfr_set_relaxation32(mgfr_ctx *ctx, double omega);
 int mgfr_assign_density(mgfr_ctx *ctx, const float *pos, const double *mass, int64_t np,
                         double *delta);
 
+/* Allocation-free variant of mgfr_assign_density, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It needs no context: mesh (a power of two,
+ * 8 <= mesh <= 1024) and box (> 0, Mpc/h) describe the periodic N^3 mesh, and
+ * the work is enqueued on `stream` (a hipStream_t as void*, NULL = default).
+ * pos, mass, np and delta as for mgfr_assign_density; particles are visited in
+ * index order (no binning).  delta (caller-owned, float64 [N^3]) first holds
+ * the cell masses and is then normalised in place.  The library allocates
+ * nothing: the reduction workspace (2048 partial sums, the total mass and the
+ * non-finite flag; 16.4 KB) is a fixed array in device memory, one per GPU,
+ * held until the process ends and reset by every call.  Calls that overlap on
+ * one GPU (two host threads, or two streams in flight) race on that array and
+ * must be serialised by the caller.  The call synchronises `stream` once to
+ * read the total mass and the flag.
+ * Errors: MGFR_ERR_ARG (NULL pointers, np < 1, mesh not a power of two in
+ * [8, 1024], box), MGFR_ERR_NONFINITE (non-finite position or mass, or a
+ * total mass that is not positive), MGFR_ERR_HIP. */
+int mgfr_assign_density_noalloc(int mesh, double box, void *stream, const float *pos, const double *mass,
+                                int64_t np, double *delta);
+
 /* Workspace for particle binning (Sec. 3.1 assignment, Sec. 2 force): four
  * uint32 arrays of max_np entries plus radix-sort scratch, owned by the
  * context, freed by mgfr_destroy or by a later call with a larger max_np

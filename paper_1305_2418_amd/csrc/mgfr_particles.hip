@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace mgfr {
 
@@ -365,6 +366,15 @@ __global__ __launch_bounds__(kBlock) void k_force_binned(const double *__restric
     }
 }
 
+// Zero an array of n doubles and one int flag: the clearing step of the
+// allocation-free assignment (a kernel, not a memset, so that a captured
+// graph replays it faithfully).
+__global__ __launch_bounds__(kBlock) void k_zero_mesh(double *__restrict__ x, size_t n, int *__restrict__ flag)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 0;
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock) x[t] = 0.0;
+}
+
 inline unsigned grid_for(size_t n, size_t cap) { return (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, cap); }
 
 }  // namespace
@@ -449,5 +459,83 @@ extern "C" int mgfr_set_binning(mgfr_ctx *c, int on)
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
     c->binning = on ? 1 : 0;
     c->perm_np = 0;
+    return MGFR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free assignment.  The context-free variant of
+// mgfr_assign_density keeps its reduction workspace in a file-scope device
+// array instead of a context: kStaticParts partial sums of the total mass,
+// the total, and the non-finite flag.  Each device the library runs on holds
+// one copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for that device.
+namespace {
+
+constexpr int kStaticParts = 2048;
+constexpr int kStaticMaxMesh = 1024;
+constexpr int kStaticMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticParts + 4];
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kStaticMaxDevices] = {};
+
+int static_scratch(double **out)
+{
+    int dev = 0;
+    MGFR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticMaxDevices)
+        return set_error(MGFR_ERR_ARG, "device %d is beyond the %d devices the allocation-free assignment supports",
+                         dev, kStaticMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double *ptr = nullptr;
+        MGFR_HIP(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return set_error(MGFR_ERR_HIP, "hipGetSymbolAddress returned NULL for the assignment scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MGFR_OK;
+}
+
+}  // namespace
+
+extern "C" int mgfr_assign_density_noalloc(int mesh, double box, void *stream, const float *pos, const double *mass,
+                                           int64_t np, double *delta)
+{
+    if (!pos) return set_error(MGFR_ERR_ARG, "pos is NULL");
+    if (!delta) return set_error(MGFR_ERR_ARG, "delta is NULL");
+    if (np < 1) return set_error(MGFR_ERR_ARG, "np must be >= 1, got %lld", (long long)np);
+    if (mesh < 8 || (mesh & (mesh - 1)))
+        return set_error(MGFR_ERR_ARG, "mesh must be a power of two >= 8, got %d", mesh);
+    if (mesh > kStaticMaxMesh)
+        return set_error(MGFR_ERR_ARG, "mesh %d exceeds the maximum %d of the allocation-free assignment", mesh,
+                         kStaticMaxMesh);
+    if (!(box > 0) || !std::isfinite(box)) return set_error(MGFR_ERR_ARG, "box must be > 0 and finite");
+    const size_t pblocks = (size_t)((np + kBlock - 1) / kBlock);
+    if (pblocks > 0x7fffffffULL) return set_error(MGFR_ERR_ARG, "np too large");
+    double *sc = nullptr;
+    if (int e = static_scratch(&sc)) return e;
+    double *partial = sc, *total = sc + kStaticParts;
+    int *flag = (int *)(sc + kStaticParts + 1);
+    int lg = 0;
+    while ((1 << lg) < mesh) ++lg;
+    const double h = box / mesh;
+    const size_t n = (size_t)mesh * mesh * mesh;
+    hipStream_t st = (hipStream_t)stream;
+    k_zero_mesh<<<grid_for(n, 8192), kBlock, 0, st>>>(delta, n, flag);
+    k_cic_scatter<<<(unsigned)pblocks, kBlock, 0, st>>>(pos, mass, np, lg, h, delta, flag);
+    const unsigned g = grid_for(n, (size_t)kStaticParts);
+    k_sum_partial<<<g, kBlock, 0, st>>>(delta, n, partial);
+    k_sum_final<<<1, 1024, 0, st>>>(partial, (int)g, total);
+    k_delta<<<grid_for(n, 8192), kBlock, 0, st>>>(delta, n, total);
+    MGFR_HIP(hipGetLastError());
+    double back[2] = {0.0, 0.0};  // total, flag word
+    MGFR_HIP(hipMemcpyAsync(back, total, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    MGFR_HIP(hipStreamSynchronize(st));
+    int hflag = 0;
+    memcpy(&hflag, &back[1], sizeof(int));
+    if (hflag) return set_error(MGFR_ERR_NONFINITE, "a particle position or mass is not finite");
+    if (!(back[0] > 0) || !std::isfinite(back[0]))
+        return set_error(MGFR_ERR_NONFINITE, "total assigned mass is not positive and finite");
     return MGFR_OK;
 }

@@ -128,6 +128,7 @@ def lib() -> C.CDLL:
         L.mgfr_effective_density.argtypes = [_VP, _VP, _VP, _VP]
         L.mgfr_power_ratio.argtypes = [_VP, _VP, _VP, C.c_int, _VP, _VP, _VP, _VP]
         L.mgfr_assign_density.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
+        L.mgfr_assign_density_noalloc.argtypes = [C.c_int, C.c_double, _VP, _VP, _VP, C.c_int64, _VP]
         L.mgfr_reserve_particles.argtypes = [_VP, C.c_int64]
         L.mgfr_set_binning.argtypes = [_VP, C.c_int]
         L.mgfr_solve.argtypes = [_VP, _VP, _VP, _VP, C.POINTER(_Stats)]
@@ -202,6 +203,23 @@ def background(p: Params):
     pc = p.to_c()
     _check(lib().mgfr_background(C.byref(pc), C.byref(fb), C.byref(beta), C.byref(Cc)))
     return fb.value, beta.value, Cc.value
+
+
+def assign_density_noalloc(pos: torch.Tensor, mesh: int, box: float, mass: torch.Tensor | None = None,
+                           out: torch.Tensor | None = None) -> torch.Tensor:
+    """Context-free CIC assignment whose library side allocates nothing (its
+    workspace is a fixed device array); ``out`` may be passed pre-allocated."""
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be [np, 3]")
+    npart = pos.shape[0]
+    shape = (mesh, mesh, mesh)
+    pp = _dev(pos, torch.float32, None, "pos")
+    mp = _dev(mass, torch.float64, (npart,), "mass", allow_none=True)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=pos.device)
+    op = _dev(out, torch.float64, shape, "delta")
+    _check(lib().mgfr_assign_density_noalloc(int(mesh), float(box), _stream_ptr(), pp, mp, npart, op))
+    return out
 
 
 class Solver:

@@ -4,9 +4,13 @@
  * TEST INFRASTRUCTURE ONLY.  This file is the parity judge for the HIP
  * library: only the test-suite, the smoke check and the CPU-baseline leg of
  * the benchmark load it.  It shares no code, header, table or helper with the
- * GPU path; it is single-threaded, unblocked and unfused on purpose so that it
- * can be read against the paper (Puchwein, Baldi & Springel 2013, "Modified
- * Gravity-GADGET") line by line.
+ * GPU path; it is unblocked and unfused on purpose so that it can be read
+ * against the paper (Puchwein, Baldi & Springel 2013, "Modified
+ * Gravity-GADGET") line by line.  Built plainly it is single-threaded; built
+ * with -fopenmp the loops whose iterations are independent (the cells of one
+ * colour of a red-black sweep, operator and transfer evaluations, max-norm
+ * reductions) run on several threads with bitwise the same results, since no
+ * floating-point sum changes its order.
  *
  * Units and form.  Positions are comoving Mpc/h, the cell side h = L/N is
  * comoving.  The paper's discrete field equation (Sec. 3.2, Eq.
@@ -29,6 +33,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_C_OVER_H0 2997.92458   /* c/H0 in Mpc/h */
 #define OR_C_KMS 299792.458       /* c in km/s */
@@ -53,6 +60,25 @@ typedef struct {
     double res0, res, scale;
     double res_hist[OR_MAX_HIST];
 } or_stats;
+
+/* Threads used by the OpenMP build (n > 0 sets them); 1 for the plain build. */
+int or_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* max of two magnitudes with NaN winning (a NaN residual must not be hidden) */
+static double nanmax(double a, double b)
+{
+    if (a != a || b != b) return NAN;
+    return a > b ? a : b;
+}
 
 /* ---------------------------------------------------------------- background */
 
@@ -119,6 +145,7 @@ void or_source(const or_params *p, const double *delta, double *f)
     or_background(p, &fb, &beta, &C);
     size_t n3 = (size_t)p->mesh * p->mesh * p->mesh;
     double s = beta * p->omega_m / (p->a * p->a * p->a);
+#pragma omp parallel for
     for (size_t c = 0; c < n3; ++c) f[c] = s * delta[c];
 }
 
@@ -134,6 +161,7 @@ void or_screened_guess(const or_params *p, const double *delta, double *u)
     or_background(p, &fb, &beta, &C);
     size_t n3 = (size_t)p->mesh * p->mesh * p->mesh;
     double s = p->omega_m / (p->a * p->a * p->a) / C;
+#pragma omp parallel for
     for (size_t c = 0; c < n3; ++c) {
         double d = delta[c] > 0.0 ? delta[c] : 0.0;
         u[c] = -(double)(p->n + 1) * log1p(s * d);
@@ -152,6 +180,7 @@ void or_effective_density(const or_params *p, const double *delta, const double 
     size_t n3 = (size_t)p->mesh * p->mesh * p->mesh;
     double om = p->omega_m / (p->a * p->a * p->a);
     double q = 1.0 / (p->n + 1);
+#pragma omp parallel for
     for (size_t c = 0; c < n3; ++c) out[c] = delta[c] / 3.0 - C * expm1(-q * u[c]) / (3.0 * om);
 }
 
@@ -189,6 +218,7 @@ static double op_cell(const double *u, int N, int i, int j, int k, double ih2,
 void or_apply_L(int N, double h, double bC, int n, const double *u, double *L)
 {
     double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
+#pragma omp parallel for
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j)
             for (int k = 0; k < N; ++k) L[IDX(i, j, k)] = op_cell(u, N, i, j, k, ih2, bC, q, NULL);
@@ -198,6 +228,7 @@ void or_apply_L(int N, double h, double bC, int n, const double *u, double *L)
 void or_apply_J(int N, double h, double bC, int n, const double *u, double *Jout)
 {
     double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
+#pragma omp parallel for
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j)
             for (int k = 0; k < N; ++k) op_cell(u, N, i, j, k, ih2, bC, q, &Jout[IDX(i, j, k)]);
@@ -207,12 +238,19 @@ void or_apply_J(int N, double h, double bC, int n, const double *u, double *Jout
 double or_residual_max(int N, double h, double bC, int n, const double *u, const double *f)
 {
     double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1), mx = 0.0;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j)
-            for (int k = 0; k < N; ++k) {
-                double r = fabs(f[IDX(i, j, k)] - op_cell(u, N, i, j, k, ih2, bC, q, NULL));
-                if (!(r <= mx)) mx = r; /* NaN propagates */
-            }
+#pragma omp parallel
+    {
+        double lm = 0.0;
+#pragma omp for
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                for (int k = 0; k < N; ++k) {
+                    double r = fabs(f[IDX(i, j, k)] - op_cell(u, N, i, j, k, ih2, bC, q, NULL));
+                    if (!(r <= lm)) lm = r; /* NaN propagates */
+                }
+#pragma omp critical
+        mx = nanmax(mx, lm);
+    }
     return mx;
 }
 
@@ -226,6 +264,8 @@ void or_ngs_sweep(int N, double h, double bC, int n, double max_du, double *u, c
 {
     double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
     for (int colour = 0; colour < 2; ++colour)
+        /* the cells of one colour have neighbours of the other colour only */
+#pragma omp parallel for
         for (int i = 0; i < N; ++i)
             for (int j = 0; j < N; ++j)
                 for (int k = 0; k < N; ++k) {
@@ -244,6 +284,7 @@ void or_ngs_sweep(int N, double h, double bC, int n, double max_du, double *u, c
 void or_restrict(int Nf, const double *fine, double *coarse)
 {
     int N = Nf / 2;
+#pragma omp parallel for
     for (int I = 0; I < N; ++I)
         for (int J = 0; J < N; ++J)
             for (int K = 0; K < N; ++K) {
@@ -264,6 +305,7 @@ void or_restrict(int Nf, const double *fine, double *coarse)
 void or_prolong_add(int Nf, int mode, const double *uc, const double *ubar, double *u)
 {
     int N = Nf / 2;
+#pragma omp parallel for
     for (int i = 0; i < Nf; ++i)
         for (int j = 0; j < Nf; ++j)
             for (int k = 0; k < Nf; ++k) {
@@ -314,11 +356,13 @@ static void vcycle(or_hier *H, int l, const or_params *p, double bC)
     size_t nc3 = (size_t)Nc * Nc * Nc;
     /* residual r = f - L(u) on this level */
     or_apply_L(N, h, bC, p->n, H->u[l], H->tmp[l]);
+#pragma omp parallel for
     for (size_t c = 0; c < n3; ++c) H->tmp[l][c] = H->f[l][c] - H->tmp[l][c];
     /* coarse problem: f_c = L_c(R u) + R(f - L(u)), initial guess R u */
     or_restrict(N, H->u[l], H->ubar[l + 1]);
     or_restrict(N, H->tmp[l], H->f[l + 1]);
     or_apply_L(Nc, H->hs[l + 1], bC, p->n, H->ubar[l + 1], H->tmp[l + 1]);
+#pragma omp parallel for
     for (size_t c = 0; c < nc3; ++c) H->f[l + 1][c] += H->tmp[l + 1][c];
     memcpy(H->u[l + 1], H->ubar[l + 1], nc3 * sizeof(double));
     vcycle(H, l + 1, p, bC);
@@ -380,7 +424,10 @@ int or_solve(const or_params *p, const double *delta, double *u, double *dfr, or
     st->vcycles = cyc;
     st->res = res;
     st->status = status;
-    if (dfr) for (size_t c = 0; c < n3; ++c) dfr[c] = -fb * expm1(u[c]);
+    if (dfr) {
+#pragma omp parallel for
+        for (size_t c = 0; c < n3; ++c) dfr[c] = -fb * expm1(u[c]);
+    }
     free(H.f[0]);
     hier_free(&H);
     return status;
@@ -426,7 +473,9 @@ void or_fifth_force(const or_params *p, const double *u, int64_t np, const float
     size_t n3 = (size_t)N * N * N;
     double *fr = malloc(n3 * sizeof(double));
     double *g = malloc(3 * n3 * sizeof(double));
+#pragma omp parallel for
     for (size_t c = 0; c < n3; ++c) fr[c] = -fb * exp(u[c]);
+#pragma omp parallel for
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j)
             for (int k = 0; k < N; ++k) {
@@ -436,6 +485,7 @@ void or_fifth_force(const or_params *p, const double *u, int64_t np, const float
                 g[3 * c + 2] = (fr[IDX(i, j, (k + 1) % N)] - fr[IDX(i, j, (k + N - 1) % N)]) / (2 * h);
             }
     double pref = OR_C_KMS * OR_C_KMS / (2.0 * p->a);
+#pragma omp parallel for
     for (int64_t q = 0; q < np; ++q) {
         long i0[3];
         double t[3];
@@ -468,6 +518,7 @@ void or_residual_at(int N, double h, double bC, int n, const double *u, const do
                     const int64_t *cells, double *out)
 {
     double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
+#pragma omp parallel for
     for (int64_t s = 0; s < count; ++s) {
         int64_t c = cells[s];
         int k = (int)(c % N), j = (int)((c / N) % N), i = (int)(c / ((int64_t)N * N));
@@ -515,6 +566,7 @@ void or_fifth_force_at(const or_params *p, const double *u, int64_t np, const fl
     or_background(p, &fb, &beta, &C);
     double pref = OR_C_KMS * OR_C_KMS / (2.0 * p->a);
 #define FR(i, j, k) (-fb * exp(u[((size_t)wrapi(i, N) * N + wrapi(j, N)) * N + wrapi(k, N)]))
+#pragma omp parallel for
     for (int64_t q = 0; q < np; ++q) {
         long i0[3];
         double t[3];

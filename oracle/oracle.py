@@ -13,18 +13,22 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mgfr_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+LIB = os.path.join(HERE, "liboracle.so")          # plain build, one thread
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")  # the same source with -fopenmp
 
 C_OVER_H0 = 2997.92458
 C_KMS = 299792.458
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, single thread)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (-O2, no fast-math): the plain single-thread
+    build and the OpenMP build of the same source (bitwise the same results)."""
+    for out, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            tmp = out + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", *extra, "-o", tmp, SRC, "-lm"],
+                                  stderr=subprocess.DEVNULL)
+            os.replace(tmp, out)
     return LIB
 
 
@@ -41,15 +45,20 @@ class Stats(C.Structure):
                 ("res", C.c_double), ("scale", C.c_double), ("res_hist", C.c_double * 512)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        L = C.CDLL(LIB)
+def lib(serial: bool | None = None):
+    """The oracle library: the OpenMP build unless serial (or MGFR_ORACLE_SERIAL=1)."""
+    if serial is None:
+        serial = os.environ.get("MGFR_ORACLE_SERIAL", "0") == "1"
+    path = LIB if serial else LIB_OMP
+    if path not in _libs:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            build(force=False)
+        L = C.CDLL(path)
+        L.or_threads.argtypes = [C.c_int]
+        L.or_threads.restype = C.c_int
         dp = C.POINTER(C.c_double)
         fp = C.POINTER(C.c_float)
         L.or_background.argtypes = [C.POINTER(Params), dp, dp, dp]
@@ -78,8 +87,13 @@ def lib():
         L.or_amr_solve.argtypes = [C.POINTER(Params), C.c_int, C.c_int64, fp, C.POINTER(dp),
                                    C.POINTER(C.c_void_p), C.POINTER(Stats)]
         L.or_amr_solve.restype = C.c_int
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
+
+
+def threads(n: int = 0, serial: bool | None = None) -> int:
+    """Set (n > 0) and return the oracle's thread count."""
+    return int(lib(serial).or_threads(int(n)))
 
 
 def _d(a):
@@ -105,18 +119,18 @@ def background(p: Params):
     return fb.value, beta.value, Cc.value
 
 
-def cic_assign(N, box, pos, mass=None):
+def cic_assign(N, box, pos, mass=None, serial=None):
     pos = np.ascontiguousarray(pos, dtype=np.float32)
     m = np.zeros((N, N, N), np.float64)
     mp = None if mass is None else _d(np.ascontiguousarray(mass, np.float64))
-    lib().or_cic_assign(N, box, pos.shape[0], _f(pos), mp, _d(m))
+    lib(serial).or_cic_assign(N, box, pos.shape[0], _f(pos), mp, _d(m))
     return m
 
 
-def density_contrast(m):
+def density_contrast(m, serial=None):
     m = np.ascontiguousarray(m, np.float64)
     d = np.empty_like(m)
-    lib().or_delta(m.shape[0], _d(m), _d(d))
+    lib(serial).or_delta(m.shape[0], _d(m), _d(d))
     return d
 
 
@@ -213,14 +227,14 @@ def num_levels(N):
     return lib().or_num_levels(N)
 
 
-def solve(p, delta, u0=None, want_dfr=True):
+def solve(p, delta, u0=None, want_dfr=True, serial=None):
     """Returns (status, u, dfr, stats)."""
     delta = np.ascontiguousarray(delta, np.float64)
     N = p.mesh
     u = np.zeros((N, N, N), np.float64) if u0 is None else np.array(u0, np.float64, order="C", copy=True)
     dfr = np.empty_like(u) if want_dfr else None
     st = Stats()
-    s = lib().or_solve(C.byref(p), _d(delta), _d(u), _d(dfr) if want_dfr else None, C.byref(st))
+    s = lib(serial).or_solve(C.byref(p), _d(delta), _d(u), _d(dfr) if want_dfr else None, C.byref(st))
     return s, u, dfr, st
 
 
@@ -230,11 +244,11 @@ def vcycle_once(p, f, u):
     return u
 
 
-def fifth_force(p, u, pos):
+def fifth_force(p, u, pos, serial=None):
     pos = np.ascontiguousarray(pos, np.float32)
     u = np.ascontiguousarray(u, np.float64)
     acc = np.empty((pos.shape[0], 3), np.float64)
-    lib().or_fifth_force(C.byref(p), _d(u), pos.shape[0], _f(pos), _d(acc))
+    lib(serial).or_fifth_force(C.byref(p), _d(u), pos.shape[0], _f(pos), _d(acc))
     return acc
 
 

@@ -630,3 +630,26 @@ def test_sampled_oracle_routines_agree_with_full_ones():
     assert np.allclose(O.residual_at(u, f, box / N, bC, cells), r_full.reshape(-1)[cells], rtol=1e-13, atol=1e-15)
     sub = pos[::97]
     assert np.allclose(O.fifth_force_at(p, u, sub), O.fifth_force(p, u, sub), rtol=1e-12)
+
+
+# ------------------------------------------------------- threaded build of the oracle
+
+def test_openmp_build_is_bitwise_the_serial_oracle():
+    """The OpenMP build parallelises only loops with independent iterations
+    (one colour of a red-black sweep, operator and transfer evaluations, max
+    reductions), so a whole solve, the source and the fifth force agree bit for
+    bit with the single-thread build."""
+    if O.threads() < 2:
+        pytest.skip("one host thread")
+    N = 32
+    pos = synth.clustered_load(N, 100.0, rms=5.0, seed=5).numpy()
+    d1 = O.density_contrast(O.cic_assign(N, 100.0, pos, serial=True), serial=True)
+    d2 = O.density_contrast(O.cic_assign(N, 100.0, pos, serial=False), serial=False)
+    assert np.array_equal(d1, d2)
+    p = O.params(mesh=N, fr0_abs=1e-6, pre_smooth=4, post_smooth=4, prolong=1)
+    s1, u1, f1, st1 = O.solve(p, d1, serial=True)
+    s2, u2, f2, st2 = O.solve(p, d1, serial=False)
+    assert s1 == s2 == 0 and st1.vcycles == st2.vcycles
+    assert np.array_equal(u1, u2) and np.array_equal(f1, f2)
+    assert list(st1.res_hist[:st1.vcycles]) == list(st2.res_hist[:st2.vcycles])
+    assert np.array_equal(O.fifth_force(p, u1, pos, serial=True), O.fifth_force(p, u1, pos, serial=False))

@@ -475,18 +475,21 @@ def test_fused_solve_matches_oracle(N, pre, post, fr0):
     mg = _mg()
     print(f"[case] fused solve N={N} pre={pre} post={post}", flush=True)
     d = _delta(N, 5.0, 14, halos=20)
-    k = None
-    if N <= 128:
-        s_o, u_o, dfr_o, st_o = O.solve(_oparams(N, fr0_abs=fr0, pre_smooth=pre, post_smooth=post), d)
-        k = st_o.vcycles
+    s_o, u_o, dfr_o, st_o = O.solve(_oparams(N, fr0_abs=fr0, pre_smooth=pre, post_smooth=post), d)
+    assert s_o == 0
+    k = st_o.vcycles
     s = mg.Solver(_params(mg, N, fr0_abs=fr0, pre_smooth=pre, post_smooth=post))
     s.set_fused_min_mesh(64)
     u, dfr, st = s.solve(torch.tensor(d, device=DEV))
     assert st.status == 0
-    if k is not None:
-        assert abs(st.vcycles - k) <= 1
-        if st.vcycles == k:
-            assert _rel(dfr.cpu().numpy(), dfr_o) < 1e-10
+    assert abs(st.vcycles - k) <= 1
+    if st.vcycles != k:  # same schedule: re-run with exactly the oracle's count
+        s = mg.Solver(_params(mg, N, fr0_abs=fr0, pre_smooth=pre, post_smooth=post, max_vcycles=k, tol=1e-300))
+        s.set_fused_min_mesh(64)
+        u, dfr, st = s.solve(torch.tensor(d, device=DEV), allow_not_converged=True)
+    err = _rel(dfr.cpu().numpy(), dfr_o)
+    print(f"  cycles {st.vcycles} (oracle {k}), rel dfr err {err:.2e}")
+    assert st.vcycles == k and err < 1e-10
     # fused and per-colour kernels agree on the same schedule
     s2 = mg.Solver(_params(mg, N, fr0_abs=fr0, pre_smooth=pre, post_smooth=post,
                            max_vcycles=st.vcycles, tol=1e-300))

@@ -1,0 +1,91 @@
+"""Parity at the schedule the benchmark times, on the 256^3 configuration's loads.
+
+The benchmark runs V(4,4) with injected corrections (Sec. 3.3, prolongation
+by injection), the Newton step limit |du| <= 2, and in the mixed modes float32
+correction sweeps over-relaxed by omega = 1.2.  Loads: N^3 particles on a
+Zel'dovich lattice with mesh rms 5 plus 20 Plummer halos of 1e13-1e15 Msun/h
+(seed 2), |f_R0| in {1e-5, 1e-6}, at N = 128 and at the configuration's own
+size N = 256.
+
+* FP64: exactly the oracle's number of V-cycles (the oracle stops at
+  res <= 1e-8; if the library's count differs, it is re-run with that count),
+  then max |d dfr| / max |dfr| < 1e-10 and the final residuals agree.
+* mixed (omega 1.2): the converged mixed solution (res <= 1e-8, judged in
+  float64) against the oracle iterated to res <= 1e-11, < 1e-6 relative.
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1305_2418_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+SCHED = dict(pre_smooth=4, post_smooth=4, prolong=1, max_du=2.0)
+CASES = [(128, 1e-5), (128, 1e-6), (256, 1e-5), (256, 1e-6)]
+
+
+def _mg():
+    from paper_1305_2418_amd import mgfr
+    return mgfr
+
+
+@functools.lru_cache(maxsize=None)
+def _delta(N):
+    pos = synth.clustered_load(N, 100.0, rms=5.0, seed=2, n_halos=20).numpy()
+    return O.density_contrast(O.cic_assign(N, 100.0, pos))
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(N, fr0):
+    """(cycles, final residual, dfr at res <= 1e-8, dfr at res <= 1e-11)."""
+    d = _delta(N)
+    p = O.params(mesh=N, fr0_abs=fr0, max_vcycles=80, **SCHED)
+    s, u, dfr, st = O.solve(p, d)
+    assert s == 0
+    p2 = O.params(mesh=N, fr0_abs=fr0, max_vcycles=80, tol=1e-11, **SCHED)
+    s2, _, dfr_tight, st2 = O.solve(p2, d, u0=u)
+    assert s2 == 0
+    return st.vcycles, st.res, dfr, dfr_tight
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("N,fr0", CASES)
+def test_fp64_timed_schedule_matches_oracle(N, fr0):
+    mg = _mg()
+    print(f"[case] FP64 V(4,4) inject N={N} fr0={fr0}", flush=True)
+    k, res_o, dfr_o, _ = _oracle(N, fr0)
+    dt = torch.tensor(_delta(N), device=DEV)
+    s = mg.Solver(mg.Params(mesh=N, fr0_abs=fr0, max_vcycles=80, **SCHED))
+    u, dfr, st = s.solve(dt)
+    assert st.status == 0
+    assert abs(st.vcycles - k) <= 1, (st.vcycles, k)
+    if st.vcycles != k:  # same schedule: exactly the oracle's count
+        s = mg.Solver(mg.Params(mesh=N, fr0_abs=fr0, max_vcycles=k, tol=1e-300, **SCHED))
+        u, dfr, st = s.solve(dt, allow_not_converged=True)
+    err = _rel(dfr.cpu().numpy(), dfr_o)
+    print(f"  cycles {st.vcycles} (oracle {k}), res {st.res:.3e} (oracle {res_o:.3e}), rel dfr err {err:.2e}")
+    assert st.vcycles == k
+    assert err < 1e-10
+    assert abs(st.res / res_o - 1) < 1e-3
+
+
+@pytest.mark.parametrize("N,fr0", CASES)
+def test_mixed_timed_schedule_matches_oracle(N, fr0):
+    mg = _mg()
+    print(f"[case] mixed omega 1.2 V(4,4) inject N={N} fr0={fr0}", flush=True)
+    _, _, _, dfr_tight = _oracle(N, fr0)
+    dt = torch.tensor(_delta(N), device=DEV)
+    s = mg.Solver(mg.Params(mesh=N, fr0_abs=fr0, max_vcycles=80, precision=mg.MIXED, **SCHED))
+    s.set_relaxation32(1.2)
+    u, dfr, st = s.solve(dt)
+    assert st.status == 0 and st.res <= 1e-8 and st.fell_back == 0
+    err = _rel(dfr.cpu().numpy(), dfr_tight)
+    print(f"  inner cycles {st.vcycles}, res {st.res:.3e}, rel dfr err vs oracle {err:.2e}")
+    assert err < 1e-6

@@ -340,7 +340,12 @@ int mgfr_conv3d_bwd_weight(const void *x, const void *dz, int B, int S, int Cin,
  * 8^3-cell blocks: a cell of level l-1 holding more than 8 particles
  * (nearest-grid-point count, unit masses) refines the aligned 4^3 group of
  * cells around it.  Level-2 blocks also refine the level-1 blocks within two
- * level-1 cells of them.  Each level starts from, and keeps as fixed ghost
+ * level-1 cells of them.  Masses follow Sec. 3.1 on the composite mesh:
+ * each particle is a cube with the side of the finest cell containing it,
+ * every leaf cell it overlaps (of any level) receives the overlapping
+ * fraction of its mass, and each coarser cell covered by a finer level the
+ * sum of its daughters; delta_l = m / mbar_l - 1 with mbar_l the total mass
+ * over N_l^3.  Each level starts from, and keeps as fixed ghost
  * values around its blocks, the linear prolongation of its parent's
  * solution, and is solved by float64 FAS V-cycles over its blocks at
  * 1/1, 1/2, 1/4 and 1/8 resolution (coarse cells outside the blocks hold the
@@ -360,9 +365,9 @@ void mgfr_amr_destroy(mgfr_amr *amr);
 int mgfr_amr_set_relaxation32(mgfr_amr *amr, double omega);
 /* pos: float32 [np][3] (unit masses); u0: float64 [N0^3] output (base solution) or
  * NULL; st: HOST array of refine_levels + 1 stats (level 0 = base) or NULL.
- * The base assignment bins the particles (see mgfr_reserve_particles); a call
- * with more particles than any before grows that workspace first.  Refinement
- * flags are built on the device; only the block maps reach the host.
+ * Refinement flags are built on the device and only the block maps reach
+ * the host; then one pass over the particles assigns the composite masses.
+ * A non-finite position (or one beyond 1e15 Mpc/h) gives MGFR_ERR_NONFINITE.
  * Returns the worst level status (MGFR_NOT_CONVERGED if a level hit
  * max_vcycles); MGFR_ERR_ARG if a level needs more than max_blocks blocks. */
 int mgfr_amr_solve(mgfr_amr *amr, const float *pos, int64_t np, double *u0, mgfr_stats *st);

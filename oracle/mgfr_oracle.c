@@ -654,6 +654,7 @@ static void sub_sweep(or_sub *S, double bC, double q, double max_du)
 {
     int N = S->N;
     for (int colour = 0; colour < 2; ++colour)
+#pragma omp parallel for
         for (int i = 0; i < N; ++i)
             for (int j = 0; j < N; ++j)
                 for (int k = 0; k < N; ++k) {
@@ -671,14 +672,21 @@ static double sub_resmax(or_sub *S, double bC, double q)
 {
     int N = S->N;
     double mx = 0.0;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j)
-            for (int k = 0; k < N; ++k) {
-                size_t c = ((size_t)i * N + j) * N + k;
-                if (!S->mask[c]) continue;
-                double r = fabs(S->f[c] - sub_op(S, i, j, k, bC, q, NULL));
-                if (!(r <= mx)) mx = r;
-            }
+#pragma omp parallel
+    {
+        double lm = 0.0;
+#pragma omp for
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                for (int k = 0; k < N; ++k) {
+                    size_t c = ((size_t)i * N + j) * N + k;
+                    if (!S->mask[c]) continue;
+                    double r = fabs(S->f[c] - sub_op(S, i, j, k, bC, q, NULL));
+                    if (!(r <= lm)) lm = r;
+                }
+#pragma omp critical
+        mx = nanmax(mx, lm);
+    }
     return mx;
 }
 
@@ -691,6 +699,7 @@ static void amr_vcycle(or_sub *Sv, int m, int nsub, const or_params *p, double b
     }
     for (int s = 0; s < p->pre_smooth; ++s) sub_sweep(S, bC, q, p->max_du);
     int N = S->N;
+#pragma omp parallel for
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j)
             for (int k = 0; k < N; ++k) {
@@ -725,6 +734,7 @@ static void amr_vcycle(or_sub *Sv, int m, int nsub, const or_params *p, double b
     amr_vcycle(Sv, m + 1, nsub, p, bC, q);
     /* correction u += P(e), e = u_c - ubar on the coarse unknowns and 0 elsewhere */
 #define EC(a, b, c) (C->mask[SIDX(C, a, b, c)] ? C->u[SIDX(C, a, b, c)] - C->ubar[SIDX(C, a, b, c)] : 0.0)
+#pragma omp parallel for
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j)
             for (int k = 0; k < N; ++k) {
@@ -763,34 +773,28 @@ static double prolong_field_at(const double *P, int N, long i, long j, long k)
     return v;
 }
 
-/* Solve the base mesh and `nref` (0..2) refined levels for np unit-mass particles.
- * u[l], mask[l]: caller arrays of (N_0 2^l)^3 elements; u[l] holds the level-l
- * solution on mask[l] cells (u[0] everywhere).  st[l]: per-level statistics.
- * Returns the worst status. */
-int or_amr_solve(const or_params *p, int nref, int64_t np, const float *pos, double **u, unsigned char **mask,
-                 or_stats *st)
+/* Block index of cell (i,j,k) (any integers, wrapped) of a level with N cells
+ * per side, in its map of (N/8)^3 block positions. */
+static size_t blk_of(int N, long i, long j, long k)
+{
+    int M = N / 8;
+    return ((size_t)(wrapi(i, N) / 8) * M + wrapi(j, N) / 8) * M + wrapi(k, N) / 8;
+}
+
+/* Refinement flags (reading of Sec. 3.1's rule that an AMR cell holds at most
+ * eight particles, for 8^3-cell blocks).  blk[l] (l = 1..nref) are caller
+ * arrays of (N_l/8)^3 bytes, N_l = N_0 2^l, set to 1 where level l has a
+ * block.  A cell of level l-1 holding more than 8 particles (nearest-grid-
+ * point count) refines the aligned 4^3 group of level-(l-1) cells around it;
+ * on level 1 only particles inside level-1 blocks count.  Proper nesting: every
+ * level-1 block with a level-1 cell within two cells of a level-2 block is
+ * refined too, so that the ghost cells of level 2 and the parents they are
+ * prolonged from lie on level 1. */
+void or_amr_flags(const or_params *p, int nref, int64_t np, const float *pos, unsigned char **blk)
 {
     int N0 = p->mesh;
-    double fb, beta, C;
-    or_background(p, &fb, &beta, &C);
-    double bC = beta * C, q = 1.0 / (p->n + 1);
-    double srcs = beta * p->omega_m / (p->a * p->a * p->a);
-    /* base level */
-    double *m0 = malloc(cube(N0) * sizeof(double)), *d0 = malloc(cube(N0) * sizeof(double));
-    or_cic_assign(N0, p->box, np, pos, NULL, m0);
-    or_delta(N0, m0, d0);
-    memset(u[0], 0, cube(N0) * sizeof(double));
-    int worst = or_solve(p, d0, u[0], NULL, &st[0]);
-    memset(mask[0], 1, cube(N0));
-    free(m0);
-    free(d0);
-    if (nref <= 0) return worst;
-    /* flags and blocks: blk[l][b] over (N_l/8)^3 blocks */
-    unsigned char *blk[OR_AMR_MAXL] = {0};
-    for (int l = 1; l <= nref; ++l) {
-        int nb = (N0 << l) / 8;
-        blk[l] = calloc(cube(nb), 1);
-    }
+    for (int l = 1; l <= nref; ++l) memset(blk[l], 0, cube((N0 << l) / 8));
+    if (nref <= 0) return;
     {   /* level 1 from base counts */
         int *cnt = calloc(cube(N0), sizeof(int));
         double h = p->box / N0;
@@ -807,13 +811,13 @@ int or_amr_solve(const or_params *p, int nref, int64_t np, const float *pos, dou
         free(cnt);
     }
     if (nref >= 2) {  /* level 2 from level-1 counts inside level-1 blocks */
-        int N1 = 2 * N0, nb1 = N1 / 8, nb2 = N1 / 4;
+        int N1 = 2 * N0, nb2 = N1 / 4;
         int *cnt = calloc(cube(N1), sizeof(int));
         double h = p->box / N1;
         for (int64_t i = 0; i < np; ++i) {
             long c[3];
             for (int d = 0; d < 3; ++d) c[d] = wrapi((long)floor((double)pos[3 * i + d] / h), N1);
-            if (blk[1][((size_t)(c[0] / 8) * nb1 + c[1] / 8) * nb1 + c[2] / 8]) cnt[((size_t)c[0] * N1 + c[1]) * N1 + c[2]]++;
+            if (blk[1][blk_of(N1, c[0], c[1], c[2])]) cnt[((size_t)c[0] * N1 + c[1]) * N1 + c[2]]++;
         }
         for (int i = 0; i < N1; ++i)
             for (int j = 0; j < N1; ++j)
@@ -827,16 +831,104 @@ int or_amr_solve(const or_params *p, int nref, int64_t np, const float *pos, dou
                     if (!blk[2][((size_t)bi * nb2 + bj) * nb2 + bk]) continue;
                     for (long ci = 4L * bi - 2; ci < 4L * bi + 6; ++ci)
                         for (long cj = 4L * bj - 2; cj < 4L * bj + 6; ++cj)
-                            for (long ck = 4L * bk - 2; ck < 4L * bk + 6; ++ck)
-                                blk[1][((size_t)(wrapi(ci, N1) / 8) * nb1 + wrapi(cj, N1) / 8) * nb1 + wrapi(ck, N1) / 8] = 1;
+                            for (long ck = 4L * bk - 2; ck < 4L * bk + 6; ++ck) blk[1][blk_of(N1, ci, cj, ck)] = 1;
                 }
     }
-    for (int l = 1; l <= nref; ++l) {
-        int N = N0 << l, nb = N / 8;
+}
+
+/* Does cell (i,j,k) of level l belong to the composite (leaf) mesh: it lies in
+ * a level-l block (every cell of level 0) and no level-(l+1) block covers it. */
+static int amr_leaf(int N0, int nref, unsigned char **blk, int l, long i, long j, long k)
+{
+    int N = N0 << l;
+    if (l >= 1 && !blk[l][blk_of(N, i, j, k)]) return 0;
+    /* the children of (i,j,k) are level-(l+1) cells 2i.., in block 2i/8 = i/4 */
+    if (l < nref && blk[l + 1][blk_of(2 * N, 2 * wrapi(i, N), 2 * wrapi(j, N), 2 * wrapi(k, N))]) return 0;
+    return 1;
+}
+
+/* Cloud-in-cell masses on the composite mesh (Sec. 3.1): a particle is a cube
+ * whose side is that of the finest cell containing it, and every leaf cell
+ * that the cube overlaps -- of whatever level -- receives the particle's mass
+ * times the overlapping fraction of the cube's volume; then each coarser
+ * cell covered by a finer level gets the sum of its eight daughters' masses.
+ * m[l]: caller arrays of N_l^3 doubles (cells outside level l's blocks end at
+ * 0).  mass == NULL means unit masses.  With nref = 0 this is or_cic_assign. */
+void or_amr_cic(const or_params *p, int nref, unsigned char **blk, int64_t np, const float *pos,
+                const double *mass, double **m)
+{
+    int N0 = p->mesh;
+    for (int l = 0; l <= nref; ++l) memset(m[l], 0, cube(N0 << l) * sizeof(double));
+    for (int64_t q = 0; q < np; ++q) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = (double)pos[3 * q + d];
+        int lp = 0; /* finest level whose blocks contain the particle */
+        for (int l = nref; l >= 1 && !lp; --l) {
+            double hl = p->box / (N0 << l);
+            if (blk[l][blk_of(N0 << l, (long)floor(x[0] / hl), (long)floor(x[1] / hl), (long)floor(x[2] / hl))]) lp = l;
+        }
+        double s = p->box / (N0 << lp), mp = mass ? mass[q] : 1.0;
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) { lo[d] = x[d] - 0.5 * s; hi[d] = x[d] + 0.5 * s; }
+        for (int l = 0; l <= nref; ++l) {
+            int N = N0 << l;
+            double h = p->box / N;
+            long c0[3], c1[3];
+            for (int d = 0; d < 3; ++d) { c0[d] = (long)floor(lo[d] / h); c1[d] = (long)floor(hi[d] / h); }
+            for (long i = c0[0]; i <= c1[0]; ++i)
+                for (long j = c0[1]; j <= c1[1]; ++j)
+                    for (long k = c0[2]; k <= c1[2]; ++k) {
+                        long c[3] = {i, j, k};
+                        double v = 1.0;
+                        for (int d = 0; d < 3; ++d) {
+                            double a = fmax(lo[d], c[d] * h), b = fmin(hi[d], (c[d] + 1) * h);
+                            v *= b > a ? (b - a) / s : 0.0;
+                        }
+                        if (v <= 0.0 || !amr_leaf(N0, nref, blk, l, i, j, k)) continue;
+                        m[l][((size_t)wrapi(i, N) * N + wrapi(j, N)) * N + wrapi(k, N)] += mp * v;
+                    }
+        }
+    }
+    /* coarser cells covered by a finer level: the sum of their daughters */
+    for (int l = nref - 1; l >= 0; --l) {
+        int N = N0 << l, Nf = 2 * N;
         for (int i = 0; i < N; ++i)
             for (int j = 0; j < N; ++j)
-                for (int k = 0; k < N; ++k)
-                    mask[l][((size_t)i * N + j) * N + k] = blk[l][((size_t)(i / 8) * nb + j / 8) * nb + k / 8];
+                for (int k = 0; k < N; ++k) {
+                    if (!blk[l + 1][blk_of(Nf, 2 * i, 2 * j, 2 * k)]) continue;
+                    double sum = 0.0;
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b)
+                            for (int c = 0; c < 2; ++c)
+                                sum += m[l + 1][((size_t)(2 * i + a) * Nf + (2 * j + b)) * Nf + (2 * k + c)];
+                    m[l][((size_t)i * N + j) * N + k] = sum;
+                }
+    }
+}
+
+/* Solve the base mesh and `nref` (0..2) refined levels (Sec. 3.3, steps 1-12)
+ * for given density contrasts.  blk[l]: the levels' block maps (as from
+ * or_amr_flags; proper nesting is the caller's business); delta[l]: N_l^3
+ * arrays, used on level l's block cells (delta[0] everywhere).  u[l], mask[l]:
+ * caller arrays of N_l^3 elements; u[l] receives the level-l solution on its
+ * block cells (u[0] everywhere, solved from u = 0), mask[l] the block cells.
+ * st[l]: per-level statistics.  Returns the worst status. */
+int or_amr_solve_fields(const or_params *p, int nref, unsigned char **blk, double **delta, double **u,
+                        unsigned char **mask, or_stats *st)
+{
+    int N0 = p->mesh;
+    double fb, beta, C;
+    or_background(p, &fb, &beta, &C);
+    double bC = beta * C, q = 1.0 / (p->n + 1);
+    double srcs = beta * p->omega_m / (p->a * p->a * p->a);
+    memset(u[0], 0, cube(N0) * sizeof(double));
+    int worst = or_solve(p, delta[0], u[0], NULL, &st[0]);
+    memset(mask[0], 1, cube(N0));
+    for (int l = 1; l <= nref; ++l) {
+        int N = N0 << l;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                for (int k = 0; k < N; ++k) mask[l][((size_t)i * N + j) * N + k] = blk[l][blk_of(N, i, j, k)];
     }
     /* level solves, coarse to fine */
     for (int l = 1; l <= nref; ++l) {
@@ -886,17 +978,13 @@ int or_amr_solve(const or_params *p, int nref, int64_t np, const float *pos, dou
         }
         /* unknowns, source and initial guess on level l */
         or_sub *S0 = &Sv[0];
-        double *ml = malloc(cube(N) * sizeof(double));
-        or_cic_assign(N, p->box, np, pos, NULL, ml);
-        double mbar = (double)np / (double)cube(N);
         double D = 0.0;
         for (size_t c = 0; c < cube(N); ++c) {
             if (!S0->mask[c]) continue;
-            S0->f[c] = srcs * (ml[c] / mbar - 1.0);
+            S0->f[c] = srcs * delta[l][c];
             S0->u[c] = S0->fr[c];
             if (fabs(S0->f[c]) > D) D = fabs(S0->f[c]);
         }
-        free(ml);
         if (D == 0.0) D = bC;
         or_stats *s = &st[l];
         memset(s, 0, sizeof *s);
@@ -922,6 +1010,32 @@ int or_amr_solve(const or_params *p, int nref, int64_t np, const float *pos, dou
             free(Sv[m].mask); free(Sv[m].u); free(Sv[m].f); free(Sv[m].fr); free(Sv[m].ubar); free(Sv[m].r);
         }
     }
+    return worst;
+}
+
+/* The adaptive solve for np unit-mass particles: refinement flags
+ * (or_amr_flags), composite cloud-in-cell masses (or_amr_cic), delta_l =
+ * m_l / mbar_l - 1 with mbar_l the total mass over N_l^3 (the mean cell mass
+ * at level l's resolution, so a parent's delta is the mean of its
+ * daughters'), then or_amr_solve_fields. */
+int or_amr_solve(const or_params *p, int nref, int64_t np, const float *pos, double **u, unsigned char **mask,
+                 or_stats *st)
+{
+    int N0 = p->mesh;
+    unsigned char *blk[OR_AMR_MAXL] = {0};
+    double *m[OR_AMR_MAXL] = {0};
+    for (int l = 1; l <= nref; ++l) blk[l] = calloc(cube((N0 << l) / 8), 1);
+    for (int l = 0; l <= nref; ++l) m[l] = malloc(cube(N0 << l) * sizeof(double));
+    or_amr_flags(p, nref, np, pos, blk);
+    or_amr_cic(p, nref, blk, np, pos, NULL, m);
+    double total = 0.0;
+    for (size_t c = 0; c < cube(N0); ++c) total += m[0][c];
+    for (int l = 0; l <= nref; ++l) {
+        double mbar = total / (double)cube(N0 << l);
+        for (size_t c = 0; c < cube(N0 << l); ++c) m[l][c] = m[l][c] / mbar - 1.0;
+    }
+    int worst = or_amr_solve_fields(p, nref, blk, m, u, mask, st);
+    for (int l = 0; l <= nref; ++l) free(m[l]);
     for (int l = 1; l <= nref; ++l) free(blk[l]);
     return worst;
 }

@@ -87,6 +87,12 @@ def lib(serial: bool | None = None):
         L.or_amr_solve.argtypes = [C.POINTER(Params), C.c_int, C.c_int64, fp, C.POINTER(dp),
                                    C.POINTER(C.c_void_p), C.POINTER(Stats)]
         L.or_amr_solve.restype = C.c_int
+        L.or_amr_flags.argtypes = [C.POINTER(Params), C.c_int, C.c_int64, fp, C.POINTER(C.c_void_p)]
+        L.or_amr_cic.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(C.c_void_p), C.c_int64, fp, dp,
+                                 C.POINTER(dp)]
+        L.or_amr_solve_fields.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(C.c_void_p), C.POINTER(dp),
+                                          C.POINTER(dp), C.POINTER(C.c_void_p), C.POINTER(Stats)]
+        L.or_amr_solve_fields.restype = C.c_int
         _libs[path] = L
     return _libs[path]
 
@@ -296,4 +302,48 @@ def amr_solve(p, nref, pos):
     mp = (C.c_void_p * (nref + 1))(*[a.ctypes.data_as(C.c_void_p) for a in ms])
     st = (Stats * (nref + 1))()
     s = lib().or_amr_solve(C.byref(p), nref, pos.shape[0], _f(pos), up, mp, st)
+    return s, us, ms, list(st)
+
+
+def _blk_ptrs(blk):
+    """blk: list indexed by level (entry 0 unused) of uint8 block maps."""
+    arrs = [None] + [np.ascontiguousarray(b, np.uint8) for b in blk[1:]]
+    ptrs = (C.c_void_p * len(arrs))(None, *[a.ctypes.data_as(C.c_void_p) for a in arrs[1:]])
+    return arrs, ptrs
+
+
+def amr_flags(p, nref, pos):
+    """Block maps [None, blk1, blk2] ((N_l/8)^3 uint8) from nearest-grid-point counts and nesting."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    N0 = p.mesh
+    blk = [None] + [np.zeros(((N0 << l) // 8,) * 3, np.uint8) for l in range(1, nref + 1)]
+    _, ptrs = _blk_ptrs(blk)
+    lib().or_amr_flags(C.byref(p), nref, pos.shape[0], _f(pos), ptrs)
+    return blk
+
+
+def amr_cic(p, nref, blk, pos, mass=None):
+    """Composite cloud-in-cell masses [m_0 .. m_nref] (Sec. 3.1) on the levels of ``blk``."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    N0 = p.mesh
+    ms = [np.zeros((N0 << l,) * 3, np.float64) for l in range(nref + 1)]
+    arrs, ptrs = _blk_ptrs(blk)
+    mp = (C.POINTER(C.c_double) * (nref + 1))(*[_d(a) for a in ms])
+    mass_p = None if mass is None else _d(np.ascontiguousarray(mass, np.float64))
+    lib().or_amr_cic(C.byref(p), nref, ptrs, pos.shape[0], _f(pos), mass_p, mp)
+    return ms
+
+
+def amr_solve_fields(p, nref, blk, deltas):
+    """Adaptive solve for given per-level density contrasts; returns (status, [u_l], [mask_l], [stats_l])."""
+    N0 = p.mesh
+    ds = [np.ascontiguousarray(d, np.float64) for d in deltas]
+    us = [np.zeros((N0 << l,) * 3, np.float64) for l in range(nref + 1)]
+    ms = [np.zeros((N0 << l,) * 3, np.uint8) for l in range(nref + 1)]
+    arrs, ptrs = _blk_ptrs(blk)
+    dp_ = (C.POINTER(C.c_double) * (nref + 1))(*[_d(a) for a in ds])
+    up = (C.POINTER(C.c_double) * (nref + 1))(*[_d(a) for a in us])
+    mp = (C.c_void_p * (nref + 1))(*[a.ctypes.data_as(C.c_void_p) for a in ms])
+    st = (Stats * (nref + 1))()
+    s = lib().or_amr_solve_fields(C.byref(p), nref, ptrs, dp_, up, mp, st)
     return s, us, ms, list(st)

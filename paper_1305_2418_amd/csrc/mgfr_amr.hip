@@ -7,6 +7,11 @@
 // two level-1 cells of them (proper nesting: the ghost cells of level 2 and
 // the parents they are prolonged from lie on level 1).
 //
+// Masses (Sec. 3.1): one pass over the particles assigns each one's cube --
+// side of the finest cell containing it -- to the leaf cells of the composite
+// mesh it overlaps; coarser cells covered by a finer level then receive the
+// sums of their daughters, and the base mesh is solved from the result.
+//
 // A level is solved after its parent.  Its initial guess and the ghost layer
 // around the union of its blocks are the linear prolongation (Sec. 3.3) of the
 // parent solution; ghosts stay fixed.  The level's FAS V-cycles use the union
@@ -189,30 +194,174 @@ __global__ void k_nest(const unsigned char *__restrict__ blk2, int N1, unsigned 
     }
 }
 
-// cloud-in-cell masses of all particles onto the level's block cells (f[0] interior)
-__global__ void k_amr_cic(const float *__restrict__ pos, int64_t np, LevelDev L, double h)
+// Composite-mesh view for the mass assignment: block maps of the refined
+// levels and the mass accumulators of every level (base mesh; interior cells
+// of sublevel 0 of each level's blocks).
+struct CicMaps {
+    int nref, lg0;
+    double box;
+    const int *map[kMaxRef + 1];  // map[l], l >= 1: block id or -1 per block position (side N_l / 8)
+    double *m0;                   // [N0^3]
+    double *f0[kMaxRef + 1];      // f0[l], l >= 1: sublevel-0 padded arrays of level l's blocks
+};
+
+// block id of cell (i,j,k) of level l, any integer indices (wrapped periodically)
+__device__ __forceinline__ int cic_blk(const CicMaps &Q, int l, long long i, long long j, long long k)
+{
+    const int lg = Q.lg0 + l, M = 1 << (lg - 3);
+    const long long m = (1LL << lg) - 1;
+    const int a = (int)(i & m), b = (int)(j & m), c = (int)(k & m);
+    return Q.map[l][((size_t)(a >> 3) * M + (b >> 3)) * M + (c >> 3)];
+}
+
+// cell (i,j,k) (wrapped) of level l is a leaf of the composite mesh: inside a
+// level-l block (every base cell) and not covered by a level-(l+1) block
+__device__ __forceinline__ bool cic_leaf(const CicMaps &Q, int l, long long i, long long j, long long k)
+{
+    if (l >= 1 && cic_blk(Q, l, i, j, k) < 0) return false;
+    if (l < Q.nref && cic_blk(Q, l + 1, 2 * i, 2 * j, 2 * k) >= 0) return false;
+    return true;
+}
+
+// add v to the mass of leaf cell (i,j,k) of level l (cic_leaf must hold)
+__device__ __forceinline__ void cic_add(const CicMaps &Q, int l, long long ii, long long jj, long long kk, double v)
+{
+    const long long m = (1LL << (Q.lg0 + l)) - 1;
+    const int i = (int)(ii & m), j = (int)(jj & m), k = (int)(kk & m);
+    if (l == 0) {
+        unsafeAtomicAdd(&Q.m0[cidx(i, j, k, Q.lg0)], v);
+    } else {
+        const int b = cic_blk(Q, l, i, j, k);
+        unsafeAtomicAdd(&Q.f0[l][(size_t)b * sub_vol(0) + pidx(0, i & 7, j & 7, k & 7)], v);
+    }
+}
+
+// Cloud-in-cell masses on the composite mesh (Sec. 3.1): each particle is a
+// cube whose side is that of the finest cell containing it; every leaf cell
+// it overlaps, of any level, gets the overlapping fraction of the unit mass.
+// When the cube's eight cells at that level are all leaves (the common case)
+// these are the usual weights (1 - t, t) per axis; otherwise the overlaps are
+// computed cell by cell over every level.
+__global__ void k_amr_cic_composite(const float *__restrict__ pos, int64_t np, CicMaps Q, int *__restrict__ flag)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    const int N = 1 << L.lg, M = 1 << L.mlg;
-    int i0[3];
-    double t[3];
-    for (int d = 0; d < 3; ++d) {
-        const double xi = (double)pos[3 * p + d] / h - 0.5;
-        if (!(fabs(xi) < 4.0e18)) return;
-        const double fl = floor(xi);
-        t[d] = xi - fl;
-        i0[d] = (int)((long long)fl & (N - 1));
+    const double x[3] = {(double)pos[3 * p + 0], (double)pos[3 * p + 1], (double)pos[3 * p + 2]};
+    // non-finite or absurdly distant positions (cell indices must fit 64 bits)
+    if (!(fabs(x[0]) < 1e15 && fabs(x[1]) < 1e15 && fabs(x[2]) < 1e15)) {
+        flag[0] = 1;
+        return;
     }
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int c = 0; c < 2; ++c) {
-                const int i = wrapn(i0[0] + a, N), j = wrapn(i0[1] + b, N), k = wrapn(i0[2] + c, N);
-                const int blk = L.map[((size_t)(i >> 3) * M + (j >> 3)) * M + (k >> 3)];
-                if (blk < 0) continue;
-                const double w = (a ? t[0] : 1.0 - t[0]) * (b ? t[1] : 1.0 - t[1]) * (c ? t[2] : 1.0 - t[2]);
-                unsafeAtomicAdd(&L.f[0][(size_t)blk * sub_vol(0) + pidx(0, i & 7, j & 7, k & 7)], w);
-            }
+    int lp = 0;
+    for (int l = Q.nref; l >= 1; --l) {
+        const double h = Q.box / (double)(1 << (Q.lg0 + l));
+        if (cic_blk(Q, l, (long long)floor(x[0] / h), (long long)floor(x[1] / h), (long long)floor(x[2] / h)) >= 0) {
+            lp = l;
+            break;
+        }
+    }
+    const int lgp = Q.lg0 + lp, mask = (1 << lgp) - 1;
+    const double s = Q.box / (double)(1 << lgp);
+    int i0, j0, k0;
+    double tx, ty, tz;
+    if (!(cic_axis((float)x[0], s, mask, i0, tx) && cic_axis((float)x[1], s, mask, j0, ty) &&
+          cic_axis((float)x[2], s, mask, k0, tz))) {
+        flag[0] = 1;
+        return;
+    }
+    bool all_leaf = true;
+    for (int a = 0; a < 2 && all_leaf; ++a)
+        for (int b = 0; b < 2 && all_leaf; ++b)
+            for (int c = 0; c < 2 && all_leaf; ++c) all_leaf = cic_leaf(Q, lp, i0 + a, j0 + b, k0 + c);
+    if (all_leaf) {
+        const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) cic_add(Q, lp, i0 + a, j0 + b, k0 + c, wx[a] * wy[b] * wz[c]);
+        return;
+    }
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = x[d] - 0.5 * s;
+        hi[d] = x[d] + 0.5 * s;
+    }
+    for (int l = 0; l <= Q.nref; ++l) {
+        const double h = Q.box / (double)(1 << (Q.lg0 + l));
+        long long c0[3], c1[3];
+        for (int d = 0; d < 3; ++d) {
+            c0[d] = (long long)floor(lo[d] / h);
+            c1[d] = (long long)floor(hi[d] / h);
+        }
+        for (long long i = c0[0]; i <= c1[0]; ++i)
+            for (long long j = c0[1]; j <= c1[1]; ++j)
+                for (long long k = c0[2]; k <= c1[2]; ++k) {
+                    const long long c[3] = {i, j, k};
+                    double v = 1.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double a = fmax(lo[d], (double)c[d] * h), b = fmin(hi[d], (double)(c[d] + 1) * h);
+                        v *= b > a ? (b - a) / s : 0.0;
+                    }
+                    if (v > 0.0 && cic_leaf(Q, l, i, j, k)) cic_add(Q, l, i, j, k, v);
+                }
+    }
+}
+
+// Masses of the level-l cells covered by level-(l+1) blocks: the sum of their
+// eight daughters (Sec. 3.1).  One thread per coarse cell: each level-(l+1)
+// block covers an aligned 4^3 group of level-l cells.
+__global__ void k_amr_mass_up(CicMaps Q, int l, int nbf, const int *__restrict__ orgf)
+{
+    const size_t n = (size_t)nbf * 64;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const int b = (int)(id >> 6), c = (int)(id & 63);
+        const int a0 = c >> 4, b0 = (c >> 2) & 3, c0 = c & 3;
+        const double *F = Q.f0[l + 1] + (size_t)b * sub_vol(0);
+        double sum = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int bb = 0; bb < 2; ++bb)
+                for (int cc = 0; cc < 2; ++cc) sum += F[pidx(0, 2 * a0 + a, 2 * b0 + bb, 2 * c0 + cc)];
+        const int i = (orgf[3 * b] >> 1) + a0, j = (orgf[3 * b + 1] >> 1) + b0, k = (orgf[3 * b + 2] >> 1) + c0;
+        if (l == 0) {
+            Q.m0[cidx(i, j, k, Q.lg0)] = sum;
+        } else {
+            const int pb = cic_blk(Q, l, i, j, k);  // exists: level-(l+1) blocks nest in level l
+            if (pb >= 0) Q.f0[l][(size_t)pb * sub_vol(0) + pidx(0, i & 7, j & 7, k & 7)] = sum;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_amr_sum_partial(const double *__restrict__ x, size_t n,
+                                                          double *__restrict__ partial)
+{
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (size_t)gridDim.x * 256) s += x[t];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ __launch_bounds__(1024) void k_amr_sum_final(const double *__restrict__ partial, int n,
+                                                        double *__restrict__ out)
+{
+    __shared__ double sh[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += partial[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) s += sh[w];
+        out[0] = s;
+    }
+}
+
+// delta = m / mbar - 1 in place on the base mesh
+__global__ void k_amr_delta0(double *__restrict__ m, size_t n, double mbar)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        m[t] = m[t] / mbar - 1.0;
 }
 
 // f = s (m / mbar - 1) on interior cells, per-block max |f| partials
@@ -704,6 +853,8 @@ struct mgfr_amr {
     int *cntb = nullptr;      // [max_blocks * 512] counts
     unsigned char *flag[kMaxRef + 1] = {nullptr};  // refinement flags per level-l block position
     double *partial = nullptr, *dscal = nullptr, *hscal = nullptr;
+    int *dflag = nullptr;       // non-finite particle position seen by the assignment
+    double total_mass = 0.0;    // of the last assignment (sum over the base mesh)
     // per refined level
     int nb[kMaxRef + 1] = {0, 0, 0};
     int *map[kMaxRef + 1] = {nullptr}, *org[kMaxRef + 1] = {nullptr}, *nbr[kMaxRef + 1] = {nullptr};
@@ -761,6 +912,7 @@ void amr_free(mgfr_amr *A)
     for (int l = 1; l <= kMaxRef; ++l) (void)hipFree(A->flag[l]);
     (void)hipFree(A->partial);
     (void)hipFree(A->dscal);
+    (void)hipFree(A->dflag);
     if (A->hscal) (void)hipHostFree(A->hscal);
     for (int l = 1; l <= kMaxRef; ++l) {
         (void)hipFree(A->map[l]);
@@ -888,7 +1040,7 @@ int amrx_vcycle(mgfr_amr *A, const LevelDev &L, int m, const MxConst *K)
     return MGFR_OK;
 }
 
-int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
+int solve_level(mgfr_amr *A, int l)
 {
     mgfr_stats &st = A->st[l];
     memset(&st, 0, sizeof st);
@@ -904,14 +1056,14 @@ int solve_level(mgfr_amr *A, int l, const float *pos, int64_t np)
         const double hm = h * (1 << m);
         K.ih2[m] = 1.0 / (hm * hm);
     }
-    // clear every array (ghost faces included) of this level
+    // clear every array (ghost faces included) of this level but the masses
+    // the assignment left in f[0]
     for (int a = 0; a < 4; ++a)
         for (int m = 0; m < kSub; ++m)
-            MGFR_HIP(hipMemsetAsync(A->arr[l][a][m], 0, (size_t)L.nb * sub_vol(m) * sizeof(double), A->stream));
-    // source
-    const unsigned pg = (unsigned)((np + 255) / 256);
-    k_amr_cic<<<pg, 256, 0, A->stream>>>(pos, np, L, h);
-    const double mbar = (double)np / ((double)N * N * N);
+            if (a != 1 || m != 0)
+                MGFR_HIP(hipMemsetAsync(A->arr[l][a][m], 0, (size_t)L.nb * sub_vol(m) * sizeof(double), A->stream));
+    // source from the composite masses: delta = m / mbar_l - 1, mbar_l = total / N_l^3
+    const double mbar = A->total_mass / ((double)N * N * N);
     const double s = A->beta * A->p.omega_m / (A->p.a * A->p.a * A->p.a);
     k_amr_source<<<L.nb, 512, 0, A->stream>>>(L, s, mbar, A->partial);
     double D;
@@ -1036,6 +1188,7 @@ extern "C" int mgfr_amr_create(const mgfr_params *p, int64_t max_blocks, void *s
     M((void **)&A->cntb, (size_t)max_blocks * 512 * sizeof(int));
     M((void **)&A->partial, (size_t)std::max<int64_t>(max_blocks, 1024) * sizeof(double));
     M((void **)&A->dscal, 8 * sizeof(double));
+    M((void **)&A->dflag, sizeof(int));
     for (int l = 1; l <= A->nref; ++l) {
         const size_t Mside = (size_t)(A->N0 << l) / 8;
         M((void **)&A->map[l], Mside * Mside * Mside * sizeof(int));
@@ -1073,15 +1226,7 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
     int rc;
     const int N0 = A->N0;
     const size_t n0 = (size_t)N0 * N0 * N0;
-    // base level: the uniform solver
     if ((rc = mgfr_set_stream(A->base, A->stream))) return rc;
-    if (A->base->binning && np > A->base->bin_cap && np <= (int64_t)0x7fffffff &&
-        (rc = bin_reserve(A->base, np)))
-        return rc;
-    if ((rc = mgfr_assign_density(A->base, pos, nullptr, np, A->delta0))) return rc;
-    MGFR_HIP(hipMemsetAsync(A->u0, 0, n0 * sizeof(double), A->stream));
-    rc = mgfr_solve(A->base, A->delta0, A->u0, nullptr, &A->st[0]);
-    if (rc < 0) return rc;
     const unsigned pg = (unsigned)((np + 255) / 256);
     auto listof = [](const std::vector<unsigned char> &v) {
         std::vector<int64_t> L;
@@ -1094,7 +1239,7 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
         v.resize(Ml * Ml * Ml);
         return hipMemcpyAsync(v.data(), A->flag[l], v.size(), hipMemcpyDeviceToHost, A->stream);
     };
-    // level-1 blocks from base counts (flags built on the device)
+    // 1. refinement: level-1 blocks from base counts (flags built on the device)
     const int M1 = N0 / 4;
     MGFR_HIP(hipMemsetAsync(A->cnt0, 0, n0 * sizeof(int), A->stream));
     MGFR_HIP(hipMemsetAsync(A->flag[1], 0, (size_t)M1 * M1 * M1, A->stream));
@@ -1128,9 +1273,49 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
         if ((rc = upload_level(A, 1, listof(blk1)))) return rc;
         if ((rc = upload_level(A, 2, listof(blk2)))) return rc;
     }
+    // 2. composite cloud-in-cell masses (Sec. 3.1) on the base mesh and the blocks,
+    //    then the covered coarser cells as sums of their daughters
+    CicMaps Q{};
+    Q.nref = A->nref;
+    Q.lg0 = A->lg0;
+    Q.box = A->p.box;
+    Q.m0 = A->delta0;
+    MGFR_HIP(hipMemsetAsync(A->delta0, 0, n0 * sizeof(double), A->stream));
+    for (int l = 1; l <= A->nref; ++l) {
+        Q.map[l] = A->map[l];
+        Q.f0[l] = A->arr[l][1][0];
+        if (A->nb[l])
+            MGFR_HIP(hipMemsetAsync(A->arr[l][1][0], 0, (size_t)A->nb[l] * sub_vol(0) * sizeof(double), A->stream));
+    }
+    MGFR_HIP(hipMemsetAsync(A->dflag, 0, sizeof(int), A->stream));
+    k_amr_cic_composite<<<pg, 256, 0, A->stream>>>(pos, np, Q, A->dflag);
+    for (int l = A->nref - 1; l >= 0; --l)
+        if (A->nb[l + 1])
+            k_amr_mass_up<<<grid_of((size_t)A->nb[l + 1] * 64), 256, 0, A->stream>>>(Q, l, A->nb[l + 1],
+                                                                                    A->org[l + 1]);
+    const unsigned sg = (unsigned)std::min<size_t>((n0 + 255) / 256, 1024);
+    k_amr_sum_partial<<<sg, 256, 0, A->stream>>>(A->delta0, n0, A->partial);
+    k_amr_sum_final<<<1, 1024, 0, A->stream>>>(A->partial, (int)sg, A->dscal);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipMemcpyAsync(A->hscal, A->dscal, sizeof(double), hipMemcpyDeviceToHost, A->stream));
+    MGFR_HIP(hipMemcpyAsync(A->hscal + 1, A->dflag, sizeof(int), hipMemcpyDeviceToHost, A->stream));
+    MGFR_HIP(hipStreamSynchronize(A->stream));
+    int hflag = 0;
+    memcpy(&hflag, A->hscal + 1, sizeof(int));
+    if (hflag) return set_error(MGFR_ERR_NONFINITE, "a particle position is not finite");
+    A->total_mass = A->hscal[0];
+    if (!(A->total_mass > 0) || !std::isfinite(A->total_mass))
+        return set_error(MGFR_ERR_NONFINITE, "total assigned mass is not positive and finite");
+    // 3. base level: delta = m / mbar - 1, solved by the uniform solver
+    k_amr_delta0<<<grid_of(n0, 8192), 256, 0, A->stream>>>(A->delta0, n0, A->total_mass / (double)n0);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipMemsetAsync(A->u0, 0, n0 * sizeof(double), A->stream));
+    rc = mgfr_solve(A->base, A->delta0, A->u0, nullptr, &A->st[0]);
+    if (rc < 0) return rc;
+    // 4. refined levels, coarse to fine
     int worst = A->st[0].status;
     for (int l = 1; l <= A->nref; ++l) {
-        if ((rc = solve_level(A, l, pos, np))) return rc;
+        if ((rc = solve_level(A, l))) return rc;
         const int s = A->st[l].status;
         if (s != MGFR_OK && (worst == MGFR_OK || s < 0)) worst = s;
     }

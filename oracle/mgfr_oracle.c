@@ -1039,3 +1039,94 @@ int or_amr_solve(const or_params *p, int nref, int64_t np, const float *pos, dou
     for (int l = 1; l <= nref; ++l) free(blk[l]);
     return worst;
 }
+
+/* ------------------------------------------------ sampled checks of the adaptive mesh */
+
+static int key_cmp(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+static uint64_t cell_key(int l, long i, long j, long k)
+{
+    return ((uint64_t)l << 60) | ((uint64_t)i << 40) | ((uint64_t)j << 20) | (uint64_t)k;
+}
+
+/* Composite cloud-in-cell mass (as or_amr_cic) of `count` listed cells, from
+ * the np given particles: lev[s] is the level of cell s and ijk[3s..3s+2] its
+ * indices there (0 <= index < N_lev < 2^20).  A listed cell that a finer
+ * level covers gets the sum over its descendants, as the daughter sums of
+ * or_amr_cic give.  mass == NULL means unit masses. */
+void or_amr_cic_cells(const or_params *p, int nref, unsigned char **blk, int64_t np, const float *pos,
+                      const double *mass, int64_t count, const int *lev, const int *ijk, double *out)
+{
+    int N0 = p->mesh;
+    uint64_t *keys = malloc((size_t)count * sizeof(uint64_t));
+    for (int64_t s = 0; s < count; ++s) {
+        keys[s] = cell_key(lev[s], ijk[3 * s], ijk[3 * s + 1], ijk[3 * s + 2]);
+        out[s] = 0.0;
+    }
+    uint64_t *sorted = malloc((size_t)count * sizeof(uint64_t));
+    memcpy(sorted, keys, (size_t)count * sizeof(uint64_t));
+    qsort(sorted, (size_t)count, sizeof(uint64_t), key_cmp);
+    for (int64_t q = 0; q < np; ++q) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = (double)pos[3 * q + d];
+        int lp = 0;
+        for (int l = nref; l >= 1 && !lp; --l) {
+            double hl = p->box / (N0 << l);
+            if (blk[l][blk_of(N0 << l, (long)floor(x[0] / hl), (long)floor(x[1] / hl), (long)floor(x[2] / hl))]) lp = l;
+        }
+        double s = p->box / (N0 << lp), mp = mass ? mass[q] : 1.0;
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) { lo[d] = x[d] - 0.5 * s; hi[d] = x[d] + 0.5 * s; }
+        for (int m = 0; m <= nref; ++m) {
+            int N = N0 << m;
+            double h = p->box / N;
+            long c0[3], c1[3];
+            for (int d = 0; d < 3; ++d) { c0[d] = (long)floor(lo[d] / h); c1[d] = (long)floor(hi[d] / h); }
+            for (long i = c0[0]; i <= c1[0]; ++i)
+                for (long j = c0[1]; j <= c1[1]; ++j)
+                    for (long k = c0[2]; k <= c1[2]; ++k) {
+                        long c[3] = {i, j, k};
+                        double v = 1.0;
+                        for (int d = 0; d < 3; ++d) {
+                            double a = fmax(lo[d], c[d] * h), b = fmin(hi[d], (c[d] + 1) * h);
+                            v *= b > a ? (b - a) / s : 0.0;
+                        }
+                        if (v <= 0.0 || !amr_leaf(N0, nref, blk, m, i, j, k)) continue;
+                        long wi = wrapi(i, N), wj = wrapi(j, N), wk = wrapi(k, N);
+                        for (int l = 0; l <= m; ++l) { /* the leaf and each of its ancestors */
+                            uint64_t key = cell_key(l, wi >> (m - l), wj >> (m - l), wk >> (m - l));
+                            uint64_t *hit = bsearch(&key, sorted, (size_t)count, sizeof(uint64_t), key_cmp);
+                            if (!hit) continue;
+                            for (int64_t t = 0; t < count; ++t)
+                                if (keys[t] == key) out[t] += mp * v;
+                        }
+                    }
+        }
+    }
+    free(keys);
+    free(sorted);
+}
+
+/* L_c at `count` cells from explicit stencils: uc[s] and its six neighbours
+ * nb[6s..6s+5] in the order +x, -x, +y, -y, +z, -z, on a level of cell side h
+ * (the operator of or_apply_L, through op_cell on a 3^3 patch). */
+void or_op_stencil(double h, double bC, int n, int64_t count, const double *uc, const double *nb, double *L)
+{
+    double ih2 = 1.0 / (h * h), q = 1.0 / (n + 1);
+    for (int64_t s = 0; s < count; ++s) {
+        double u[27];
+        for (int c = 0; c < 27; ++c) u[c] = 0.0;
+        u[13] = uc[s];
+        u[22] = nb[6 * s + 0]; /* (2,1,1) */
+        u[4] = nb[6 * s + 1];  /* (0,1,1) */
+        u[16] = nb[6 * s + 2]; /* (1,2,1) */
+        u[10] = nb[6 * s + 3]; /* (1,0,1) */
+        u[14] = nb[6 * s + 4]; /* (1,1,2) */
+        u[12] = nb[6 * s + 5]; /* (1,1,0) */
+        L[s] = op_cell(u, 3, 1, 1, 1, ih2, bC, q, NULL);
+    }
+}

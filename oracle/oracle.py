@@ -93,6 +93,9 @@ def lib(serial: bool | None = None):
         L.or_amr_solve_fields.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(C.c_void_p), C.POINTER(dp),
                                           C.POINTER(dp), C.POINTER(C.c_void_p), C.POINTER(Stats)]
         L.or_amr_solve_fields.restype = C.c_int
+        L.or_amr_cic_cells.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(C.c_void_p), C.c_int64, fp, dp,
+                                       C.c_int64, C.c_void_p, C.c_void_p, dp]
+        L.or_op_stencil.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp, dp, dp]
         _libs[path] = L
     return _libs[path]
 
@@ -347,3 +350,25 @@ def amr_solve_fields(p, nref, blk, deltas):
     st = (Stats * (nref + 1))()
     s = lib().or_amr_solve_fields(C.byref(p), nref, ptrs, dp_, up, mp, st)
     return s, us, ms, list(st)
+
+
+def amr_cic_cells(p, nref, blk, pos, levels, ijk, mass=None):
+    """Composite CIC masses of listed cells (level, i, j, k) from the given particles."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    lev = np.ascontiguousarray(levels, np.int32)
+    ijk = np.ascontiguousarray(ijk, np.int32).reshape(-1, 3)
+    out = np.zeros(lev.size, np.float64)
+    arrs, ptrs = _blk_ptrs(blk)
+    mass_p = None if mass is None else _d(np.ascontiguousarray(mass, np.float64))
+    lib().or_amr_cic_cells(C.byref(p), nref, ptrs, pos.shape[0], _f(pos), mass_p, lev.size,
+                           lev.ctypes.data_as(C.c_void_p), ijk.ctypes.data_as(C.c_void_p), _d(out))
+    return out
+
+
+def op_stencil(h, bC, uc, nb, n=1):
+    """The operator L at cells given their value uc [count] and neighbours nb [count, 6] (+x,-x,+y,-y,+z,-z)."""
+    uc = np.ascontiguousarray(uc, np.float64)
+    nb = np.ascontiguousarray(nb, np.float64).reshape(-1, 6)
+    out = np.empty(uc.size, np.float64)
+    lib().or_op_stencil(h, bC, n, uc.size, _d(uc), _d(nb), _d(out))
+    return out

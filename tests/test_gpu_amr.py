@@ -102,3 +102,127 @@ def test_amr_rejects_bad_arguments():
     with pytest.raises(mgfr.MgfrError) as ei:
         amr.solve(pos)
     assert "max_blocks" in str(ei.value)
+
+
+def _val_fn(u0, levels, N0):
+    """value(l, i, j, k) of the library's solution on level l (0 = base), wrapped;
+    None where level l has no block."""
+    def val(l, i, j, k):
+        N = N0 << l
+        i, j, k = i % N, j % N, k % N
+        if l == 0:
+            return u0[i, j, k]
+        idx, ul = levels[l]
+        b = idx.get((i - i % 8, j - j % 8, k - k % 8))
+        return None if b is None else ul[b, i % 8, j % 8, k % 8]
+    return val
+
+
+def _prolong_parent(val, l, i, j, k):
+    """Linear reconstruction (Sec. 3.3) of the level-(l-1) solution at level-l cell (i,j,k)."""
+    I, J, K = i // 2, j // 2, k // 2
+    v = val(l - 1, I, J, K)
+    for d, s in ((0, 1 if i % 2 else -1), (1, 1 if j % 2 else -1), (2, 1 if k % 2 else -1)):
+        e = [0, 0, 0]
+        e[d] = 1
+        v += s * (val(l - 1, I + e[0], J + e[1], K + e[2]) - val(l - 1, I - e[0], J - e[1], K - e[2])) / 8.0
+    return v
+
+
+def test_config4_full_size_sampled_residual():
+    """The adaptive configuration at its own size: 256^3 base plus two levels on
+    256^3 particles with 50 NFW halos (seed 4), mixed precision with the
+    benchmark's schedule.  The library's block sets equal the oracle's
+    refinement flags exactly; at sampled cells of every level (random cells,
+    cells next to ghost faces and, on the base and level 1, cells covered by
+    the next level) the residual f - L(u) evaluated by the oracle -- composite
+    masses from the particles, the operator on the stencil, ghost values
+    reconstructed from the parent level's solution -- is within the solve's
+    tolerance of the level's scale."""
+    from paper_1305_2418_amd import mgfr
+    N0, nref, fr0 = 256, 2, 1e-6
+    print("[case] adaptive 256^3 + 2 levels, 256^3 particles, sampled residuals", flush=True)
+    pos = synth.clustered_load(N0, 100.0, rms=5.0, seed=4, n_halos=50, profile="nfw")
+    params = mgfr.Params(mesh=N0, fr0_abs=fr0, refine_levels=nref, precision=mgfr.MIXED, pre_smooth=4,
+                         post_smooth=4, prolong=mgfr.PROLONG_INJECT, coarse_sweeps=4)
+    amr = mgfr.Amr(params, max_blocks=65536)
+    amr.set_relaxation32(1.2)
+    u0, st = amr.solve(pos.to(DEV))
+    assert all(s.status == 0 and s.res <= 1e-8 for s in st), [(s.status, s.res) for s in st]
+    u0 = u0.cpu().numpy()
+    pnp = pos.numpy()
+    op = O.params(mesh=N0, fr0_abs=fr0)
+    blk = O.amr_flags(op, nref, pnp)
+    levels = {}
+    for l in (1, 2):
+        org, ul = amr.level(l)
+        org = org.tolist()
+        M = (N0 << l) // 8
+        got = np.zeros((M, M, M), np.uint8)
+        for o in org:
+            got[o[0] // 8, o[1] // 8, o[2] // 8] = 1
+        assert np.array_equal(got, blk[l]), f"level {l} block sets differ"
+        levels[l] = ({tuple(o): b for b, o in enumerate(org)}, ul.cpu().numpy())
+    print(f"  blocks {[len(levels[l][0]) for l in (1, 2)]}, cycles {[s.vcycles for s in st]}", flush=True)
+    val = _val_fn(u0, levels, N0)
+    rng = np.random.default_rng(44)
+    fb, beta, C = O.background(op)
+    srcs = beta * 0.3
+    samples = []  # (level, i, j, k)
+    for l in range(nref + 1):
+        N = N0 << l
+        if l == 0:
+            cand = rng.integers(0, N, (600, 3))
+            covered = np.argwhere(blk[1])[rng.choice(int(blk[1].sum()), 100)] * 4 + rng.integers(0, 4, (100, 3))
+            cand = np.concatenate([cand, covered])
+        else:
+            org = np.array(list(levels[l][0].keys()))
+            pick = org[rng.choice(len(org), 500)] + rng.integers(0, 8, (500, 3))
+            face = org[rng.choice(len(org), 400)]
+            fc = rng.integers(0, 8, (400, 3))
+            ax = rng.integers(0, 3, 400)
+            fc[np.arange(400), ax] = np.where(rng.random(400) < 0.5, 0, 7)  # on a block face
+            cand = np.concatenate([pick, face + fc])
+            if l < nref:
+                org2 = np.argwhere(blk[l + 1]) * 8 // 2  # level-l cells under level-(l+1) blocks
+                cand = np.concatenate([cand, org2[rng.choice(len(org2), 100)] + rng.integers(0, 4, (100, 3))])
+        samples += [(l, *c) for c in cand.tolist()]
+    samples = sorted(set(samples))
+    # particles that can reach the sampled cells: those within one base cell of them
+    h0 = 100.0 / N0
+    bc = np.floor(pnp / h0).astype(np.int64) % N0
+    key = (bc[:, 0] * N0 + bc[:, 1]) * N0 + bc[:, 2]
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    near = set()
+    for (l, i, j, k) in samples:
+        I, J, K = i >> l, j >> l, k >> l
+        for a in (-1, 0, 1):
+            for b in (-1, 0, 1):
+                for c in (-1, 0, 1):
+                    near.add((((I + a) % N0) * N0 + (J + b) % N0) * N0 + (K + c) % N0)
+    near = np.array(sorted(near), np.int64)
+    lo = np.searchsorted(ks, near, "left")
+    hi = np.searchsorted(ks, near, "right")
+    sub = np.concatenate([order[a:b] for a, b in zip(lo, hi)])
+    lev = np.array([s[0] for s in samples], np.int32)
+    ijk = np.array([s[1:] for s in samples], np.int32)
+    mass = O.amr_cic_cells(op, nref, blk, pnp[sub], lev, ijk)
+    total = float(pnp.shape[0])
+    for l in range(nref + 1):
+        N = N0 << l
+        sel = [t for t, s in enumerate(samples) if s[0] == l]
+        uc, nb = [], []
+        for t in sel:
+            _, i, j, k = samples[t]
+            uc.append(val(l, i, j, k))
+            row = []
+            for (di, dj, dk) in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                v = val(l, i + di, j + dj, k + dk)
+                row.append(_prolong_parent(val, l, i + di, j + dj, k + dk) if v is None else v)
+            nb.append(row)
+        f = srcs * (mass[sel] / (total / N ** 3) - 1.0)
+        r = f - O.op_stencil(100.0 / N, beta * C, np.array(uc), np.array(nb))
+        worst = np.abs(r).max() / st[l].scale
+        print(f"  level {l}: {len(sel)} cells, max |f - L(u)| / D = {worst:.2e} (solve: {st[l].res:.2e})")
+        assert worst <= 1.01e-8

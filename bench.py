@@ -52,7 +52,6 @@ def parse():
     ap.add_argument("--compare", default="fp64,mixed,mixed_scr",
                     help="other modes timed in the same run (_scr: from the screened-limit initial guess)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-mesh", type=int, default=128)
     ap.add_argument("--workload", choices=["uniform", "amr", "sequence"], default="uniform",
                     help="amr: 256^3 base + 2 block-refined levels on 256^3 particles with 50 NFW halos; "
                          "sequence: consecutive steps of a growing displacement field, each solve warm-started "
@@ -79,25 +78,68 @@ def prolong_code(args):
     return 1 if args.prolong == "inject" else 0
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, log):
-    """The FP64 oracle, as it stands, on a bounded sample of the same recipe."""
+    """The FP64 oracle, as it stands, on a bounded sample of the same recipe:
+    its OpenMP build on the host's threads at N/2 (the headline figure) and
+    its single-thread build at N/4.  Also returns the N/2 sample and the
+    oracle's solution of it iterated to 1e-11, for the error of the library's
+    mixed solve against the oracle."""
     from oracle import oracle as O
     from paper_1305_2418_amd import synth
-    N = args.cpu_mesh
-    pos = synth.clustered_load(N, 100.0, rms=5.0, seed=args.seed, n_halos=20).numpy()
-    t0 = time.perf_counter()
-    m = O.cic_assign(N, 100.0, pos)
-    d = O.density_contrast(m)
-    p = O.params(mesh=N, a=args.a, fr0_abs=args.fr0, tol=1e-8, pre_smooth=args.smooth, post_smooth=args.smooth,
-                 prolong=prolong_code(args))
-    s, u, dfr, st = O.solve(p, d)
-    O.fifth_force(p, u, pos)
-    dt = time.perf_counter() - t0
-    log(f"cpu oracle {N}^3: {dt:.2f}s, {st.vcycles} V-cycles, status {s}")
-    return {"value": N ** 3 / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"{N}^3 mesh and {N}^3 particles of the same recipe (seed {args.seed}), one full step "
-                      f"(CIC + FP64 FAS V({args.smooth},{args.smooth}) {args.prolong} solve to 1e-8 + fifth force), "
-                      f"{st.vcycles} V-cycles, single-threaded C oracle; {os.cpu_count()} host cpus seen"}
+    threads = O.threads()
+    res = {}
+    for tag, N, serial in (("omp", args.mesh // 2, False), ("serial", args.mesh // 4, True)):
+        pos = synth.clustered_load(N, 100.0, rms=5.0, seed=args.seed, n_halos=20).numpy()
+        t0 = time.perf_counter()
+        m = O.cic_assign(N, 100.0, pos, serial=serial)
+        d = O.density_contrast(m, serial=serial)
+        p = O.params(mesh=N, a=args.a, fr0_abs=args.fr0, tol=1e-8, pre_smooth=args.smooth,
+                     post_smooth=args.smooth, prolong=prolong_code(args))
+        s, u, dfr, st = O.solve(p, d, serial=serial)
+        O.fifth_force(p, u, pos, serial=serial)
+        dt = time.perf_counter() - t0
+        log(f"cpu oracle ({tag}, {1 if serial else threads} threads) {N}^3: {dt:.2f}s, {st.vcycles} V-cycles")
+        res[tag] = dict(N=N, dt=dt, cycles=st.vcycles, delta=d, u=u, p=p)
+    o = res["omp"]
+    pt = O.params(mesh=o["N"], a=args.a, fr0_abs=args.fr0, tol=1e-11, pre_smooth=args.smooth,
+                  post_smooth=args.smooth, prolong=prolong_code(args))
+    _, _, dfr_tight, _ = O.solve(pt, o["delta"], u0=o["u"])
+    sr = res["serial"]
+    base = {"value": o["N"] ** 3 / o["dt"], "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus_seen": os.cpu_count(),
+            "sample": f"{o['N']}^3 mesh and {o['N']}^3 particles of the same recipe (seed {args.seed}), one full "
+                      f"step (CIC + FP64 FAS V({args.smooth},{args.smooth}) {args.prolong} solve to 1e-8 + fifth "
+                      f"force), OpenMP build of the C oracle on {threads} threads",
+            "oracle_vcycles": o["cycles"],
+            "single_thread": {"value": sr["N"] ** 3 / sr["dt"], "unit": "cells/s", "cores": 1,
+                              "sample": f"{sr['N']}^3 of the same recipe", "oracle_vcycles": sr["cycles"]}}
+    return base, o["delta"], dfr_tight
+
+
+def mixed_vs_oracle(args, delta, dfr_oracle, dev, log):
+    """The library's mixed solve (headline schedule and omega) of the oracle's
+    sample: max-norm relative delta f_R difference from the oracle's solution."""
+    import torch
+    from paper_1305_2418_amd import mgfr
+    N = delta.shape[0]
+    s = mgfr.Solver(mgfr.Params(mesh=N, box=100.0, a=args.a, fr0_abs=args.fr0, tol=1e-8, precision=mgfr.MIXED,
+                                pre_smooth=args.smooth, post_smooth=args.smooth, prolong=prolong_code(args)))
+    s.set_relaxation32(args.omega)
+    u, dfr, st = s.solve(torch.tensor(delta, device=dev))
+    ref = torch.tensor(dfr_oracle, device=dev)
+    err = float((dfr - ref).abs().max() / ref.abs().max())
+    log(f"mixed solve of the {N}^3 oracle sample: {st.vcycles} cycles, rel dfr difference from the oracle {err:.2e}")
+    return {"mesh": N, "rel_dfr_vs_oracle": err, "vcycles": st.vcycles, "oracle_tol": 1e-11}
 
 
 # The network's convolutions (input channels, output channels, level: 0 = S, 1 = S/2, 2 = S/4)
@@ -223,7 +265,7 @@ def run_mode(mode, args, pos, dev, log, a=None, dfr_ref=None):
         out["rel_dfr_vs_fp64"] = float((last["dfr"] - dfr_ref).abs().max() / dfr_ref.abs().max())
         log(f"[{mode} a={a}] max-norm relative delta f_R difference from the float64 solve: "
             f"{out['rel_dfr_vs_fp64']:.2e}")
-    if mode == "fp64" and a == args.a:
+    if mode == "fp64":
         out["_dfr"] = last["dfr"]
     log(f"[{mode} a={a}] step {ms:.2f} ms, solve {solve_ms:.2f} ms, V-cycles {out['vcycles']}, res {out['res']:.2e}, "
         f"sweep launch {sweep_ms:.3f} ms, nn {out['nn_ms']:.2f} ms")
@@ -268,8 +310,9 @@ def run_amr(args, log):
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"256^3 base + 2 refined levels (8^3 blocks where a cell holds > 8 particles), "
                                f"256^3 particles, Zel'dovich k^-2 rms 5 + 50 NFW halos (c 5-10), seed 4, "
-                               f"a={args.a}, |f_R0|={args.fr0}; step = base CIC + mixed solve + flagging + "
-                               f"refined-level CIC and float64 solves",
+                               f"a={args.a}, |f_R0|={args.fr0}; step = flagging + composite CIC (Sec. 3.1) + "
+                               f"base and refined-level mixed solves (float64 defect loop, float32 correction "
+                               f"cycles)",
                    "coarse_sweeps": params.coarse_sweeps, "omega": args.omega,
                    "blocks_per_level": nb, "cells": cells, "vcycles_per_level": [s.vcycles for s in st],
                    "res_per_level": [s.res for s in st]},
@@ -388,7 +431,11 @@ def main():
     other_a = {}
     for a in [float(x) for x in args.also_a.split(",") if x]:
         if a != args.a:
-            other_a[str(a)] = {m: run_mode(m, args, pos, dev, log, a=a) for m in ("mixed", "mixed_nn", "mixed_scr")}
+            other_a[str(a)] = {}
+            for m in ("fp64", "mixed", "mixed_nn", "mixed_scr"):
+                ref = other_a[str(a)].get("fp64", {}).get("_dfr")
+                other_a[str(a)][m] = run_mode(m, args, pos, dev, log, a=a, dfr_ref=ref)
+            other_a[str(a)]["fp64"].pop("_dfr", None)
     copy_gbs = measure_copy(dev, log)
     mfma = measure_mfma(N, dev, log)
     # dominant kernel of the headline mode: the finest-level smoothing sweep
@@ -444,7 +491,10 @@ def main():
                      "counted_GBs": traffic / (head["sweep_launch_ms"] * 1e-3) / 1e9 if traffic else None},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, log)
+        base, d_o, dfr_o = cpu_baseline(args, log)
+        base["gpu_vcycles"] = head["vcycles"][-1]
+        out["cpu_baseline"] = base
+        out["config"]["mixed_vs_oracle"] = mixed_vs_oracle(args, d_o, dfr_o, dev, log)
     print(json.dumps(out), flush=True)
 
 

@@ -72,7 +72,8 @@ typedef struct mgfr_params {
     double fr0_abs;  /* |fbar_R0| > 0 (the paper's fbar_R0 is negative) */
     int n;           /* Hu-Sawicki exponent n >= 1 (the paper runs n = 1) */
     int mesh;        /* N: cells per side, a power of two, 8 <= N <= 1024 (the 1024^3 solve needs ~60 GB) */
-    int refine_levels; /* must be 0 for the uniform-mesh context */
+    int refine_levels; /* refinement levels above the base mesh (Sec. 3.3): 0 for mgfr_create
+                          (uniform mesh), 1 or 2 for mgfr_amr_create */
     double tol;      /* accept when max|f - L(u)| / D <= tol, D = max|f| (Sec. 3.3 step 8); > 0 */
     int pre_smooth;  /* red-black sweeps before restriction, >= 0 */
     int post_smooth; /* red-black sweeps after the correction, >= 0 */
@@ -300,6 +301,11 @@ int64_t mgfr_net_num_params(const mgfr_net *net);
  * set_params also resets the Adam state. */
 int mgfr_net_get_params(mgfr_net *net, float *host);
 int mgfr_net_set_params(mgfr_net *net, const float *host);
+/* Checkpoint to / restore from a file: the master parameters, the Adam moments
+ * and step count, after a header naming the layer shapes.  load rejects a file
+ * of another layout (MGFR_ERR_ARG) and leaves the network unchanged then. */
+int mgfr_net_save(mgfr_net *net, const char *path);
+int mgfr_net_load(mgfr_net *net, const char *path);
 /* u = network(delta) for B volumes of side S (power of two, 32 <= S <= 1024).
  * delta, u: float64 [B][S^3]; cond: HOST float64 [B][2] = (a, |f_R0|) per volume. */
 int mgfr_net_predict(mgfr_net *net, const double *delta, int B, int S, const double *cond, double *u);

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <random>
 #include <vector>
@@ -776,6 +777,64 @@ extern "C" int mgfr_net_set_params(mgfr_net *n, const float *host)
     MGFR_HIP(hipMemsetAsync(n->m, 0, n->nparam * sizeof(float), n->stream));
     MGFR_HIP(hipMemsetAsync(n->v, 0, n->nparam * sizeof(float), n->stream));
     n->step = 0;
+    int rc = net_refresh(n);
+    if (rc) return rc;
+    MGFR_HIP(hipStreamSynchronize(n->stream));
+    return MGFR_OK;
+}
+
+// Checkpoint file: 8-byte tag "MGFRNET1", int64 parameter count, int32 Adam
+// step, int32 layer count (10) and each layer's (Cin, Cout) as int32, then the
+// float32 master parameters, Adam first and second moments (native byte order).
+namespace {
+constexpr char kNetTag[8] = {'M', 'G', 'F', 'R', 'N', 'E', 'T', '1'};
+}
+
+extern "C" int mgfr_net_save(mgfr_net *n, const char *path)
+{
+    if (!n || !path) return set_error(MGFR_ERR_ARG, "net and path must be non-NULL");
+    const size_t P = n->nparam;
+    std::vector<float> buf(3 * P);
+    MGFR_HIP(hipMemcpyAsync(buf.data(), n->p, P * sizeof(float), hipMemcpyDeviceToHost, n->stream));
+    MGFR_HIP(hipMemcpyAsync(buf.data() + P, n->m, P * sizeof(float), hipMemcpyDeviceToHost, n->stream));
+    MGFR_HIP(hipMemcpyAsync(buf.data() + 2 * P, n->v, P * sizeof(float), hipMemcpyDeviceToHost, n->stream));
+    MGFR_HIP(hipStreamSynchronize(n->stream));
+    FILE *f = fopen(path, "wb");
+    if (!f) return set_error(MGFR_ERR_ARG, "cannot open %s for writing", path);
+    const int64_t np = (int64_t)P;
+    int32_t hdr[2 + 20];
+    hdr[0] = n->step;
+    hdr[1] = 10;
+    for (int i = 0; i < 10; ++i) {
+        hdr[2 + 2 * i] = n->L[i].cin;
+        hdr[3 + 2 * i] = n->L[i].cout;
+    }
+    const bool ok = fwrite(kNetTag, 1, 8, f) == 8 && fwrite(&np, sizeof np, 1, f) == 1 &&
+                    fwrite(hdr, sizeof hdr, 1, f) == 1 && fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    if (fclose(f) != 0 || !ok) return set_error(MGFR_ERR_ARG, "writing %s failed", path);
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_net_load(mgfr_net *n, const char *path)
+{
+    if (!n || !path) return set_error(MGFR_ERR_ARG, "net and path must be non-NULL");
+    FILE *f = fopen(path, "rb");
+    if (!f) return set_error(MGFR_ERR_ARG, "cannot open %s", path);
+    char tag[8];
+    int64_t np = 0;
+    int32_t hdr[2 + 20];
+    const size_t P = n->nparam;
+    std::vector<float> buf(3 * P);
+    bool ok = fread(tag, 1, 8, f) == 8 && memcmp(tag, kNetTag, 8) == 0 && fread(&np, sizeof np, 1, f) == 1 &&
+              np == (int64_t)P && fread(hdr, sizeof hdr, 1, f) == 1 && hdr[1] == 10;
+    for (int i = 0; ok && i < 10; ++i) ok = hdr[2 + 2 * i] == n->L[i].cin && hdr[3 + 2 * i] == n->L[i].cout;
+    ok = ok && fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    fclose(f);
+    if (!ok) return set_error(MGFR_ERR_ARG, "%s is not a checkpoint of this network", path);
+    MGFR_HIP(hipMemcpyAsync(n->p, buf.data(), P * sizeof(float), hipMemcpyHostToDevice, n->stream));
+    MGFR_HIP(hipMemcpyAsync(n->m, buf.data() + P, P * sizeof(float), hipMemcpyHostToDevice, n->stream));
+    MGFR_HIP(hipMemcpyAsync(n->v, buf.data() + 2 * P, P * sizeof(float), hipMemcpyHostToDevice, n->stream));
+    n->step = hdr[0];
     int rc = net_refresh(n);
     if (rc) return rc;
     MGFR_HIP(hipStreamSynchronize(n->stream));

@@ -144,6 +144,8 @@ def lib() -> C.CDLL:
         L.mgfr_net_num_params.restype = C.c_int64
         L.mgfr_net_get_params.argtypes = [_VP, _VP]
         L.mgfr_net_set_params.argtypes = [_VP, _VP]
+        L.mgfr_net_save.argtypes = [_VP, C.c_char_p]
+        L.mgfr_net_load.argtypes = [_VP, C.c_char_p]
         L.mgfr_net_predict.argtypes = [_VP, _VP, C.c_int, C.c_int, _VP, _VP]
         L.mgfr_net_train_step.argtypes = [_VP, _VP, _VP, C.c_int, C.c_int, _VP, C.c_float,
                                           C.POINTER(C.c_float)]
@@ -426,6 +428,14 @@ class Net:
         if p.size != self.num_params:
             raise ValueError("wrong parameter count")
         _check(lib().mgfr_net_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+
+    def save(self, path: str):
+        """Checkpoint parameters and Adam state to a file."""
+        _check(lib().mgfr_net_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Restore parameters and Adam state written by save()."""
+        _check(lib().mgfr_net_load(self._h, os.fsencode(path)))
 
     def predict(self, delta: torch.Tensor, cond) -> torch.Tensor:
         self._sync()

@@ -266,6 +266,46 @@ int mgfr_solve(mgfr_ctx *ctx, const double *delta, double *u, double *dfr, mgfr_
  * u: float64 [N^3]; pos: float32 [np][3]; acc: float32 [np][3] output. */
 int mgfr_fifth_force(mgfr_ctx *ctx, const double *u, const float *pos, int64_t np, float *acc);
 
+/* Chained time steps (the paper's solve is one per time step and starts from
+ * the previous step's u, Sec. 3.3 step 2).  These calls carry a particle-mesh
+ * step around the solve; the Newtonian part is the standard PM force, not a
+ * step of the paper's method.
+ *
+ * mgfr_set_scale_factor: change a (the background of Sec. 2 is recomputed on
+ * the host; nothing is reallocated).  MGFR_ERR_ARG unless a > 0.
+ *
+ * mgfr_pm_accel: peculiar acceleration of the particles, acc = -(1/a) grad_x Psi
+ * with Psi = phi + (c^2/2) fbar e^u, where lap_x phi = (3/2) Omega_m H0^2 delta / a
+ * (H0 = 100 km/s per Mpc/h) is solved by FFT with the eigenvalues of the
+ * periodic 7-point Laplacian (zero mean), and the second term is the fifth
+ * force of mgfr_fifth_force (Sec. 2, Eq. modgrav_accel); u == NULL gives the
+ * Newtonian acceleration alone.  Same gradient and cloud-in-cell gather as
+ * mgfr_fifth_force; units (km/s)^2 h/Mpc.  delta, u: float64 [N^3]; pos,
+ * acc: float32 [np][3].  The first call makes two FFT plans and an
+ * N^2 (N/2+1) complex workspace, kept by the context.
+ *
+ * mgfr_kick_drift: mom += acc kick, then pos += mom drift, every component in
+ * float64 as fused multiply-adds from the float32 values and stored as float32;
+ * positions wrapped into [0, box).  acc may be NULL (drift only); pos, mom,
+ * acc float32 [np][3], in place.  With p = a^2 dx/dt the equations of motion
+ * are dp/da = g / H(a) and dx/da = p / (a^3 H(a)); the caller chooses the
+ * kick and drift integrals of a step. */
+int mgfr_set_scale_factor(mgfr_ctx *ctx, double a);
+int mgfr_pm_accel(mgfr_ctx *ctx, const double *delta, const double *u, const float *pos, int64_t np, float *acc);
+int mgfr_kick_drift(mgfr_ctx *ctx, float *pos, float *mom, const float *acc, int64_t np, double kick, double drift);
+
+/* One kick-drift-kick step from the context's a = a0 to a1 > a0 with the
+ * midpoint rule, am = (a0 + a1)/2, H(a) = 100 sqrt(Omega_m a^-3 + Omega_L):
+ *   mom += acc (am - a0) / H((a0 + am)/2);  pos += mom (a1 - a0) / (am^3 H(am));
+ *   a = a1; delta = assignment of pos; u = solve from the u passed in (the
+ *   previous step's solution, Sec. 3.3 step 2); acc = mgfr_pm_accel(delta, u, pos);
+ *   mom += acc (a1 - am) / H((am + a1)/2).
+ * pos, mom, acc: float32 [np][3] in/out (acc in: the acceleration at a0);
+ * delta: float64 [N^3] output; u: float64 [N^3] in/out; st: the solve's stats.
+ * Returns the solve's status (MGFR_NOT_CONVERGED keeps going) or an error. */
+int mgfr_pm_step(mgfr_ctx *ctx, float *pos, float *mom, float *acc, int64_t np, double a1, double *delta, double *u,
+                 mgfr_stats *st);
+
 /* Per-step entry points (Sec. 3.3), used to check single steps.
  * mgfr_ngs_sweep: `sweeps` red-black sweeps on the finest level, u updated
  * in place, f = the source of L(u) = f.  mgfr_vcycle: one V-cycle on u with

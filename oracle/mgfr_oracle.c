@@ -1130,3 +1130,54 @@ void or_op_stencil(double h, double bC, int n, int64_t count, const double *uc, 
         L[s] = op_cell(u, 3, 1, 1, 1, ih2, bC, q, NULL);
     }
 }
+
+/* ---------------------------------------------------- chained particle-mesh steps */
+
+/* pref times the cloud-in-cell interpolation, to each particle, of the
+ * two-point central-difference gradient of a cell-centred field (the
+ * gradient and weights of or_fifth_force).  acc: [np][3]. */
+void or_gather_gradient(int N, double box, const double *field, int64_t np, const float *pos, double pref,
+                        double *acc)
+{
+    double h = box / N;
+#pragma omp parallel for
+    for (int64_t q = 0; q < np; ++q) {
+        long i0[3];
+        double t[3];
+        for (int d = 0; d < 3; ++d) {
+            double xi = (double)pos[3 * q + d] / h - 0.5;
+            double fl = floor(xi);
+            t[d] = xi - fl;
+            i0[d] = (long)fl;
+        }
+        double s[3] = {0, 0, 0};
+#define F(i, j, k) field[((size_t)wrapi(i, N) * N + wrapi(j, N)) * N + wrapi(k, N)]
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    double w = (a ? t[0] : 1.0 - t[0]) * (b ? t[1] : 1.0 - t[1]) * (c ? t[2] : 1.0 - t[2]);
+                    long i = i0[0] + a, j = i0[1] + b, k = i0[2] + c;
+                    s[0] += w * (F(i + 1, j, k) - F(i - 1, j, k)) / (2 * h);
+                    s[1] += w * (F(i, j + 1, k) - F(i, j - 1, k)) / (2 * h);
+                    s[2] += w * (F(i, j, k + 1) - F(i, j, k - 1)) / (2 * h);
+                }
+#undef F
+        for (int d = 0; d < 3; ++d) acc[3 * q + d] = pref * s[d];
+    }
+}
+
+/* Leapfrog kick and drift on float32 particle arrays: mom += acc kick, then
+ * pos += mom drift, each in float64 as one fused multiply-add from the float32
+ * values and rounded to float32; positions wrapped into [0, box).  acc may be
+ * NULL (drift only). */
+void or_kick_drift(int64_t np, float *pos, float *mom, const float *acc, double kick, double drift, double box)
+{
+    for (int64_t t = 0; t < 3 * np; ++t) {
+        double m = (double)mom[t];
+        if (acc) m = fma((double)acc[t], kick, m);
+        mom[t] = (float)m;
+        double x = fma((double)mom[t], drift, (double)pos[t]);
+        x -= box * floor(x / box);
+        pos[t] = (float)x;
+    }
+}

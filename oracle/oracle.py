@@ -96,6 +96,8 @@ def lib(serial: bool | None = None):
         L.or_amr_cic_cells.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(C.c_void_p), C.c_int64, fp, dp,
                                        C.c_int64, C.c_void_p, C.c_void_p, dp]
         L.or_op_stencil.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp, dp, dp]
+        L.or_gather_gradient.argtypes = [C.c_int, C.c_double, dp, C.c_int64, fp, C.c_double, dp]
+        L.or_kick_drift.argtypes = [C.c_int64, fp, fp, fp, C.c_double, C.c_double, C.c_double]
         _libs[path] = L
     return _libs[path]
 
@@ -372,3 +374,77 @@ def op_stencil(h, bC, uc, nb, n=1):
     out = np.empty(uc.size, np.float64)
     lib().or_op_stencil(h, bC, n, uc.size, _d(uc), _d(nb), _d(out))
     return out
+
+
+# ------------------------------------------------------ chained particle-mesh steps
+
+H0 = 100.0  # km/s per Mpc/h
+
+
+def hubble(a, omega_m, omega_l):
+    """H(a) of flat LCDM in km/s per Mpc/h."""
+    return H0 * np.sqrt(omega_m / a ** 3 + omega_l)
+
+
+def pm_potential(box, a, omega_m, delta):
+    """phi with lap phi = (3/2) Omega_m H0^2 delta / a for the periodic 7-point
+    Laplacian, by the definition: divide each Fourier mode by the stencil's
+    eigenvalue -(4/h^2) sum_d sin^2(pi n_d / N) (numpy's FFT as the transform);
+    the k = 0 mode of phi is zero."""
+    delta = np.asarray(delta, np.float64)
+    N = delta.shape[0]
+    h = box / N
+    F = np.fft.rfftn(delta)
+    n = np.fft.fftfreq(N) * N
+    nz = np.arange(N // 2 + 1)
+    s2 = (np.sin(np.pi * n / N) ** 2)[:, None, None] + (np.sin(np.pi * n / N) ** 2)[None, :, None] \
+        + (np.sin(np.pi * nz / N) ** 2)[None, None, :]
+    lam = -4.0 / h ** 2 * s2
+    lam[0, 0, 0] = 1.0
+    G = 1.5 * omega_m * H0 ** 2 / a / lam
+    G[0, 0, 0] = 0.0
+    return np.fft.irfftn(F * G, s=delta.shape, axes=(0, 1, 2))
+
+
+def gather_gradient(box, field, pos, pref):
+    field = np.ascontiguousarray(field, np.float64)
+    pos = np.ascontiguousarray(pos, np.float32)
+    acc = np.empty((pos.shape[0], 3), np.float64)
+    lib().or_gather_gradient(field.shape[0], box, _d(field), pos.shape[0], _f(pos), pref, _d(acc))
+    return acc
+
+
+def pm_accel(p, delta, u, pos):
+    """-(1/a) grad (phi + (c^2/2) |fbar| e^u) at the particles (u None: phi alone)."""
+    fb, _, _ = background(p)
+    psi = pm_potential(p.box, p.a, p.omega_m, delta)
+    if u is not None:
+        psi = psi + 0.5 * C_KMS ** 2 * fb * np.exp(np.asarray(u, np.float64))
+    return gather_gradient(p.box, psi, pos, -1.0 / p.a)
+
+
+def kick_drift(pos, mom, acc, kick, drift, box):
+    """In place on float32 arrays [np, 3]."""
+    assert pos.dtype == np.float32 and mom.dtype == np.float32 and pos.flags.c_contiguous and mom.flags.c_contiguous
+    ap = None if acc is None else _f(np.ascontiguousarray(acc, np.float32))
+    lib().or_kick_drift(pos.shape[0], _f(pos), _f(mom), ap, kick, drift, box)
+
+
+def pm_step(p, pos, mom, acc, a1, u):
+    """One kick-drift-kick step from a = p.a to a1 (midpoint-rule kick and
+    drift integrals of dp/da = g/H, dx/da = p/(a^3 H)); the solve at a1 starts
+    from u (the previous step's solution).  pos, mom (float32) are updated in
+    place; returns (delta, u, acc32, stats) at a1 and sets p.a = a1."""
+    a0 = p.a
+    am = 0.5 * (a0 + a1)
+    H = lambda a: hubble(a, p.omega_m, p.omega_l)
+    K1 = (am - a0) / H(0.5 * (a0 + am))
+    D = (a1 - a0) / (am ** 3 * H(am))
+    K2 = (a1 - am) / H(0.5 * (am + a1))
+    kick_drift(pos, mom, acc, K1, D, p.box)
+    p.a = a1
+    delta = density_contrast(cic_assign(p.mesh, p.box, pos))
+    s, u1, _, st = solve(p, delta, u0=u, want_dfr=False)
+    acc1 = pm_accel(p, delta, u1, pos).astype(np.float32)
+    kick_drift(pos, mom, acc1, K2, 0.0, p.box)
+    return delta, u1, acc1, st

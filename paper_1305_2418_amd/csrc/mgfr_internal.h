@@ -80,6 +80,9 @@ struct mgfr_ctx {
     uint32_t *bkey = nullptr, *bkey_s = nullptr, *bidx = nullptr, *perm = nullptr;
     void *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
+    // particle-mesh potential (mgfr_pm_accel): FFT plans and the half spectrum, made on first use
+    void *pm_fwd = nullptr, *pm_inv = nullptr;
+    double2 *pm_spec = nullptr;
 };
 
 namespace mgfr {
@@ -134,6 +137,11 @@ __device__ __forceinline__ bool cic_axis(float x, double h, int mask, int &i0, d
     i0 = (int)((long long)fl & (long long)mask);
     return true;
 }
+
+// particle-mesh potential (mgfr_spectrum.hip): phi with lap phi = (3/2) Omega_m H0^2 delta / a
+// by FFT of the 7-point Laplacian; delta and phi may not alias
+int pm_potential(mgfr_ctx *c, const double *delta, double *phi);
+void pm_free(mgfr_ctx *c);
 
 // learned warm start (mgfr_nn.hip)
 int nn_warm_start(mgfr_ctx *c, const double *delta, double *u, double *t_ms);

@@ -220,6 +220,19 @@ __device__ __forceinline__ float mx_prolong(const float *__restrict__ ec, const 
     return v;
 }
 
+// Element at a wave-uniform row pointer plus a 32-bit byte offset (lets the
+// compiler address with a scalar base and one 32-bit lane offset).
+template <typename T>
+__device__ __forceinline__ const T &at_off(const float *base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ T &at_off(float *base, uint32_t byte_off)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
+
 // ---------------------------------------------------------- colour pass (N >= 128)
 //
 // One colour of the float32 correction sweep on a level with N >= 128: the
@@ -315,17 +328,18 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
     const size_t rowbase = (size_t)jg << lg;
     // rows that update nothing load r of the tile's first row (already fetched)
     const size_t rrowbase = upd ? rowbase : (size_t)j0 << lg;
-    const size_t kk = (size_t)(k0 + 2 * lane), kh2 = (size_t)(k0 / 2 + lane);
+    // addresses: a wave-uniform row pointer (scalar arithmetic) plus a 32-bit lane offset
+    const uint32_t kk = 4u * (uint32_t)(k0 + 2 * lane), kh2 = 4u * (uint32_t)(k0 / 2 + lane);  // byte offsets
     auto pb = [&](int pl) { return (size_t)(pl & m) * plane + rowbase; };
     // u in natural order; e and r split by colour (column 0 of plane pl lies in half (pl + jg) & 1)
-    auto ldu = [&](int pl) { return *reinterpret_cast<const float2 *>(A.u + pb(pl) + kk); };
+    auto ldu = [&](int pl) { return at_off<float2>(A.u + pb(pl), kk); };
     auto lde = [&](int pl) {
-        const size_t b = pb(pl) + kh2;
         const bool odd = ((pl + jg) & 1) != 0;
-        return make_float2(A.e[b + (odd ? hN : 0)], A.e[b + (odd ? 0 : hN)]);
+        const float *h0 = A.e + pb(pl) + (odd ? hN : 0), *h1 = A.e + pb(pl) + (odd ? 0 : hN);
+        return make_float2(at_off<float>(h0, kh2), at_off<float>(h1, kh2));
     };
-    auto at_c = [&](int pl) { return pb(pl) + (size_t)A.colour * hN + kh2; };  // the updated cell's slot
-    auto at_r = [&](int pl) { return (size_t)(pl & m) * plane + rrowbase + (size_t)A.colour * hN + kh2; };
+    auto row_c = [&](int pl) { return A.e + pb(pl) + (size_t)A.colour * hN; };  // half of the updated cells
+    auto row_r = [&](int pl) { return A.r + (size_t)(pl & m) * plane + rrowbase + (size_t)A.colour * hN; };
     // k-halo duty: lanes 0..CTJ-1 of the upper halo wave serve row `lane`.  Every
     // lane of every wave issues the same loads in every plane (lane mod CTJ), so
     // that no load sits under a branch and the prefetch waits stay exact.
@@ -361,7 +375,7 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         Raw w;
         w.u = ldu(p + 1);
         w.e = lde(p + 1);
-        w.r = A.r[at_r(p)];
+        w.r = at_off<float>(row_r(p), kh2);
         w.khu = A.u[kh_u(p)];
         w.khe = A.e[kh_e(p)];
         return w;
@@ -385,7 +399,7 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
             const Cell4 sd = unpack(B[(row + 1) * CLW + lane + (S ? 2 : 0)]);
             const float en = S ? mx_update(c1, cur.r, c0, sd, up, dn, prev, n1, A.kc)
                                : mx_update(c0, cur.r, c1, sd, up, dn, prev, n0, A.kc);
-            A.e[at_c(p)] = en;
+            at_off<float>(row_c(p), kh2) = en;
         }
         prev = S ? c0 : c1;
         c0 = n0;
@@ -463,6 +477,47 @@ struct Sweep2Args {
     MxConst kc;
 };
 
+// (u, e, P = w X, W = w E) of a cell, w = e^u, X = e^e - 1 (fexpm1), E = e^e
+__device__ __forceinline__ float4 mx_cell4(float u, float e, float w)
+{
+    const float E = fexp(e);
+    const float X = fabsf(e) < 0x1p-10f ? fmaf(0.5f * e, e, e) : E - 1.0f;
+    return make_float4(u, e, w * X, w * E);
+}
+
+// New e at a cell c = (u, e, P, W) from its residual target r and six
+// neighbours (u, e, P, W): the Newton step of mx_update.
+__device__ __forceinline__ float own_update(const float4 &c, float r, const float4 &n0, const float4 &n1,
+                                            const float4 &n2, const float4 &n3, const float4 &n4, const float4 &n5,
+                                            const MxConst &k)
+{
+    float Su = 0.f, Se = 0.f, A = 0.f, B = 0.f, SW = 0.f;
+    auto add = [&](const float4 &n) {
+        const float du = n.x - c.x, de = n.y - c.y;
+        Su += du;
+        Se += de;
+        A = fmaf(n.z, du, A);
+        B = fmaf(n.w, de, B);
+        SW += n.w;
+    };
+    add(n0);
+    add(n1);
+    add(n2);
+    add(n3);
+    add(n4);
+    add(n5);
+    const float flux = 0.5f * ((A + c.z * Su) + (B + c.w * Se));
+    const float dflux = 0.5f * (c.w * (Su + Se - 6.0f) - SW);
+    const float sc = fexp(-k.q * c.x);
+    const float cm = fexpm1(-k.q * c.y);
+    const float bs = k.bC * sc;
+    const float N = k.ih2 * flux + bs * cm;
+    const float J = k.ih2 * dflux - k.q * bs * (1.0f + cm);
+    float d = -(N - r) * __builtin_amdgcn_rcpf(J) * k.omega;
+    if (k.max_du > 0.f) d = fminf(fmaxf(d, -k.max_du), k.max_du);
+    return c.y + d;
+}
+
 template <int S0>
 __device__ __forceinline__ void mx_sweep2_rows(const Sweep2Args &A, int i0, int j0, int k0, int w, int lane,
                                                float4 *sX)
@@ -472,14 +527,16 @@ __device__ __forceinline__ void mx_sweep2_rows(const Sweep2Args &A, int i0, int 
     const int jg = (j0 + w - 2) & m;
     const bool red_row = w >= 1 && w <= FW - 2;                          // uniform over the wave
     const bool blk_row = w >= 2 && w <= FW - 3 && j0 + w - 2 <= m;      // rows stored
-    const size_t rowb = (size_t)jg << lg, kh2 = (size_t)(k0 / 2 + lane);
+    const size_t rowb = (size_t)jg << lg;
+    // addresses: a wave-uniform row pointer plus a 32-bit lane byte offset
+    const uint32_t kk = 4u * (uint32_t)(k0 + 2 * lane), kh2 = 4u * (uint32_t)(k0 / 2 + lane);
     auto pb = [&](int pl) { return (size_t)(pl & m) * plane + rowb; };
-    auto ldu = [&](int pl) { return *reinterpret_cast<const float2 *>(A.u + pb(pl) + (size_t)k0 + 2 * lane); };
+    auto ldu = [&](int pl) { return at_off<float2>(A.u + pb(pl), kk); };
     // cell k0 + 2l lies in half (pl + jg) & 1 of its row (k0 is even)
     auto lde = [&](int pl) {
-        const size_t b = pb(pl) + kh2;
         const bool odd = ((pl + jg) & 1) != 0;
-        return make_float2(A.ein[b + (odd ? hN : 0)], A.ein[b + (odd ? 0 : hN)]);
+        return make_float2(at_off<float>(A.ein + pb(pl) + (odd ? hN : 0), kh2),
+                           at_off<float>(A.ein + pb(pl) + (odd ? 0 : hN), kh2));
     };
     // k-halo duty of the first wave: lane = 4 row + c, c -> k0 - 2, k0 - 1, k0 + 128, k0 + 129
     const bool hv = w == 0 && lane < 4 * FW;
@@ -490,42 +547,41 @@ __device__ __forceinline__ void mx_sweep2_rows(const Sweep2Args &A, int i0, int 
     const bool hin = hv && (hc == 1 || hc == 2) && hw >= 2 && hw <= FW - 3;
     const size_t hrow = (size_t)hjg << lg;
     auto hb = [&](int pl) { return (size_t)(pl & m) * plane + hrow; };
+    auto hle = [&](int pl) { return A.ein[hb(pl) + ((size_t)((pl + hjg + hk) & 1) << (lg - 1)) + (size_t)(hk >> 1)]; };
+    auto cell = [&](float u, float e) { return mx_cell4(u, e, fexp(u)); };
     auto at = [&](int buf, int row, int par, int slot) { return ((buf * FW + row) * 2 + par) * FS + slot; };
 
     // raw loads of step p, issued one step ahead in two alternating register sets
     struct Raw {
-        float2 u, e;     // plane p + 2
-        float rr, rb;    // r of the red cell of plane p + 1, of the black cell of plane p
+        float2 u, e;       // plane p + 2
+        float rr, rb;      // r of the red cell of plane p + 1, of the black cell of plane p
         float hu, he, hr;  // k-halo cell: u, e of plane p + 2, r of plane p + 1 (red half)
     };
     auto load = [&](int p) {
         Raw x;
         x.u = ldu(p + 2);
         x.e = lde(p + 2);
-        x.rr = A.r[pb(p + 1) + kh2];
-        x.rb = A.r[pb(p) + hN + kh2];
+        x.rr = at_off<float>(A.r + pb(p + 1), kh2);
+        x.rb = at_off<float>(A.r + pb(p) + hN, kh2);
         x.hu = A.u[hb(p + 2) + (size_t)hk];
-        x.he = A.ein[hb(p + 2) + ((size_t)(((p + 2) + hjg + hk) & 1) << (lg - 1)) + (size_t)(hk >> 1)];
+        x.he = hle(p + 2);
         x.hr = A.r[hb(p + 1) + (size_t)(hk >> 1)];
         return x;
     };
 
     // planes i0 - 2 (P0) and i0 - 1 (P1), old values; the k-halo cell of plane
     // p is read back from LDS, that of plane p + 1 is kept in H1
-    Cell4 P0[2], P1[2], prev, H1;
+    float4 P0[2], P1[2], H1, prev;
     {
         const float2 ua = ldu(i0 - 2), ea = lde(i0 - 2), ub = ldu(i0 - 1), eb = lde(i0 - 1);
-        P0[0] = mx_cell(ua.x, ea.x);
-        P0[1] = mx_cell(ua.y, ea.y);
-        P1[0] = mx_cell(ub.x, eb.x);
-        P1[1] = mx_cell(ub.y, eb.y);
+        P0[0] = cell(ua.x, ea.x);
+        P0[1] = cell(ua.y, ea.y);
+        P1[0] = cell(ub.x, eb.x);
+        P1[1] = cell(ub.y, eb.y);
         prev = P0[0];
-        const int pa = i0 - 2, pq = i0 - 1;
-        const Cell4 H0 = mx_cell(A.u[hb(pa) + (size_t)hk],
-                                 A.ein[hb(pa) + ((size_t)((pa + hjg + hk) & 1) << (lg - 1)) + (size_t)(hk >> 1)]);
-        if (hv) sX[at(0, hw, hpar, hslot)] = pack(H0);  // ordered by the first step's barrier
-        H1 = mx_cell(A.u[hb(pq) + (size_t)hk],
-                     A.ein[hb(pq) + ((size_t)((pq + hjg + hk) & 1) << (lg - 1)) + (size_t)(hk >> 1)]);
+        const float4 H0 = cell(A.u[hb(i0 - 2) + (size_t)hk], hle(i0 - 2));
+        if (hv) sX[at(0, hw, hpar, hslot)] = H0;  // ordered by the first step's barrier
+        H1 = cell(A.u[hb(i0 - 1) + (size_t)hk], hle(i0 - 1));
     }
     Raw ra = load(i0 - 2), rb;
     int x0 = 0, x1 = 1, x2 = 2;  // LDS buffers of planes p, p + 1, p + 2
@@ -535,44 +591,47 @@ __device__ __forceinline__ void mx_sweep2_rows(const Sweep2Args &A, int i0, int 
         constexpr int S = decltype(Sc)::value;
         constexpr bool BLACK = decltype(Bc)::value;
         nxt = load(p + 1);
-        const Cell4 Q0 = mx_cell(cur.u.x, cur.e.x), Q1 = mx_cell(cur.u.y, cur.e.y);
-        const Cell4 &QS = S ? Q1 : Q0;
-        Cell4 HQ = H1;
-        if (w == 0) HQ = mx_cell(cur.hu, cur.he);
+        const float4 Q0 = cell(cur.u.x, cur.e.x), Q1 = cell(cur.u.y, cur.e.y);
+        const float4 &QS = S ? Q1 : Q0;
+        float4 HQ = H1;
+        if (w == 0) HQ = cell(cur.hu, cur.he);
         // publish the old black cell of plane p + 1 (and the k-halo cells)
-        sX[at(x1, w, 1 - S, lane + 1)] = pack(P1[1 - S]);
-        if (hv) sX[at(x1, hw, hpar, hslot)] = pack(H1);
+        sX[at(x1, w, 1 - S, lane + 1)] = P1[1 - S];
+        if (hv) sX[at(x1, hw, hpar, hslot)] = H1;
         __syncthreads();
         // red cell of plane p + 1: neighbours black and old
         if (red_row) {
-            const Cell4 sd = unpack(S ? sX[at(x1, w, 0, lane + 2)] : sX[at(x1, w, 1, lane)]);
-            const Cell4 up = unpack(sX[at(x1, w - 1, S, lane + 1)]);
-            const Cell4 dn = unpack(sX[at(x1, w + 1, S, lane + 1)]);
-            const float en = mx_update(P1[S], cur.rr, P1[1 - S], sd, up, dn, P0[S], QS, A.kc);
-            P1[S] = mx_cell(P1[S].u, en);
-            sX[at(x1, w, S, lane + 1)] = pack(P1[S]);
-            if (blk_row && p + 1 >= i0 && p + 1 < iend) A.eout[pb(p + 1) + kh2] = en;
+            const float4 sd = S ? sX[at(x1, w, 0, lane + 2)] : sX[at(x1, w, 1, lane)];
+            const float4 up = sX[at(x1, w - 1, S, lane + 1)];
+            const float4 dn = sX[at(x1, w + 1, S, lane + 1)];
+            const float wr = fexp(P1[S].x);
+            const float en = own_update(P1[S], cur.rr, P1[1 - S], sd, up, dn, P0[S], QS, A.kc);
+            P1[S] = mx_cell4(P1[S].x, en, wr);
+            sX[at(x1, w, S, lane + 1)] = P1[S];
+            if (blk_row && p + 1 >= i0 && p + 1 < iend) at_off<float>(A.eout + pb(p + 1), kh2) = en;
         }
         if (w == 0) {
             // red k-halo cells of the stored rows
             if (hin && (((p + 1) + hjg + hk) & 1) == 0) {
-                const Cell4 na = unpack(hc == 1 ? sX[at(x1, hw, 0, 0)] : sX[at(x1, hw, 1, FS - 1)]);
-                const Cell4 nb = unpack(hc == 1 ? sX[at(x1, hw, 0, 1)] : sX[at(x1, hw, 1, FS - 2)]);
-                const Cell4 up = unpack(sX[at(x1, hw - 1, hpar, hslot)]);
-                const Cell4 dn = unpack(sX[at(x1, hw + 1, hpar, hslot)]);
-                const Cell4 H0 = unpack(sX[at(x0, hw, hpar, hslot)]);
-                const float en = mx_update(H1, cur.hr, na, nb, up, dn, H0, HQ, A.kc);
-                H1 = mx_cell(H1.u, en);
-                sX[at(x1, hw, hpar, hslot)] = pack(H1);
+                const float4 na = hc == 1 ? sX[at(x1, hw, 0, 0)] : sX[at(x1, hw, 1, FS - 1)];
+                const float4 nb = hc == 1 ? sX[at(x1, hw, 0, 1)] : sX[at(x1, hw, 1, FS - 2)];
+                const float4 up = sX[at(x1, hw - 1, hpar, hslot)];
+                const float4 dn = sX[at(x1, hw + 1, hpar, hslot)];
+                const float4 H0 = sX[at(x0, hw, hpar, hslot)];
+                const float wh = fexp(H1.x);
+                const float en = own_update(H1, cur.hr, na, nb, up, dn, H0, HQ, A.kc);
+                H1 = mx_cell4(H1.x, en, wh);
+                sX[at(x1, hw, hpar, hslot)] = H1;
             }
         }
         // black cell of plane p: neighbours red and new (plane p's buffer was
         // completed in the previous step)
         if (BLACK && blk_row) {
-            const Cell4 sd = unpack(S ? sX[at(x0, w, 0, lane + 2)] : sX[at(x0, w, 1, lane)]);
-            const Cell4 up = unpack(sX[at(x0, w - 1, S, lane + 1)]);
-            const Cell4 dn = unpack(sX[at(x0, w + 1, S, lane + 1)]);
-            A.eout[pb(p) + hN + kh2] = mx_update(P0[S], cur.rb, P0[1 - S], sd, up, dn, prev, P1[S], A.kc);
+            const float4 sd = S ? sX[at(x0, w, 0, lane + 2)] : sX[at(x0, w, 1, lane)];
+            const float4 up = sX[at(x0, w - 1, S, lane + 1)];
+            const float4 dn = sX[at(x0, w + 1, S, lane + 1)];
+            at_off<float>(A.eout + pb(p) + hN, kh2) =
+                own_update(P0[S], cur.rb, P0[1 - S], sd, up, dn, prev, P1[S], A.kc);
         }
         prev = P0[1 - S];
         P0[0] = P1[0];

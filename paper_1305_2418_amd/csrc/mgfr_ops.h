@@ -196,13 +196,17 @@ struct MxConst {
 // perturbs the linearisation point the float64 outer loop corrects anyway).
 __device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 
-// e^x - 1 without cancellation: Taylor series to x^6 for |x| < 1/4 (truncation
-// below 2e-8 relative), fexp(x) - 1 otherwise (at most ~5 ulp of cancellation).
+// e^x - 1 for the float32 correction cycle: x + x^2/2 for |x| < 2^-10
+// (truncation below 2e-7 relative), fexp(x) - 1 otherwise (cancellation at
+// most ~1.2e-4 relative, at |x| = 2^-10, falling as 1/|x|).  Its relative
+// error is proportional to expm1 itself, so the correction operator stays
+// free of the O(ulp) absolute error that would stall the outer loop; the
+// float64 residual decides convergence.
 __device__ __forceinline__ float fexpm1(float x)
 {
-    const float p = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
     const float q = fexp(x) - 1.0f;  // evaluated unconditionally: a select, not a branch
-    return __builtin_amdgcn_fmed3f(fabsf(x), 0.0f, 0.25f) < 0.25f ? p : q;
+    const float p = fmaf(0.5f * x, x, x);
+    return fabsf(x) < 0x1p-10f ? p : q;
 }
 
 // Newton step on e at one cell from precomputed per-cell quantities:

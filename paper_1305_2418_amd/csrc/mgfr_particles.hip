@@ -366,6 +366,33 @@ __global__ __launch_bounds__(kBlock) void k_force_binned(const double *__restric
     }
 }
 
+// Psi = phi + (c^2/2) fbar e^u in place (the total potential of a
+// particle-mesh step: g = -(1/a) grad Psi; u == NULL: phi alone)
+__global__ __launch_bounds__(kBlock) void k_psi(double *__restrict__ phi, const double *__restrict__ u, double s,
+                                                size_t n)
+{
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock)
+        phi[t] = fma(s, exp(u[t]), phi[t]);
+}
+
+// mom += acc kick, then pos += mom drift, per component in float64 with
+// explicit fused multiply-adds (the rounding is part of the definition), both
+// stored as float32; positions are wrapped into [0, box).
+__global__ __launch_bounds__(kBlock) void k_kick_drift(float *__restrict__ pos, float *__restrict__ mom,
+                                                       const float *__restrict__ acc, size_t n3, double kick,
+                                                       double drift, double box)
+{
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n3; t += (size_t)gridDim.x * kBlock) {
+        double m = (double)mom[t];
+        if (acc) m = fma((double)acc[t], kick, m);
+        const float mf = (float)m;
+        mom[t] = mf;
+        double x = fma((double)mf, drift, (double)pos[t]);
+        x -= box * floor(x / box);
+        pos[t] = (float)x;
+    }
+}
+
 // Zero an array of n doubles and one int flag: the clearing step of the
 // allocation-free assignment (a kernel, not a memset, so that a captured
 // graph replays it faithfully).
@@ -445,6 +472,75 @@ extern "C" int mgfr_fifth_force(mgfr_ctx *c, const double *u, const float *pos, 
     MGFR_HIP(hipStreamSynchronize(c->stream));
     if (*hflag) return set_error(MGFR_ERR_NONFINITE, "a particle position is not finite");
     return MGFR_OK;
+}
+
+extern "C" int mgfr_pm_accel(mgfr_ctx *c, const double *delta, const double *u, const float *pos, int64_t np,
+                             float *acc)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (!delta || !pos || !acc) return set_error(MGFR_ERR_ARG, "delta, pos and acc must be non-NULL");
+    if (np < 0) return set_error(MGFR_ERR_ARG, "np must be >= 0");
+    if (np == 0) return MGFR_OK;
+    const Level &L0 = c->lev[0];
+    const size_t n = (size_t)L0.N * L0.N * L0.N;
+    double *psi = L0.f;  // the level-0 source buffer is free between solves
+    if (int rc = pm_potential(c, delta, psi)) return rc;
+    if (u) k_psi<<<grid_for(n, 8192), kBlock, 0, c->stream>>>(psi, u, 0.5 * kCkms * kCkms * c->fbar, n);
+    MGFR_HIP(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+    const size_t pblocks = (size_t)((np + kBlock - 1) / kBlock);
+    if (pblocks > 0x7fffffffULL) return set_error(MGFR_ERR_ARG, "np too large");
+    const double pref = -1.0 / c->p.a;
+    if (c->perm_np == np && c->perm) {
+        k_force_binned<<<(unsigned)((np + kCicChunk - 1) / kCicChunk), kBlock, 0, c->stream>>>(
+            psi, pos, c->bkey_s, c->perm, np, L0.lg, L0.h, pref, acc, c->dflag);
+    } else {
+        k_force_gather<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(psi, pos, nullptr, np, L0.lg, L0.h, pref, acc,
+                                                                     c->dflag);
+    }
+    MGFR_HIP(hipGetLastError());
+    int *hflag = (int *)(c->hscal + 6);
+    MGFR_HIP(hipMemcpyAsync(hflag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    MGFR_HIP(hipStreamSynchronize(c->stream));
+    if (*hflag) return set_error(MGFR_ERR_NONFINITE, "a particle position is not finite");
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_kick_drift(mgfr_ctx *c, float *pos, float *mom, const float *acc, int64_t np, double kick,
+                               double drift)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (!pos || !mom) return set_error(MGFR_ERR_ARG, "pos and mom must be non-NULL");
+    if (np < 0) return set_error(MGFR_ERR_ARG, "np must be >= 0");
+    if (!std::isfinite(kick) || !std::isfinite(drift)) return set_error(MGFR_ERR_ARG, "kick and drift must be finite");
+    if (np == 0) return MGFR_OK;
+    const size_t n3 = 3 * (size_t)np;
+    k_kick_drift<<<grid_for(n3, 65536), kBlock, 0, c->stream>>>(pos, mom, acc, n3, kick, drift, c->p.box);
+    MGFR_HIP(hipGetLastError());
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_pm_step(mgfr_ctx *c, float *pos, float *mom, float *acc, int64_t np, double a1, double *delta,
+                            double *u, mgfr_stats *st)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (!pos || !mom || !acc || !delta || !u) return set_error(MGFR_ERR_ARG, "null argument");
+    if (np < 1) return set_error(MGFR_ERR_ARG, "np must be >= 1");
+    const double a0 = c->p.a;
+    if (!(a1 > a0) || !std::isfinite(a1)) return set_error(MGFR_ERR_ARG, "a1 must exceed the current a = %g", a0);
+    const double om = c->p.omega_m, ol = c->p.omega_l;
+    auto H = [&](double a) { return 100.0 * std::sqrt(om / (a * a * a) + ol); };  // km/s per Mpc/h
+    const double am = 0.5 * (a0 + a1);
+    const double K1 = (am - a0) / H(0.5 * (a0 + am)), K2 = (a1 - am) / H(0.5 * (am + a1));
+    const double D = (a1 - a0) / (am * am * am * H(am));
+    int rc;
+    if ((rc = mgfr_kick_drift(c, pos, mom, acc, np, K1, D))) return rc;
+    if ((rc = mgfr_set_scale_factor(c, a1))) return rc;
+    if ((rc = mgfr_assign_density(c, pos, nullptr, np, delta))) return rc;
+    const int status = mgfr_solve(c, delta, u, nullptr, st);
+    if (status < 0) return status;
+    if ((rc = mgfr_pm_accel(c, delta, u, pos, np, acc))) return rc;
+    if ((rc = mgfr_kick_drift(c, pos, mom, acc, np, K2, 0.0))) return rc;
+    return status;
 }
 
 extern "C" int mgfr_reserve_particles(mgfr_ctx *c, int64_t max_np)

@@ -726,6 +726,7 @@ static void free_ctx(mgfr_ctx *c)
     if (!c) return;
     nn_free(c);
     bin_free(c);
+    pm_free(c);
     for (int l = 0; l < kMaxLevels; ++l) {
         Level &L = c->lev[l];
         if (l > 0) {
@@ -826,6 +827,22 @@ extern "C" int mgfr_set_stream(mgfr_ctx *c, void *stream)
 {
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
     c->stream = (hipStream_t)stream;
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_set_scale_factor(mgfr_ctx *c, double a)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (!(a > 0) || !std::isfinite(a)) return set_error(MGFR_ERR_ARG, "a must be > 0 and finite");
+    mgfr_params q = c->p;
+    q.a = a;
+    double fb, beta, C;
+    if (int rc = mgfr_background(&q, &fb, &beta, &C)) return rc;
+    c->p.a = a;
+    c->fbar = fb;
+    c->beta = beta;
+    c->C = C;
+    c->bC = beta * C;
     return MGFR_OK;
 }
 

@@ -168,3 +168,84 @@ extern "C" int mgfr_power_ratio(mgfr_ctx *c, const double *delta, const double *
     (void)hipFree(acc);
     return rc;
 }
+
+// ------------------------------------------------------------------------
+// Particle-mesh potential for chained steps: lap_x phi = (3/2) Omega_m H0^2
+// delta / a with the periodic 7-point Laplacian (the operator's own
+// discretisation), inverted exactly in Fourier space: its eigenvalue at
+// integer wave vector n is -(4/h^2) sum_d sin^2(pi n_d / N).  H0 = 100 in
+// km/s per Mpc/h, so phi is in (km/s)^2.  The k = 0 mode of phi is zero.
+namespace mgfr {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_pm_green(double2 *__restrict__ F, int lg, double ih2, double pref)
+{
+    const int N = 1 << lg, Nz = N / 2 + 1;
+    const size_t n = (size_t)N * N * Nz;
+    const double pN = M_PI / (double)N;
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (size_t)gridDim.x * kBlock) {
+        const int iz = (int)(t % Nz);
+        const size_t r = t / Nz;
+        const int iy = (int)(r & (N - 1)), ix = (int)(r >> lg);
+        const double sx = sin(pN * ix), sy = sin(pN * iy), sz = sin(pN * iz);
+        const double lam = 4.0 * ih2 * (sx * sx + sy * sy + sz * sz);  // minus the Laplacian's eigenvalue
+        const double g = (ix | iy | iz) ? -pref / lam : 0.0;
+        F[t].x *= g;
+        F[t].y *= g;
+    }
+}
+
+}  // namespace
+
+void pm_free(mgfr_ctx *c)
+{
+    if (c->pm_fwd) (void)hipfftDestroy((hipfftHandle)c->pm_fwd);
+    if (c->pm_inv) (void)hipfftDestroy((hipfftHandle)c->pm_inv);
+    (void)hipFree(c->pm_spec);
+    c->pm_fwd = c->pm_inv = nullptr;
+    c->pm_spec = nullptr;
+}
+
+int pm_potential(mgfr_ctx *c, const double *delta, double *phi)
+{
+    const Level &L0 = c->lev[0];
+    const int N = L0.N;
+    const size_t n = (size_t)N * N * N, nc = (size_t)N * N * (N / 2 + 1);
+    hipfftResult fr;
+    if (!c->pm_spec) {
+        if (hipMalloc(&c->pm_spec, nc * sizeof(double2)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->pm_spec = nullptr;
+            return set_error(MGFR_ERR_OOM, "particle-mesh spectrum for N = %d", N);
+        }
+        hipfftHandle a = 0, b = 0;
+        if ((fr = hipfftPlan3d(&a, N, N, N, HIPFFT_D2Z)) != HIPFFT_SUCCESS) {
+            pm_free(c);
+            return set_error(MGFR_ERR_HIP, "%s (particle-mesh plan)", fft_err(fr));
+        }
+        c->pm_fwd = (void *)a;
+        if ((fr = hipfftPlan3d(&b, N, N, N, HIPFFT_Z2D)) != HIPFFT_SUCCESS) {
+            pm_free(c);
+            return set_error(MGFR_ERR_HIP, "%s (particle-mesh plan)", fft_err(fr));
+        }
+        c->pm_inv = (void *)b;
+    }
+    const hipfftHandle a = (hipfftHandle)c->pm_fwd, b = (hipfftHandle)c->pm_inv;
+    if ((fr = hipfftSetStream(a, c->stream)) != HIPFFT_SUCCESS || (fr = hipfftSetStream(b, c->stream)) != HIPFFT_SUCCESS)
+        return set_error(MGFR_ERR_HIP, "%s (stream)", fft_err(fr));
+    const unsigned g = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 16384);
+    k_add<<<g, kBlock, 0, c->stream>>>(delta, nullptr, n, phi);  // the transform may overwrite its input
+    MGFR_HIP(hipGetLastError());
+    if ((fr = hipfftExecD2Z(a, phi, (hipfftDoubleComplex *)c->pm_spec)) != HIPFFT_SUCCESS)
+        return set_error(MGFR_ERR_HIP, "%s (transform)", fft_err(fr));
+    const double H0 = 100.0;
+    const double pref = 1.5 * c->p.omega_m * H0 * H0 / c->p.a / (double)n;  // with the 1/N^3 of the inverse
+    const unsigned gc = (unsigned)std::min<size_t>((nc + kBlock - 1) / kBlock, 16384);
+    k_pm_green<<<gc, kBlock, 0, c->stream>>>(c->pm_spec, L0.lg, 1.0 / (L0.h * L0.h), pref);
+    MGFR_HIP(hipGetLastError());
+    if ((fr = hipfftExecZ2D(b, (hipfftDoubleComplex *)c->pm_spec, phi)) != HIPFFT_SUCCESS)
+        return set_error(MGFR_ERR_HIP, "%s (inverse transform)", fft_err(fr));
+    return MGFR_OK;
+}
+
+}  // namespace mgfr

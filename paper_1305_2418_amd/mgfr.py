@@ -133,6 +133,10 @@ def lib() -> C.CDLL:
         L.mgfr_set_binning.argtypes = [_VP, C.c_int]
         L.mgfr_solve.argtypes = [_VP, _VP, _VP, _VP, C.POINTER(_Stats)]
         L.mgfr_fifth_force.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
+        L.mgfr_set_scale_factor.argtypes = [_VP, C.c_double]
+        L.mgfr_pm_accel.argtypes = [_VP, _VP, _VP, _VP, C.c_int64, _VP]
+        L.mgfr_kick_drift.argtypes = [_VP, _VP, _VP, _VP, C.c_int64, C.c_double, C.c_double]
+        L.mgfr_pm_step.argtypes = [_VP, _VP, _VP, _VP, C.c_int64, C.c_double, _VP, _VP, C.POINTER(_Stats)]
         L.mgfr_ngs_sweep.argtypes = [_VP, _VP, _VP, C.c_int]
         L.mgfr_vcycle.argtypes = [_VP, _VP, _VP]
         L.mgfr_residual.argtypes = [_VP, _VP, _VP, _VP]
@@ -356,6 +360,46 @@ class Solver:
         ap = _dev(out, torch.float32, (npart, 3), "acc")
         _check(lib().mgfr_fifth_force(self._h, up, pp, npart, ap))
         return out
+
+    def set_scale_factor(self, a: float):
+        _check(lib().mgfr_set_scale_factor(self._h, float(a)))
+        self.params.a = float(a)
+
+    def pm_accel(self, delta: torch.Tensor, u: torch.Tensor | None, pos: torch.Tensor, out: torch.Tensor | None = None):
+        """Peculiar acceleration -(1/a) grad (phi + (c^2/2) fbar e^u) at the particles (float32 [np, 3])."""
+        self._sync_stream()
+        npart = pos.shape[0]
+        dp = _dev(delta, torch.float64, self.shape, "delta")
+        up = _dev(u, torch.float64, self.shape, "u", allow_none=True)
+        pp = _dev(pos, torch.float32, (npart, 3), "pos")
+        if out is None:
+            out = torch.empty((npart, 3), dtype=torch.float32, device=pos.device)
+        ap = _dev(out, torch.float32, (npart, 3), "acc")
+        _check(lib().mgfr_pm_accel(self._h, dp, up, pp, npart, ap))
+        return out
+
+    def kick_drift(self, pos: torch.Tensor, mom: torch.Tensor, acc: torch.Tensor | None, kick: float, drift: float):
+        """mom += acc kick; pos += mom drift (in place, float32 [np, 3])."""
+        self._sync_stream()
+        npart = pos.shape[0]
+        pp = _dev(pos, torch.float32, (npart, 3), "pos")
+        mp = _dev(mom, torch.float32, (npart, 3), "mom")
+        ap = _dev(acc, torch.float32, (npart, 3), "acc", allow_none=True)
+        _check(lib().mgfr_kick_drift(self._h, pp, mp, ap, npart, float(kick), float(drift)))
+
+    def pm_step(self, pos, mom, acc, a1: float, delta, u, allow_not_converged: bool = True):
+        """One kick-drift-kick step to a1 (all arrays updated in place); returns the solve's Stats."""
+        self._sync_stream()
+        npart = pos.shape[0]
+        args = [_dev(pos, torch.float32, (npart, 3), "pos"), _dev(mom, torch.float32, (npart, 3), "mom"),
+                _dev(acc, torch.float32, (npart, 3), "acc")]
+        dp = _dev(delta, torch.float64, self.shape, "delta")
+        up = _dev(u, torch.float64, self.shape, "u")
+        st = _Stats()
+        rc = lib().mgfr_pm_step(self._h, *args, npart, float(a1), dp, up, C.byref(st))
+        _check(rc, allow_not_converged=allow_not_converged)
+        self.params.a = float(a1)
+        return Stats.from_c(st)
 
     def set_net(self, net):
         _check(lib().mgfr_set_net(self._h, None if net is None else net._h))

@@ -69,22 +69,27 @@ def gaussian_field_k(n: int, box: float, rms: float, seed: int, slope: float = -
     return dk * (rms / s if s > 0 else 0.0)
 
 
-def zeldovich(n: int, box: float, rms: float, seed: int, device="cpu") -> torch.Tensor:
+def zeldovich(n: int, box: float, rms: float, seed: int, device="cpu", displacement: bool = False):
     """n^3 lattice particles displaced by psi = -grad(Laplacian^-1 delta_L), float64 [n^3,3].
 
     delta_L is the P(k) ~ k^-2 Gaussian field of :func:`gaussian_field_k`;
     the displacement obeys div psi = -delta_L, i.e. psi_k = i k delta_k / k^2.
+    With ``displacement`` the displacements psi [n^3, 3] are returned too.
     """
     dk = gaussian_field_k(n, box, rms, seed, device=device)
     kx, ky, kz = _kgrid(n, box, device)
     k2 = kx * kx + ky * ky + kz * kz
     inv = torch.where(k2 > 0, 1.0 / k2.clamp_min(1e-300), torch.zeros_like(k2))
     pos = lattice(n, box, device)
+    disp = torch.empty_like(pos) if displacement else None
     for d, kd in enumerate((kx, ky, kz)):
         psi = torch.fft.irfftn(1j * kd * inv * dk, s=(n, n, n)).reshape(-1)
         pos[:, d] += psi
+        if displacement:
+            disp[:, d] = psi
         del psi
-    return torch.remainder(pos, box)
+    pos = torch.remainder(pos, box)
+    return (pos, disp) if displacement else pos
 
 
 def _directions(m: int, g: torch.Generator) -> torch.Tensor:
@@ -170,6 +175,28 @@ def clustered_load(n: int, box: float = 100.0, rms: float = 1.0, seed: int = 1,
     if n_halos:
         pos = add_halos(pos, box, n_halos, m_lo, m_hi, omega_m, seed, profile)
     return to_f32(pos, box).cpu() if str(device) == "cpu" else to_f32(pos, box)
+
+
+def initial_conditions(n: int, box: float, rms: float, seed: int, a: float, omega_m: float = 0.3,
+                       omega_l: float = 0.7, n_halos: int = 0, profile: str = "plummer", device="cpu"):
+    """Positions and momenta (float32 [n^3, 3] each) for a chain of time steps:
+    the Zel'dovich load of :func:`clustered_load` at scale factor ``a`` with the
+    linear-theory momentum p = a^2 dx/dt = a^2 H(a) f(a) psi, f = Omega_m(a)^0.55
+    (H in km/s per Mpc/h, so p is in km/s); particles relocated into halos start
+    at rest."""
+    pos, disp = zeldovich(n, box, rms, seed, device=device, displacement=True)
+    hub = 100.0 * math.sqrt(omega_m / a ** 3 + omega_l)
+    om_a = omega_m / a ** 3 / (omega_m / a ** 3 + omega_l)
+    mom = disp * (a * a * hub * om_a ** 0.55)
+    del disp
+    if n_halos:
+        moved = add_halos(pos, box, n_halos, 1e13, 1e15, omega_m, seed, profile)
+        mom[(moved != pos).any(dim=1)] = 0.0
+        pos = moved
+    pos32, mom32 = to_f32(pos, box), mom.to(torch.float32).contiguous()
+    if str(device) == "cpu":
+        return pos32.cpu(), mom32.cpu()
+    return pos32, mom32
 
 
 # -- simple density fields (delta on an N^3 mesh, C order, float64 numpy) -------------

@@ -417,6 +417,15 @@ int mgfr_amr_set_relaxation32(mgfr_amr *amr, double omega);
  * Returns the worst level status (MGFR_NOT_CONVERGED if a level hit
  * max_vcycles); MGFR_ERR_ARG if a level needs more than max_blocks blocks. */
 int mgfr_amr_solve(mgfr_amr *amr, const float *pos, int64_t np, double *u0, mgfr_stats *st);
+/* Composite fields of the last solve on the uniform mesh of the finest level,
+ * side N0 2^refine_levels (the paper's power-spectrum comparison of adaptive
+ * and fixed meshes, Sec. 5.1, needs the adaptive solution on one grid):
+ * every cell takes delta and the effective density of Sec. 3.4,
+ * delta_eff = delta/3 - C(a) expm1(-u/(n+1)) / (3 Omega_m a^-3), of the finest
+ * level covering it, so a coarser leaf's values fill its sub-cells (its mass
+ * spread over its volume).  delta, delta_eff: device float64 arrays of that
+ * size.  Feed them to mgfr_power_ratio of a context of that mesh. */
+int mgfr_amr_composite(mgfr_amr *amr, double *delta, double *delta_eff);
 /* Blocks of level l (1..refine_levels) after the last solve, -1 on error. */
 int64_t mgfr_amr_num_blocks(const mgfr_amr *amr, int level);
 /* origins: HOST int32 [nblocks][3] block origins in level cells (multiples of 8);

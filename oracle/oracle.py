@@ -448,3 +448,38 @@ def pm_step(p, pos, mom, acc, a1, u):
     acc1 = pm_accel(p, delta, u1, pos).astype(np.float32)
     kick_drift(pos, mom, acc1, K2, 0.0, p.box)
     return delta, u1, acc1, st
+
+
+def amr_levels(p, nref, pos):
+    """The adaptive solve step by step (flags, composite masses, delta_l =
+    m_l / (total / N_l^3) - 1, field-driven solve): returns
+    (status, blk, [delta_l], [u_l], [mask_l], [stats_l])."""
+    blk = amr_flags(p, nref, pos)
+    ms = amr_cic(p, nref, blk, pos)
+    total = ms[0].sum()
+    deltas = [m / (total / m.size) - 1.0 for m in ms]
+    s, us, masks, st = amr_solve_fields(p, nref, blk, deltas)
+    return s, blk, deltas, us, masks, st
+
+
+def amr_composite(p, deltas, us, masks):
+    """delta and the effective density (Sec. 3.4) of the finest level covering
+    each cell, on the finest level's uniform mesh (a coarser leaf's value fills
+    its sub-cells)."""
+    fb, beta, C = background(p)
+    om = p.omega_m / p.a ** 3
+    q = 1.0 / (p.n + 1)
+    L = len(deltas) - 1
+    Nf = deltas[L].shape[0]
+    d = np.empty((Nf,) * 3)
+    u = np.empty((Nf,) * 3)
+    have = np.zeros((Nf,) * 3, bool)
+    for l in range(L, -1, -1):
+        r = 1 << (L - l)
+        up = lambda a: np.repeat(np.repeat(np.repeat(a, r, 0), r, 1), r, 2)
+        m = up(masks[l].astype(bool)) & ~have
+        d[m] = up(deltas[l])[m]
+        u[m] = up(us[l])[m]
+        have |= m
+    assert have.all()
+    return d, d / 3.0 - C * np.expm1(-q * u) / (3.0 * om)

@@ -833,6 +833,52 @@ __global__ void k_amr_copy_out(LevelDev L, double *__restrict__ out)
     }
 }
 
+// Composite fields on the uniform mesh of the finest level (side 2^lgf): every
+// cell takes delta and the effective density of the finest level covering it
+// (a coarse leaf's value fills all its sub-cells: its mass spread over its
+// volume).  delta_l = f_l / s on the refined levels (f_l = s delta_l is the
+// level's source), delta_0 on the base;
+// delta_eff = delta / 3 - C expm1(-q u) / (3 Omega_m a^-3)  (Sec. 3.4).
+struct CompArgs {
+    int nref, lgf;
+    const double *d0, *u0;
+    int lg0;
+    const int *map[kMaxRef + 1];
+    const double *u[kMaxRef + 1], *f[kMaxRef + 1];
+    double inv_s, third_C_om, q;
+    double *dout, *eout;
+};
+
+__global__ void k_amr_composite(CompArgs A)
+{
+    const size_t n = (size_t)1 << (3 * A.lgf);
+    const int mf = (1 << A.lgf) - 1;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(t & mf), j = (int)((t >> A.lgf) & mf), i = (int)(t >> (2 * A.lgf));
+        double d = 0.0, u = 0.0;
+        bool found = false;
+        for (int l = A.nref; l >= 1 && !found; --l) {
+            const int sh = A.nref - l, lg = A.lg0 + l, M = 1 << (lg - 3);
+            const int a = i >> sh, b = j >> sh, c = k >> sh;
+            const int blk = A.map[l][((size_t)(a >> 3) * M + (b >> 3)) * M + (c >> 3)];
+            if (blk >= 0) {
+                const size_t o = (size_t)blk * sub_vol(0) + pidx(0, a & 7, b & 7, c & 7);
+                d = A.f[l][o] * A.inv_s;
+                u = A.u[l][o];
+                found = true;
+            }
+        }
+        if (!found) {
+            const int sh = A.nref;
+            const size_t o = cidx(i >> sh, j >> sh, k >> sh, A.lg0);
+            d = A.d0[o];
+            u = A.u0[o];
+        }
+        A.dout[t] = d;
+        A.eout[t] = d / 3.0 - A.third_C_om * expm1(-A.q * u);
+    }
+}
+
 inline unsigned grid_of(size_t n, unsigned cap = 65535) { return (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, cap)); }
 
 }  // namespace
@@ -1324,6 +1370,33 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
     if (st_levels)
         for (int l = 0; l <= A->nref; ++l) st_levels[l] = A->st[l];
     return worst;
+}
+
+extern "C" int mgfr_amr_composite(mgfr_amr *A, double *delta, double *delta_eff)
+{
+    if (!A || !delta || !delta_eff) return set_error(MGFR_ERR_ARG, "amr, delta and delta_eff must be non-NULL");
+    CompArgs C{};
+    C.nref = A->nref;
+    C.lg0 = A->lg0;
+    C.lgf = A->lg0 + A->nref;
+    C.d0 = A->delta0;
+    C.u0 = A->u0;
+    for (int l = 1; l <= A->nref; ++l) {
+        C.map[l] = A->map[l];
+        C.u[l] = A->arr[l][0][0];
+        C.f[l] = A->arr[l][1][0];
+    }
+    const double a3 = 1.0 / (A->p.a * A->p.a * A->p.a);
+    C.inv_s = 1.0 / (A->beta * A->p.omega_m * a3);
+    C.third_C_om = A->C / (3.0 * A->p.omega_m * a3);
+    C.q = 1.0 / (A->p.n + 1);
+    C.dout = delta;
+    C.eout = delta_eff;
+    const size_t n = (size_t)1 << (3 * C.lgf);
+    k_amr_composite<<<grid_of(n, 16384), 256, 0, A->stream>>>(C);
+    MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipStreamSynchronize(A->stream));
+    return MGFR_OK;
 }
 
 extern "C" int64_t mgfr_amr_num_blocks(const mgfr_amr *A, int level)

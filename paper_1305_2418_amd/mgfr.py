@@ -166,6 +166,7 @@ def lib() -> C.CDLL:
         L.mgfr_amr_num_blocks.argtypes = [_VP, C.c_int]
         L.mgfr_amr_num_blocks.restype = C.c_int64
         L.mgfr_amr_get_level.argtypes = [_VP, C.c_int, _VP, _VP]
+        L.mgfr_amr_composite.argtypes = [_VP, _VP, _VP]
         _lib = L
     return _lib
 
@@ -591,6 +592,14 @@ class Amr:
         rc = lib().mgfr_amr_solve(self._h, pos.data_ptr(), npart, u0.data_ptr(), sts)
         _check(rc, allow_not_converged=allow_not_converged)
         return u0, [Stats.from_c(sts[i]) for i in range(nl)]
+
+    def composite(self):
+        """(delta, delta_eff) of the last solve on the finest level's uniform mesh."""
+        Nf = self.params.mesh << self.params.refine_levels
+        d = torch.empty((Nf, Nf, Nf), dtype=torch.float64, device="cuda")
+        e = torch.empty_like(d)
+        _check(lib().mgfr_amr_composite(self._h, d.data_ptr(), e.data_ptr()))
+        return d, e
 
     def level(self, l: int):
         """(origins int32 [nb, 3] numpy, u float64 [nb, 8, 8, 8] tensor) of refined level l."""

@@ -226,3 +226,32 @@ def test_config4_full_size_sampled_residual():
         worst = np.abs(r).max() / st[l].scale
         print(f"  level {l}: {len(sel)} cells, max |f - L(u)| / D = {worst:.2e} (solve: {st[l].res:.2e})")
         assert worst <= 1.01e-8
+
+
+@pytest.mark.parametrize("fr0", [1e-6, 1e-5])
+def test_composite_spectrum_matches_oracle(fr0):
+    """The adaptive solution on one grid (Sec. 5.1's comparison of adaptive and
+    fixed meshes): composite delta and effective density of the library against
+    the oracle's composite cell by cell, and the ratio P(delta + delta_eff) /
+    P(delta) of the library's shell spectra against numpy's."""
+    from paper_1305_2418_amd import mgfr
+    N0, nref = 32, 2
+    print(f"[case] composite spectrum fr0={fr0}", flush=True)
+    pos = synth.clustered_load(N0, 100.0, rms=5.0, seed=4, n_halos=50, profile="nfw")
+    p = O.params(mesh=N0, fr0_abs=fr0)
+    s_o, blk, ds, us, ms, sts = O.amr_levels(p, nref, pos.numpy())
+    assert s_o == 0
+    d_o, e_o = O.amr_composite(p, ds, us, ms)
+    amr = mgfr.Amr(mgfr.Params(mesh=N0, fr0_abs=fr0, refine_levels=nref), max_blocks=20000)
+    amr.solve(pos.to(DEV))
+    d, e = amr.composite()
+    d, e = d.cpu().numpy(), e.cpu().numpy()
+    assert np.abs(d - d_o).max() <= 1e-12 * np.abs(d_o).max()
+    assert np.abs(e - e_o).max() <= 1e-9 * np.abs(d_o).max()
+    Nf = N0 << nref
+    k_o, r_o, pd_o, c_o = O.power_ratio(100.0, d_o, e_o, Nf // 2)
+    ctx = mgfr.Solver(mgfr.Params(mesh=Nf))
+    k, r, pd, c = ctx.power_ratio(torch.tensor(d, device=DEV), torch.tensor(e, device=DEV))
+    print(f"  ratio at k_1 {r[0]:.4f}, k_8 {r[7]:.4f}, k_32 {r[31]:.4f}")
+    assert np.array_equal(c, c_o)
+    assert np.allclose(r, r_o, rtol=1e-8) and np.allclose(pd, pd_o, rtol=1e-9)

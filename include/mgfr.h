@@ -349,6 +349,19 @@ int mgfr_net_load(mgfr_net *net, const char *path);
 /* u = network(delta) for B volumes of side S (power of two, 32 <= S <= 1024).
  * delta, u: float64 [B][S^3]; cond: HOST float64 [B][2] = (a, |f_R0|) per volume. */
 int mgfr_net_predict(mgfr_net *net, const double *delta, int B, int S, const double *cond, double *u);
+/* Copy one intermediate tensor of the last forward pass (predict, train_step
+ * or grads) into the DEVICE buffer dst of exactly `count` elements, on the
+ * network's stream, synchronised before return.  index, in forward order
+ * (channels; side for an input of side S):
+ *    0 features x0 (16; S)        1 conv1a (16; S)    2 conv1b = skip 1 (16; S)
+ *    3 pool (16; S/2)             4 conv2a (32; S/2)  5 conv2b = skip 2 (32; S/2)
+ *    6 pool (32; S/4)             7 conv3a (64; S/4)  8 conv3b (64; S/4)
+ *    9 up + skip 2 (96; S/2)     10 conv4a (32; S/2) 11 conv4b (32; S/2)
+ *   12 up + skip 1 (48; S)       13 conv5a (16; S)   14 conv5b (16; S)
+ *   15 head output y = u / 5 (float32 [B][S^3]).
+ * Indices 0-14 are bf16 channels-last tensors.  MGFR_ERR_ARG for an index out
+ * of range, a count that is not the tensor's size, or no forward pass yet. */
+int mgfr_net_activation(mgfr_net *net, int index, void *dst, int64_t count);
 /* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error
  * between the network output and u_target / 5; *loss (host, nullable) gets the loss
  * before the step.  Returns MGFR_ERR_NONFINITE if the loss is not finite. */

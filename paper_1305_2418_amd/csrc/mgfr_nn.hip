@@ -527,6 +527,7 @@ struct mgfr_net {
     __bf16 *wbf = nullptr;   // bf16 copy of every parameter (conv weights used in [t][o][c] layout)
     __bf16 *wt = nullptr;    // transposed, mirrored conv weights for backward-data (same offsets)
     int step = 0;
+    int fwd_B = 0, fwd_lg = 0;  // shape of the last forward pass (0: none yet)
     // activations
     __bf16 *x0, *h1a, *s1, *p1, *h2a, *s2, *p2, *h3a, *h3, *cat4, *h4a, *h4, *cat5, *h5a, *h5;
     float *y32, *dy32, *cond, *loss;
@@ -632,6 +633,8 @@ int net_forward(mgfr_net *n, const double *delta, int B, int lgS)
 {
     const size_t V = (size_t)B << (3 * lgS), V2 = V / 8, V3 = V / 64;
     int rc;
+    n->fwd_B = B;
+    n->fwd_lg = lgS;
     MGFR_HIP(hipMemcpyAsync(n->cond, n->hcond, 2 * B * sizeof(float), hipMemcpyHostToDevice, n->stream));
     k_features<<<gridn(V), 256, 0, n->stream>>>(delta, V, lgS, n->cond, n->x0);
     if ((rc = conv(n, n->x0, V, lgS, 0, true, n->h1a)) || (rc = conv(n, n->h1a, V, lgS, 1, true, n->s1))) return rc;
@@ -851,6 +854,26 @@ extern "C" int mgfr_net_predict(mgfr_net *n, const double *delta, int B, int S, 
     const size_t V = (size_t)B << (3 * lgS);
     k_to_u<<<gridn(V), 256, 0, n->stream>>>(n->y32, V, u);
     MGFR_HIP(hipGetLastError());
+    MGFR_HIP(hipStreamSynchronize(n->stream));
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_net_activation(mgfr_net *n, int index, void *dst, int64_t count)
+{
+    if (!n || !dst) return set_error(MGFR_ERR_ARG, "net and dst must be non-NULL");
+    if (index < 0 || index > 15) return set_error(MGFR_ERR_ARG, "activation index must be in [0, 15]");
+    if (n->fwd_B == 0) return set_error(MGFR_ERR_ARG, "no forward pass has run on this network yet");
+    // buffer, channels and pooling depth (0: S^3, 1: (S/2)^3, 2: (S/4)^3) in forward order
+    const __bf16 *buf[15] = {n->x0, n->h1a, n->s1, n->p1, n->h2a, n->s2, n->p2, n->h3a,
+                             n->h3, n->cat4, n->h4a, n->h4, n->cat5, n->h5a, n->h5};
+    static const int ch[16] = {16, 16, 16, 16, 32, 32, 32, 64, 64, 96, 32, 32, 48, 16, 16, 1};
+    static const int depth[16] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 1, 1, 0, 0, 0, 0};
+    const size_t vox = ((size_t)n->fwd_B << (3 * n->fwd_lg)) >> (3 * depth[index]);
+    const size_t elems = vox * ch[index];
+    if (count != (int64_t)elems) return set_error(MGFR_ERR_ARG, "count does not match the activation's size");
+    const void *src = index == 15 ? (const void *)n->y32 : (const void *)buf[index];
+    const size_t esz = index == 15 ? sizeof(float) : sizeof(__bf16);
+    MGFR_HIP(hipMemcpyAsync(dst, src, elems * esz, hipMemcpyDeviceToDevice, n->stream));
     MGFR_HIP(hipStreamSynchronize(n->stream));
     return MGFR_OK;
 }

@@ -151,6 +151,7 @@ def lib() -> C.CDLL:
         L.mgfr_net_save.argtypes = [_VP, C.c_char_p]
         L.mgfr_net_load.argtypes = [_VP, C.c_char_p]
         L.mgfr_net_predict.argtypes = [_VP, _VP, C.c_int, C.c_int, _VP, _VP]
+        L.mgfr_net_activation.argtypes = [_VP, C.c_int, _VP, C.c_int64]
         L.mgfr_net_train_step.argtypes = [_VP, _VP, _VP, C.c_int, C.c_int, _VP, C.c_float,
                                           C.POINTER(C.c_float)]
         L.mgfr_net_grads.argtypes = [_VP, _VP, _VP, C.c_int, C.c_int, _VP, C.POINTER(C.c_float), _VP]
@@ -442,6 +443,7 @@ class Net:
         _check(lib().mgfr_net_create(int(seed), int(max_voxels), s, C.byref(h)))
         self._h = h
         self.max_voxels = max_voxels
+        self._last = None  # (B, S, device) of the last predict()
 
     def close(self):
         if getattr(self, "_h", None):
@@ -491,7 +493,27 @@ class Net:
         if arr.shape[0] != B:
             raise ValueError("cond must have one (a, |f_R0|) row per volume")
         _check(lib().mgfr_net_predict(self._h, delta.data_ptr(), B, S, cp, u.data_ptr()))
+        self._last = (B, S, delta.device)
         return u
+
+    # (channels, pooling depth) of the tensors mgfr_net_activation exports, in forward order
+    ACTIVATIONS = ((16, 0), (16, 0), (16, 0), (16, 1), (32, 1), (32, 1), (32, 2), (64, 2), (64, 2),
+                   (96, 1), (32, 1), (32, 1), (48, 0), (16, 0), (16, 0), (1, 0))
+
+    def activation(self, index: int) -> torch.Tensor:
+        """Tensor `index` of the last predict(): bf16 [B, s, s, s, C] for 0-14, the head's
+        float32 output [B, S, S, S] for 15."""
+        if self._last is None:
+            raise MgfrError(MGFR_ERR_ARG, "no predict() has run on this network yet")
+        B, S, dev = self._last
+        ch, depth = self.ACTIVATIONS[index]
+        s = S >> depth
+        if index == 15:
+            out = torch.empty((B, S, S, S), dtype=torch.float32, device=dev)
+        else:
+            out = torch.empty((B, s, s, s, ch), dtype=torch.bfloat16, device=dev)
+        _check(lib().mgfr_net_activation(self._h, int(index), out.data_ptr(), out.numel()))
+        return out
 
     def train_step(self, delta: torch.Tensor, u_target: torch.Tensor, cond, lr: float) -> float:
         self._sync()

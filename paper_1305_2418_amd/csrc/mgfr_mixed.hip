@@ -254,6 +254,11 @@ __device__ __forceinline__ T &at_off(float *base, uint32_t byte_off)
 #define MGFR_CTJ 8
 #endif
 constexpr int CTJ = MGFR_CTJ;  // updated rows per workgroup (the last row tile may be partial)
+#ifndef MGFR_COLOUR_PF
+#define MGFR_COLOUR_PF 3
+#endif
+constexpr int kColourPf = MGFR_COLOUR_PF;  // planes between a raw load and its use (1, 2 or 3)
+static_assert(kColourPf >= 1 && kColourPf <= 3, "prefetch distance 1, 2 or 3");
 #ifndef MGFR_CHUNKS
 #define MGFR_CHUNKS 8
 #endif
@@ -365,7 +370,7 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         prev = S0 ? mx_cell(um.y, em.y) : mx_cell(um.x, em.x);
     }
     // raw loads of step p: u, e of plane p + 1, r of plane p, the k-halo cell of plane p.
-    // They are issued two steps ahead; four register sets rotate with the
+    // They are issued kColourPf steps ahead; four register sets rotate with the
     // four-plane loop body, so that no register holding a load in flight is copied.
     struct Raw {
         float2 u, e;
@@ -380,14 +385,14 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         w.khe = A.e[kh_e(p)];
         return w;
     };
-    Raw ra = load(i0), rb = load(i0 + 1), rc, rd;
+    Raw ra = load(i0), rb = kColourPf >= 2 ? load(i0 + 1) : Raw{}, rc = kColourPf == 3 ? load(i0 + 2) : Raw{}, rd;
     int buf = 0;
 
-    // one plane with updated column S: consume cur (step p), load nxt (step p + 2)
+    // one plane with updated column S: consume cur (step p), load nxt (step p + kColourPf)
     auto step = [&](int p, auto Sc, const Raw &cur, Raw &nxt) {
         constexpr int S = decltype(Sc)::value;
-        nxt = load(p + 2);
-        // plane p + 1 from the raw values loaded two planes ago
+        nxt = load(p + kColourPf);
+        // plane p + 1 from the raw values loaded kColourPf planes ago
         const Cell4 n0 = mx_cell(cur.u.x, cur.e.x), n1 = mx_cell(cur.u.y, cur.e.y);
         float4 *B = sB + buf * (CTJ + 2) * CLW;
         B[(row + 1) * CLW + lane + 1] = pack(S ? c0 : c1);
@@ -408,11 +413,25 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
     };
     using Z0 = std::integral_constant<int, S0>;
     using Z1 = std::integral_constant<int, 1 - S0>;
-    for (int p = i0; p < i0 + A.chunk; p += 4) {  // chunk is a multiple of 4
-        step(p, Z0{}, ra, rc);
-        step(p + 1, Z1{}, rb, rd);
-        step(p + 2, Z0{}, rc, ra);
-        step(p + 3, Z1{}, rd, rb);
+    if constexpr (kColourPf == 3) {
+        for (int p = i0; p < i0 + A.chunk; p += 4) {  // chunk is a multiple of 4
+            step(p, Z0{}, ra, rd);
+            step(p + 1, Z1{}, rb, ra);
+            step(p + 2, Z0{}, rc, rb);
+            step(p + 3, Z1{}, rd, rc);
+        }
+    } else if constexpr (kColourPf == 2) {
+        for (int p = i0; p < i0 + A.chunk; p += 4) {
+            step(p, Z0{}, ra, rc);
+            step(p + 1, Z1{}, rb, rd);
+            step(p + 2, Z0{}, rc, ra);
+            step(p + 3, Z1{}, rd, rb);
+        }
+    } else {
+        for (int p = i0; p < i0 + A.chunk; p += 2) {
+            step(p, Z0{}, ra, rb);
+            step(p + 1, Z1{}, rb, ra);
+        }
     }
 }
 

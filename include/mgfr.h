@@ -425,11 +425,23 @@ int mgfr_amr_set_relaxation32(mgfr_amr *amr, double omega);
 /* pos: float32 [np][3] (unit masses); u0: float64 [N0^3] output (base solution) or
  * NULL; st: HOST array of refine_levels + 1 stats (level 0 = base) or NULL.
  * Refinement flags are built on the device and only the block maps reach
- * the host; then one pass over the particles assigns the composite masses.
+ * the host; then the composite masses are assigned (binned when
+ * mgfr_amr_reserve_particles covers np).
  * A non-finite position (or one beyond 1e15 Mpc/h) gives MGFR_ERR_NONFINITE.
  * Returns the worst level status (MGFR_NOT_CONVERGED if a level hit
  * max_vcycles); MGFR_ERR_ARG if a level needs more than max_blocks blocks. */
 int mgfr_amr_solve(mgfr_amr *amr, const float *pos, int64_t np, double *u0, mgfr_stats *st);
+/* Workspace for the binned composite assignment (Sec. 3.1): four uint32
+ * arrays of max_np entries plus the radix sort's scratch, owned by the amr
+ * object (max_np = 0 frees it).  A solve with np <= max_np sorts the particles
+ * by the aligned 8^3 group of cells of their level holding their lower CIC
+ * corner, accumulates each run in an LDS window and adds the window to the
+ * level with one atomic per touched cell; the few particles whose cube
+ * overlaps leaves of several levels keep the per-particle path.  Without it
+ * (or for larger np) every particle adds its eight weights with global
+ * atomics.  Both give the same masses up to the order of the float64 sums.
+ * Errors: MGFR_ERR_ARG for max_np < 0 or > 2^31 - 1, MGFR_ERR_OOM. */
+int mgfr_amr_reserve_particles(mgfr_amr *amr, int64_t max_np);
 /* Composite fields of the last solve on the uniform mesh of the finest level,
  * side N0 2^refine_levels (the paper's power-spectrum comparison of adaptive
  * and fixed meshes, Sec. 5.1, needs the adaptive solution on one grid):

@@ -242,24 +242,48 @@ __device__ __forceinline__ void cic_add(const CicMaps &Q, int l, long long ii, l
 // When the cube's eight cells at that level are all leaves (the common case)
 // these are the usual weights (1 - t, t) per axis; otherwise the overlaps are
 // computed cell by cell over every level.
-__global__ void k_amr_cic_composite(const float *__restrict__ pos, int64_t np, CicMaps Q, int *__restrict__ flag)
+// finest level whose blocks contain position x (0: the base mesh)
+__device__ __forceinline__ int cic_level(const CicMaps &Q, const double x[3])
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const double x[3] = {(double)pos[3 * p + 0], (double)pos[3 * p + 1], (double)pos[3 * p + 2]};
-    // non-finite or absurdly distant positions (cell indices must fit 64 bits)
-    if (!(fabs(x[0]) < 1e15 && fabs(x[1]) < 1e15 && fabs(x[2]) < 1e15)) {
-        flag[0] = 1;
-        return;
-    }
-    int lp = 0;
     for (int l = Q.nref; l >= 1; --l) {
         const double h = Q.box / (double)(1 << (Q.lg0 + l));
-        if (cic_blk(Q, l, (long long)floor(x[0] / h), (long long)floor(x[1] / h), (long long)floor(x[2] / h)) >= 0) {
-            lp = l;
-            break;
-        }
+        if (cic_blk(Q, l, (long long)floor(x[0] / h), (long long)floor(x[1] / h), (long long)floor(x[2] / h)) >= 0)
+            return l;
     }
+    return 0;
+}
+
+// the eight CIC cells (i0..i0+1, ...) of level lp are all leaves
+__device__ __forceinline__ bool cic_all_leaf(const CicMaps &Q, int lp, int i0, int j0, int k0)
+{
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c)
+                if (!cic_leaf(Q, lp, i0 + a, j0 + b, k0 + c)) return false;
+    return true;
+}
+
+// position of particle p; false (and the flag set) if it is not finite or
+// absurdly distant (cell indices must fit 64 bits)
+__device__ __forceinline__ bool cic_position(const float *__restrict__ pos, int64_t p, double x[3],
+                                             int *__restrict__ flag)
+{
+    for (int d = 0; d < 3; ++d) x[d] = (double)pos[3 * p + d];
+    if (!(fabs(x[0]) < 1e15 && fabs(x[1]) < 1e15 && fabs(x[2]) < 1e15)) {
+        flag[0] = 1;
+        return false;
+    }
+    return true;
+}
+
+// The whole assignment of particle p with global atomics: the usual weights
+// when its eight cells at level lp are leaves, else the overlaps cell by cell
+// over every level.
+__device__ void cic_composite_one(const float *__restrict__ pos, int64_t p, const CicMaps &Q, int *__restrict__ flag)
+{
+    double x[3];
+    if (!cic_position(pos, p, x, flag)) return;
+    const int lp = cic_level(Q, x);
     const int lgp = Q.lg0 + lp, mask = (1 << lgp) - 1;
     const double s = Q.box / (double)(1 << lgp);
     int i0, j0, k0;
@@ -269,11 +293,7 @@ __global__ void k_amr_cic_composite(const float *__restrict__ pos, int64_t np, C
         flag[0] = 1;
         return;
     }
-    bool all_leaf = true;
-    for (int a = 0; a < 2 && all_leaf; ++a)
-        for (int b = 0; b < 2 && all_leaf; ++b)
-            for (int c = 0; c < 2 && all_leaf; ++c) all_leaf = cic_leaf(Q, lp, i0 + a, j0 + b, k0 + c);
-    if (all_leaf) {
+    if (cic_all_leaf(Q, lp, i0, j0, k0)) {
         const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
@@ -304,6 +324,150 @@ __global__ void k_amr_cic_composite(const float *__restrict__ pos, int64_t np, C
                     if (v > 0.0 && cic_leaf(Q, l, i, j, k)) cic_add(Q, l, i, j, k, v);
                 }
     }
+}
+
+__global__ void k_amr_cic_composite(const float *__restrict__ pos, int64_t np, CicMaps Q, int *__restrict__ flag)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < np) cic_composite_one(pos, p, Q, flag);
+}
+
+// Binned composite assignment.  Sort keys: a particle whose eight CIC cells
+// at its level lp are all leaves gets koff[lp] + the position of the aligned
+// 8^3 group of level-lp cells holding its lower corner (row-major over the
+// N_lp / 8 groups per axis); every other particle (a cube overlapping leaves
+// of several levels, a bad position) gets the largest key koff[nref + 1] and
+// takes the general path.
+struct CicKeys {
+    uint32_t koff[kMaxRef + 2];
+};
+
+__global__ __launch_bounds__(kBlock) void k_amr_cic_keys(const float *__restrict__ pos, int64_t np, CicMaps Q,
+                                                           CicKeys K, uint32_t *__restrict__ key,
+                                                           uint32_t *__restrict__ idx)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= np) return;
+    idx[p] = (uint32_t)p;
+    uint32_t k = K.koff[Q.nref + 1];
+    double x[3];
+    int dummy = 0;
+    if (cic_position(pos, p, x, &dummy)) {
+        const int lp = cic_level(Q, x);
+        const int lgp = Q.lg0 + lp, mask = (1 << lgp) - 1;
+        const double s = Q.box / (double)(1 << lgp);
+        int i0, j0, k0;
+        double t;
+        if (cic_axis(pos[3 * p + 0], s, mask, i0, t) && cic_axis(pos[3 * p + 1], s, mask, j0, t) &&
+            cic_axis(pos[3 * p + 2], s, mask, k0, t) && cic_all_leaf(Q, lp, i0, j0, k0)) {
+            const uint32_t gl = (uint32_t)(lgp - kBinLg);
+            k = K.koff[lp] + (((((uint32_t)i0 >> kBinLg) << gl) | ((uint32_t)j0 >> kBinLg)) << gl) +
+                ((uint32_t)k0 >> kBinLg);
+        }
+    }
+    key[p] = k;
+}
+
+// Workgroup b takes the sorted slots [b kCicChunk, (b + 1) kCicChunk) and
+// walks their runs of equal key as the uniform binned assignment does: each
+// run of a group of level-l cells is accumulated in a 9^3 LDS window (lower
+// corners in the group, upper corners one cell beyond, all leaves), whose
+// non-zero entries then go to the level's cells with float64 atomics (the
+// cells one beyond may belong to a neighbouring block).  The general-path
+// runs, last in the order, are left to k_amr_cic_general.
+__global__ __launch_bounds__(kBlock) void k_amr_cic_binned(const float *__restrict__ pos,
+                                                             const uint32_t *__restrict__ key_s,
+                                                             const uint32_t *__restrict__ perm, int64_t np,
+                                                             CicMaps Q, CicKeys K, int *__restrict__ flag)
+{
+    __shared__ double win[kWin3];
+    __shared__ int red[kBlock / 64];
+    const int tid = threadIdx.x;
+    const int64_t start = (int64_t)blockIdx.x * kCicChunk;
+    const int64_t end = start + kCicChunk < np ? start + kCicChunk : np;
+    const uint32_t ksent = K.koff[Q.nref + 1];
+    uint32_t key[kCicPer];
+    float px[kCicPer], py[kCicPer], pz[kCicPer];
+#pragma unroll
+    for (int s = 0; s < kCicPer; ++s) {
+        const int64_t i = start + tid + (int64_t)s * kBlock;
+        key[s] = 0xffffffffu;  // above every key
+        px[s] = py[s] = pz[s] = 0.0f;
+        if (i < end) {
+            key[s] = key_s[i];
+            const size_t p = perm[i];
+            px[s] = pos[3 * p + 0];
+            py[s] = pos[3 * p + 1];
+            pz[s] = pos[3 * p + 2];
+        }
+    }
+    for (int e = tid; e < kWin3; e += kBlock) win[e] = 0.0;
+    int64_t cur = start;
+    while (cur < end) {
+        const uint32_t t = key_s[cur];  // the same in every thread
+        if (t >= ksent) break;          // the rest of the chunk takes the general path
+        int cnt = 0;
+#pragma unroll
+        for (int s = 0; s < kCicPer; ++s) cnt += key[s] <= t ? 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = cnt;
+        __syncthreads();
+        int total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) total += red[w];
+        const int64_t rend = start + total > cur ? start + total : cur + 1;
+        int l = 0;
+        while (l < Q.nref && t >= K.koff[l + 1]) ++l;
+        const int lg = Q.lg0 + l, gl = lg - kBinLg, gmask = (1 << gl) - 1, mask = (1 << lg) - 1;
+        const uint32_t q = t - K.koff[l];
+        const int ti = (int)(q >> (2 * gl)) << kBinLg, tj = (int)((q >> gl) & gmask) << kBinLg,
+                  tk = (int)(q & gmask) << kBinLg;
+        const double h = Q.box / (double)(1 << lg);
+#pragma unroll
+        for (int s = 0; s < kCicPer; ++s) {
+            if (key[s] != t) continue;
+            int i0, j0, k0;
+            double tx, ty, tz;
+            const bool ok = cic_axis(px[s], h, mask, i0, tx) && cic_axis(py[s], h, mask, j0, ty) &&
+                            cic_axis(pz[s], h, mask, k0, tz);
+            const int a = i0 - ti, b = j0 - tj, c = k0 - tk;
+            if (!ok || (unsigned)a >= (1u << kBinLg) || (unsigned)b >= (1u << kBinLg) ||
+                (unsigned)c >= (1u << kBinLg)) {
+                flag[0] = 1;
+                continue;
+            }
+            const double wx0 = 1.0 - tx, wx1 = tx, wy0 = 1.0 - ty, wy1 = ty, wz0 = 1.0 - tz, wz1 = tz;
+            double *w0 = win + (a * kWin + b) * kWin + c;
+            atomicAdd(w0, wx0 * wy0 * wz0);
+            atomicAdd(w0 + 1, wx0 * wy0 * wz1);
+            atomicAdd(w0 + kWin, wx0 * wy1 * wz0);
+            atomicAdd(w0 + kWin + 1, wx0 * wy1 * wz1);
+            atomicAdd(w0 + kWin * kWin, wx1 * wy0 * wz0);
+            atomicAdd(w0 + kWin * kWin + 1, wx1 * wy0 * wz1);
+            atomicAdd(w0 + kWin * kWin + kWin, wx1 * wy1 * wz0);
+            atomicAdd(w0 + kWin * kWin + kWin + 1, wx1 * wy1 * wz1);
+        }
+        __syncthreads();
+        for (int e = tid; e < kWin3; e += kBlock) {
+            const double v = win[e];
+            if (v != 0.0) {
+                const int a = e / (kWin * kWin), b = (e / kWin) % kWin, c = e % kWin;
+                cic_add(Q, l, ti + a, tj + b, tk + c, v);
+                win[e] = 0.0;
+            }
+        }
+        __syncthreads();
+        cur = rend;
+    }
+}
+
+// the particles of the general path (largest key, sorted last)
+__global__ void k_amr_cic_general(const float *__restrict__ pos, const uint32_t *__restrict__ key_s,
+                                  const uint32_t *__restrict__ perm, int64_t np, CicMaps Q, uint32_t ksent,
+                                  int *__restrict__ flag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+        if (key_s[i] == ksent) cic_composite_one(pos, (int64_t)perm[i], Q, flag);
 }
 
 // Masses of the level-l cells covered by level-(l+1) blocks: the sum of their
@@ -910,6 +1074,11 @@ struct mgfr_amr {
     mgfr_stats st[kMaxRef + 1];
     double beta = 0, C = 0, fbar = 0;
     double omega32 = 1.0;  // relaxation factor of the refined levels' float32 correction sweeps
+    // binned composite assignment (mgfr_amr_reserve_particles): sort keys, indices, workspace
+    uint32_t *bkey = nullptr, *bkey_s = nullptr, *bidx = nullptr, *perm = nullptr;
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    int64_t bin_cap = 0;
 };
 
 namespace {
@@ -947,6 +1116,42 @@ Composite composite(const mgfr_amr *A, int nsolved)
     return C;
 }
 
+void amr_bin_free(mgfr_amr *A)
+{
+    (void)hipFree(A->bkey);
+    (void)hipFree(A->bkey_s);
+    (void)hipFree(A->bidx);
+    (void)hipFree(A->perm);
+    (void)hipFree(A->sort_tmp);
+    A->bkey = A->bkey_s = A->bidx = A->perm = nullptr;
+    A->sort_tmp = nullptr;
+    A->sort_tmp_bytes = 0;
+    A->bin_cap = 0;
+}
+
+// key offsets of the binned assignment: level l's groups of 8^3 cells follow
+// those of the coarser levels; the last entry is the general path's key
+CicKeys cic_keys(const mgfr_amr *A)
+{
+    CicKeys K{};
+    uint32_t off = 0;
+    for (int l = 0; l <= A->nref; ++l) {
+        K.koff[l] = off;
+        const uint32_t g = (uint32_t)1 << (A->lg0 + l - kBinLg);
+        off += g * g * g;
+    }
+    K.koff[A->nref + 1] = off;
+    return K;
+}
+
+unsigned cic_key_bits(const mgfr_amr *A)
+{
+    const uint32_t top = cic_keys(A).koff[A->nref + 1];
+    unsigned b = 1;
+    while (b < 32 && (top >> b) != 0) ++b;
+    return b;
+}
+
 void amr_free(mgfr_amr *A)
 {
     if (!A) return;
@@ -959,6 +1164,7 @@ void amr_free(mgfr_amr *A)
     (void)hipFree(A->partial);
     (void)hipFree(A->dscal);
     (void)hipFree(A->dflag);
+    amr_bin_free(A);
     if (A->hscal) (void)hipHostFree(A->hscal);
     for (int l = 1; l <= kMaxRef; ++l) {
         (void)hipFree(A->map[l]);
@@ -1334,7 +1540,23 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
             MGFR_HIP(hipMemsetAsync(A->arr[l][1][0], 0, (size_t)A->nb[l] * sub_vol(0) * sizeof(double), A->stream));
     }
     MGFR_HIP(hipMemsetAsync(A->dflag, 0, sizeof(int), A->stream));
-    k_amr_cic_composite<<<pg, 256, 0, A->stream>>>(pos, np, Q, A->dflag);
+    if (np <= A->bin_cap) {
+        // binned: particles sorted by the group of cells they deposit into, one
+        // LDS window per run; the few cubes across levels take the general path
+        const CicKeys K = cic_keys(A);
+        k_amr_cic_keys<<<(unsigned)((np + kBlock - 1) / kBlock), kBlock, 0, A->stream>>>(pos, np, Q, K, A->bkey,
+                                                                                       A->bidx);
+        MGFR_HIP(hipGetLastError());
+        size_t tmp = A->sort_tmp_bytes;
+        MGFR_HIP(sort_pairs_u32(A->sort_tmp, &tmp, A->bkey, A->bkey_s, A->bidx, A->perm, (size_t)np, cic_key_bits(A),
+                                A->stream));
+        k_amr_cic_binned<<<(unsigned)((np + kCicChunk - 1) / kCicChunk), kBlock, 0, A->stream>>>(
+            pos, A->bkey_s, A->perm, np, Q, K, A->dflag);
+        k_amr_cic_general<<<(unsigned)std::min<int64_t>((np + 255) / 256, 8192), 256, 0, A->stream>>>(
+            pos, A->bkey_s, A->perm, np, Q, K.koff[A->nref + 1], A->dflag);
+    } else {
+        k_amr_cic_composite<<<pg, 256, 0, A->stream>>>(pos, np, Q, A->dflag);
+    }
     for (int l = A->nref - 1; l >= 0; --l)
         if (A->nb[l + 1])
             k_amr_mass_up<<<grid_of((size_t)A->nb[l + 1] * 64), 256, 0, A->stream>>>(Q, l, A->nb[l + 1],
@@ -1370,6 +1592,30 @@ extern "C" int mgfr_amr_solve(mgfr_amr *A, const float *pos, int64_t np, double 
     if (st_levels)
         for (int l = 0; l <= A->nref; ++l) st_levels[l] = A->st[l];
     return worst;
+}
+
+extern "C" int mgfr_amr_reserve_particles(mgfr_amr *A, int64_t max_np)
+{
+    if (!A) return set_error(MGFR_ERR_ARG, "amr is NULL");
+    if (max_np < 0) return set_error(MGFR_ERR_ARG, "max_np must be >= 0");
+    if (max_np > (int64_t)0x7fffffff) return set_error(MGFR_ERR_ARG, "binning holds at most 2^31 - 1 particles");
+    MGFR_HIP(hipStreamSynchronize(A->stream));
+    amr_bin_free(A);
+    if (max_np == 0) return MGFR_OK;
+    size_t tmp = 0;
+    MGFR_HIP(sort_pairs_u32(nullptr, &tmp, nullptr, nullptr, nullptr, nullptr, (size_t)max_np, cic_key_bits(A),
+                            A->stream));
+    const size_t b = (size_t)max_np * sizeof(uint32_t);
+    if (hipMalloc(&A->bkey, b) != hipSuccess || hipMalloc(&A->bkey_s, b) != hipSuccess ||
+        hipMalloc(&A->bidx, b) != hipSuccess || hipMalloc(&A->perm, b) != hipSuccess ||
+        hipMalloc(&A->sort_tmp, std::max<size_t>(tmp, 256)) != hipSuccess) {
+        (void)hipGetLastError();
+        amr_bin_free(A);
+        return set_error(MGFR_ERR_OOM, "binning workspace for %lld particles", (long long)max_np);
+    }
+    A->sort_tmp_bytes = std::max<size_t>(tmp, 256);
+    A->bin_cap = max_np;
+    return MGFR_OK;
 }
 
 extern "C" int mgfr_amr_composite(mgfr_amr *A, double *delta, double *delta_eff)

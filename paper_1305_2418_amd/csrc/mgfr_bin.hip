@@ -77,6 +77,12 @@ int bin_reserve(mgfr_ctx *c, int64_t np)
     return MGFR_OK;
 }
 
+hipError_t sort_pairs_u32(void *tmp, size_t *tmp_bytes, const uint32_t *kin, uint32_t *kout, const uint32_t *vin,
+                          uint32_t *vout, size_t n, unsigned bits, hipStream_t stream)
+{
+    return rocprim::radix_sort_pairs(tmp, *tmp_bytes, kin, kout, vin, vout, n, 0u, bits, stream);
+}
+
 int bin_particles(mgfr_ctx *c, const float *pos, int64_t np)
 {
     c->perm_np = 0;

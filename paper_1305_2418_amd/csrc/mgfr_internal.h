@@ -121,9 +121,17 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D);
 
 // particle binning (mgfr_bin.hip)
 constexpr int kBinLg = 3;  // tile edge 2^kBinLg cells
+constexpr int kCicPer = 8;                        // particles per thread and workgroup chunk of a binned assignment
+constexpr int kCicChunk = kBlock * kCicPer;
+constexpr int kWin = (1 << kBinLg) + 1;           // LDS window edge: a tile plus one cell
+constexpr int kWin3 = kWin * kWin * kWin;
 int bin_reserve(mgfr_ctx *c, int64_t np);
 int bin_particles(mgfr_ctx *c, const float *pos, int64_t np);  // keys + sort; sets perm_np
 void bin_free(mgfr_ctx *c);
+// Stable radix sort of (key, value) uint32 pairs on the low `bits` key bits.
+// With tmp == nullptr only *tmp_bytes is set (the workspace the sort needs).
+hipError_t sort_pairs_u32(void *tmp, size_t *tmp_bytes, const uint32_t *kin, uint32_t *kout, const uint32_t *vin,
+                          uint32_t *vout, size_t n, unsigned bits, hipStream_t stream);
 
 // Cloud-in-cell weights along one axis: xi = x/h - 1/2, i0 = floor(xi), t = xi - i0,
 // weights (1 - t, t) on cells (i0, i0 + 1) mod N.  Returns false for positions

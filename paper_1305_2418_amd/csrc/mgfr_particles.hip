@@ -43,11 +43,6 @@ __global__ __launch_bounds__(kBlock) void k_cic_scatter(const float *__restrict_
             }
 }
 
-constexpr int kCicPer = 8;                        // particles per thread and workgroup chunk
-constexpr int kCicChunk = kBlock * kCicPer;
-constexpr int kWin = (1 << kBinLg) + 1;           // LDS window edge: a tile plus one cell
-constexpr int kWin3 = kWin * kWin * kWin;
-
 // Cloud-in-cell assignment of binned particles.  Workgroup b takes the
 // sorted slots [b kCicChunk, (b + 1) kCicChunk); its slots split into runs of
 // equal tile key.  Each run is accumulated in a 9^3 LDS window (lower corners

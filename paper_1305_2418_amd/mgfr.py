@@ -164,6 +164,7 @@ def lib() -> C.CDLL:
         L.mgfr_amr_destroy.restype = None
         L.mgfr_amr_set_relaxation32.argtypes = [_VP, C.c_double]
         L.mgfr_amr_solve.argtypes = [_VP, _VP, C.c_int64, _VP, _VP]
+        L.mgfr_amr_reserve_particles.argtypes = [_VP, C.c_int64]
         L.mgfr_amr_num_blocks.argtypes = [_VP, C.c_int]
         L.mgfr_amr_num_blocks.restype = C.c_int64
         L.mgfr_amr_get_level.argtypes = [_VP, C.c_int, _VP, _VP]
@@ -602,6 +603,10 @@ class Amr:
     def set_relaxation32(self, omega: float):
         """Over-relaxation factor of the float32 correction sweeps (base and refined levels)."""
         _check(lib().mgfr_amr_set_relaxation32(self._h, float(omega)))
+
+    def reserve_particles(self, max_np: int):
+        """Workspace for the binned composite assignment of up to max_np particles (0 frees it)."""
+        _check(lib().mgfr_amr_reserve_particles(self._h, int(max_np)))
 
     def solve(self, pos: torch.Tensor, allow_not_converged=False):
         """Returns (u0 [N0^3] tensor, [Stats per level])."""

@@ -136,7 +136,8 @@ def test_config4_full_size_sampled_residual():
     refinement flags exactly; at sampled cells of every level (random cells,
     cells next to ghost faces and, on the base and level 1, cells covered by
     the next level) the residual f - L(u) evaluated by the oracle -- composite
-    masses from the particles, the operator on the stencil, ghost values
+    masses from the particles (the library assigns them binned, as the
+    benchmark does), the operator on the stencil, ghost values
     reconstructed from the parent level's solution -- is within the solve's
     tolerance of the level's scale."""
     from paper_1305_2418_amd import mgfr
@@ -147,6 +148,7 @@ def test_config4_full_size_sampled_residual():
                          post_smooth=4, prolong=mgfr.PROLONG_INJECT, coarse_sweeps=4)
     amr = mgfr.Amr(params, max_blocks=65536)
     amr.set_relaxation32(1.2)
+    amr.reserve_particles(pos.shape[0])  # the benchmark's binned assignment
     u0, st = amr.solve(pos.to(DEV))
     assert all(s.status == 0 and s.res <= 1e-8 for s in st), [(s.status, s.res) for s in st]
     u0 = u0.cpu().numpy()
@@ -228,21 +230,23 @@ def test_config4_full_size_sampled_residual():
         assert worst <= 1.01e-8
 
 
-@pytest.mark.parametrize("fr0", [1e-6, 1e-5])
-def test_composite_spectrum_matches_oracle(fr0):
+@pytest.mark.parametrize("fr0,binned", [(1e-6, False), (1e-5, False), (1e-6, True)])
+def test_composite_spectrum_matches_oracle(fr0, binned):
     """The adaptive solution on one grid (Sec. 5.1's comparison of adaptive and
     fixed meshes): composite delta and effective density of the library against
     the oracle's composite cell by cell, and the ratio P(delta + delta_eff) /
     P(delta) of the library's shell spectra against numpy's."""
     from paper_1305_2418_amd import mgfr
     N0, nref = 32, 2
-    print(f"[case] composite spectrum fr0={fr0}", flush=True)
+    print(f"[case] composite spectrum fr0={fr0} binned={binned}", flush=True)
     pos = synth.clustered_load(N0, 100.0, rms=5.0, seed=4, n_halos=50, profile="nfw")
     p = O.params(mesh=N0, fr0_abs=fr0)
     s_o, blk, ds, us, ms, sts = O.amr_levels(p, nref, pos.numpy())
     assert s_o == 0
     d_o, e_o = O.amr_composite(p, ds, us, ms)
     amr = mgfr.Amr(mgfr.Params(mesh=N0, fr0_abs=fr0, refine_levels=nref), max_blocks=20000)
+    if binned:
+        amr.reserve_particles(pos.shape[0])
     amr.solve(pos.to(DEV))
     d, e = amr.composite()
     d, e = d.cpu().numpy(), e.cpu().numpy()
@@ -255,3 +259,30 @@ def test_composite_spectrum_matches_oracle(fr0):
     print(f"  ratio at k_1 {r[0]:.4f}, k_8 {r[7]:.4f}, k_32 {r[31]:.4f}")
     assert np.array_equal(c, c_o)
     assert np.allclose(r, r_o, rtol=1e-8) and np.allclose(pd, pd_o, rtol=1e-9)
+
+
+@pytest.mark.parametrize("N0,nref,npart", [(256, 2, 256), (64, 2, 96), (32, 1, 40)])
+def test_binned_assignment_equals_per_particle(N0, nref, npart):
+    """The binned composite assignment (particles sorted by the group of cells
+    they deposit into, one LDS window per run; cubes across levels on the
+    per-particle path) against the per-particle one on the same solve: the
+    same composite density up to the order of the float64 sums, and the same
+    converged solution up to the solve's tolerance.  Covers the 256^3 configuration (256^3 particles, 50
+    NFW halos) and particle counts that leave a ragged last chunk."""
+    from paper_1305_2418_amd import mgfr
+    print(f"[case] binned vs per-particle N0={N0} nref={nref} np={npart}^3", flush=True)
+    pos = synth.clustered_load(npart, 100.0, rms=5.0, seed=4, n_halos=50, profile="nfw").to(DEV)
+    out = []
+    for binned in (False, True):
+        amr = mgfr.Amr(mgfr.Params(mesh=N0, fr0_abs=1e-6, refine_levels=nref), max_blocks=65536)
+        if binned:
+            amr.reserve_particles(pos.shape[0] + 5)
+        u0, st = amr.solve(pos)
+        assert all(s.status == 0 for s in st)
+        d, _ = amr.composite()
+        out.append((d.cpu().numpy(), u0.cpu().numpy()))
+        del amr
+    (d0, u0), (d1, u1) = out
+    assert np.abs(d1 - d0).max() <= 1e-12 * np.abs(d0).max()
+    # both solves stop at residual 1e-8: their answers differ by less than that error
+    assert np.abs(u1 - u0).max() <= 1e-6 * np.abs(u0).max()

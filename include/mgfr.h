@@ -371,8 +371,27 @@ int mgfr_net_train_step(mgfr_net *net, const double *delta, const double *u_targ
  * without updating the weights. */
 int mgfr_net_grads(mgfr_net *net, const double *delta, const double *u_target, int B, int S,
                    const double *cond, float *loss, float *grad_host);
-/* Attach (or detach with NULL) the network used by nn_mode = MGFR_NN_COARSE. */
+/* Attach (or detach with NULL) the network used by nn_mode = MGFR_NN_COARSE.
+ * A network the context created with mgfr_nn_init is destroyed first. */
 int mgfr_set_net(mgfr_ctx *ctx, mgfr_net *net);
+
+/* The same network owned by the context (the ctx-level calls of the
+ * boundary).  mgfr_nn_init creates it (He-normal weights from seed, capacity
+ * max((N/4)^3, 8 * 64^3) voxels), attaches it for nn_mode = MGFR_NN_COARSE
+ * and replaces any attached network; mgfr_destroy destroys it.  The others
+ * act on the attached network (either kind) on the context's stream, with
+ * the arguments of the mgfr_net_* call of the same name.  mgfr_nn_predict
+ * writes to u0 (device float64 [N^3]) the initial guess a solve with
+ * nn_mode = MGFR_NN_COARSE starts from when coarse_cycles = 0: delta
+ * restricted to N/4 by 4^3 means, the network's u there, prolonged twice
+ * (Sec. 3.3 reconstruction); it needs N >= 128.  MGFR_ERR_ARG without a
+ * network. */
+int mgfr_nn_init(mgfr_ctx *ctx, int seed);
+int mgfr_nn_train_step(mgfr_ctx *ctx, const double *delta, const double *u_target, int B, int S,
+                       const double *cond, float lr, float *loss);
+int mgfr_nn_predict(mgfr_ctx *ctx, const double *delta, double *u0);
+int mgfr_nn_save(mgfr_ctx *ctx, const char *path);
+int mgfr_nn_load(mgfr_ctx *ctx, const char *path);
 
 /* Single convolution layers on bf16 tensors (the network's building blocks),
  * on `stream`, no synchronisation:

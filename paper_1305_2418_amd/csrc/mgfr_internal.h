@@ -71,8 +71,10 @@ struct mgfr_ctx {
     bool timing = false;
     mgfr::Timer sweep_timer;
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
-    // learned warm start (owned by the network module)
+    // learned warm start: the attached network (mgfr_set_net: the caller's;
+    // mgfr_nn_init: the context's own, destroyed with it)
     void *nn = nullptr;
+    bool nn_owned = false;
     // particle binning by 8^3 tiles of CIC lower-corner cells (mgfr_bin.hip)
     int binning = 1;           // 0: assign by direct global atomics
     int64_t bin_cap = 0;       // particles the binning workspace holds

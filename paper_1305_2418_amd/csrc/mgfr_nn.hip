@@ -985,8 +985,71 @@ extern "C" int mgfr_conv3d_bwd_weight(const void *x, const void *dz, int B, int 
 extern "C" int mgfr_set_net(mgfr_ctx *c, mgfr_net *n)
 {
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    nn_free(c);
     c->nn = n;
     return MGFR_OK;
+}
+
+// The context's own network (the mgfr_nn_* calls): capacity for the N/4 mesh
+// and for training batches of eight 64^3 volumes.
+extern "C" int mgfr_nn_init(mgfr_ctx *c, int seed)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    const int64_t n4 = (int64_t)(c->lev[0].N / 4) * (c->lev[0].N / 4) * (c->lev[0].N / 4);
+    const int64_t cap = std::max<int64_t>({n4, (int64_t)8 * 64 * 64 * 64});
+    mgfr_net *n = nullptr;
+    int rc = mgfr_net_create(seed, (cap + 4095) / 4096 * 4096, c->stream, &n);
+    if (rc) return rc;
+    nn_free(c);
+    c->nn = n;
+    c->nn_owned = true;
+    return MGFR_OK;
+}
+
+namespace {
+mgfr_net *ctx_net(mgfr_ctx *c)
+{
+    if (!c) {
+        set_error(MGFR_ERR_ARG, "ctx is NULL");
+        return nullptr;
+    }
+    if (!c->nn) set_error(MGFR_ERR_ARG, "no network: call mgfr_nn_init or mgfr_set_net first");
+    return (mgfr_net *)c->nn;
+}
+}  // namespace
+
+extern "C" int mgfr_nn_train_step(mgfr_ctx *c, const double *delta, const double *u_target, int B, int S,
+                                  const double *cond, float lr, float *loss)
+{
+    mgfr_net *n = ctx_net(c);
+    if (!n) return MGFR_ERR_ARG;
+    int rc = mgfr_net_set_stream(n, c->stream);
+    return rc ? rc : mgfr_net_train_step(n, delta, u_target, B, S, cond, lr, loss);
+}
+
+extern "C" int mgfr_nn_predict(mgfr_ctx *c, const double *delta, double *u0)
+{
+    mgfr_net *n = ctx_net(c);
+    if (!n) return MGFR_ERR_ARG;
+    if (!delta || !u0) return set_error(MGFR_ERR_ARG, "delta and u0 must be non-NULL");
+    const int cc = c->p.coarse_cycles;
+    c->p.coarse_cycles = 0;  // the guess itself, without the coarse-level V-cycles of a solve
+    double ms = 0.0;
+    const int rc = nn_warm_start(c, delta, u0, &ms);
+    c->p.coarse_cycles = cc;
+    return rc;
+}
+
+extern "C" int mgfr_nn_save(mgfr_ctx *c, const char *path)
+{
+    mgfr_net *n = ctx_net(c);
+    return n ? mgfr_net_save(n, path) : MGFR_ERR_ARG;
+}
+
+extern "C" int mgfr_nn_load(mgfr_ctx *c, const char *path)
+{
+    mgfr_net *n = ctx_net(c);
+    return n ? mgfr_net_load(n, path) : MGFR_ERR_ARG;
 }
 
 namespace mgfr {
@@ -1044,6 +1107,12 @@ int nn_warm_start(mgfr_ctx *c, const double *delta, double *u, double *t_ms)
     return MGFR_OK;
 }
 
-void nn_free(mgfr_ctx *c) { c->nn = nullptr; }  // the network is owned by its creator
+// detach the network; destroy it if the context created it (mgfr_nn_init)
+void nn_free(mgfr_ctx *c)
+{
+    if (c->nn_owned && c->nn) mgfr_net_destroy((mgfr_net *)c->nn);
+    c->nn = nullptr;
+    c->nn_owned = false;
+}
 
 }  // namespace mgfr

@@ -156,6 +156,11 @@ def lib() -> C.CDLL:
                                           C.POINTER(C.c_float)]
         L.mgfr_net_grads.argtypes = [_VP, _VP, _VP, C.c_int, C.c_int, _VP, C.POINTER(C.c_float), _VP]
         L.mgfr_set_net.argtypes = [_VP, _VP]
+        L.mgfr_nn_init.argtypes = [_VP, C.c_int]
+        L.mgfr_nn_train_step.argtypes = [_VP, _VP, _VP, C.c_int, C.c_int, _VP, C.c_float, C.POINTER(C.c_float)]
+        L.mgfr_nn_predict.argtypes = [_VP, _VP, _VP]
+        L.mgfr_nn_save.argtypes = [_VP, C.c_char_p]
+        L.mgfr_nn_load.argtypes = [_VP, C.c_char_p]
         L.mgfr_conv3d_fwd.argtypes = [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, C.c_int, C.c_int, _VP, _VP, _VP]
         L.mgfr_conv3d_bwd_data.argtypes = [_VP, C.c_int, C.c_int, C.c_int, _VP, C.c_int, _VP, _VP, _VP]
         L.mgfr_conv3d_bwd_weight.argtypes = [_VP, _VP, C.c_int, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]
@@ -407,6 +412,38 @@ class Solver:
     def set_net(self, net):
         _check(lib().mgfr_set_net(self._h, None if net is None else net._h))
         self._net = net
+
+    # the context's own network (mgfr_nn_*)
+    def nn_init(self, seed: int = 0):
+        _check(lib().mgfr_nn_init(self._h, int(seed)))
+        self._net = None
+
+    def nn_train_step(self, delta: torch.Tensor, u_target: torch.Tensor, cond, lr: float) -> float:
+        self._sync_stream()
+        B, S = delta.shape[0], delta.shape[1]
+        _dev(delta, torch.float64, (B, S, S, S), "delta")
+        _dev(u_target, torch.float64, (B, S, S, S), "u_target")
+        arr, cp = _cond_array(cond)
+        loss = C.c_float()
+        _check(lib().mgfr_nn_train_step(self._h, delta.data_ptr(), u_target.data_ptr(), B, S, cp, float(lr),
+                                        C.byref(loss)))
+        return loss.value
+
+    def nn_predict(self, delta: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """The network's initial guess at N (prediction on N/4, prolonged twice)."""
+        self._sync_stream()
+        dp = _dev(delta, torch.float64, self.shape, "delta")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=delta.device)
+        up = _dev(out, torch.float64, self.shape, "u0")
+        _check(lib().mgfr_nn_predict(self._h, dp, up))
+        return out
+
+    def nn_save(self, path: str):
+        _check(lib().mgfr_nn_save(self._h, os.fsencode(path)))
+
+    def nn_load(self, path: str):
+        _check(lib().mgfr_nn_load(self._h, os.fsencode(path)))
 
     def ngs_sweep(self, u: torch.Tensor, f: torch.Tensor, sweeps: int = 1):
         self._sync_stream()

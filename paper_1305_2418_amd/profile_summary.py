@@ -24,7 +24,8 @@ _OPS = "paper_1305_2418_amd/csrc/mgfr_ops.h"
 SWEEPS = {"k_mx_colour": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip", _OPS],
           "k_mx_sweep2": ["paper_1305_2418_amd/csrc/mgfr_mixed.hip", _OPS],
           "k_sweep_fused": ["paper_1305_2418_amd/csrc/mgfr_solver.hip", _OPS]}
-BY_GRID = ("k_mx_colour", "k_sweep_fused", "k_mx_correct_residual", "k_mx_restrict_pass", "k_mx_sweep2")
+BY_GRID = ("k_mx_colour", "k_sweep_fused", "k_mx_correct_residual", "k_mx_restrict_pass", "k_mx_sweep2",
+           "k_amrx_sweep", "k_amrx_restrict")
 COPY = "bitwise_not"
 
 

@@ -526,9 +526,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{N}^3 mesh, {N}^3 particles (float32), 100 Mpc/h, a={args.a}, |f_R0|={args.fr0}, "
-                        f"Zel'dovich k^-2 rms 5 + 20 Plummer halos, seed {args.seed}; step = CIC + solve from a "
-                        f"cold start to 1e-8 with V({args.smooth},{args.smooth}), {args.prolong} prolongation, + fifth force; "
-                        f"mixed modes: float32 correction sweeps relaxed by omega = {args.omega}",
+                        f"Zel'dovich k^-2 rms 5 + 20 Plummer halos, seed {args.seed}; step = CIC + solve to 1e-8 with "
+                        f"V({args.smooth},{args.smooth}), {args.prolong} prolongation, + fifth force; initial guess "
+                        f"per mode: u = 0 (fp64, mixed), the network's prediction on the N/4 mesh (mixed_nn, its "
+                        f"time included), the screened-limit guess (_scr, its time included); mixed modes: float32 "
+                        f"correction sweeps relaxed by omega = {args.omega}",
             "mode": args.mode,
             "modes": results,
             "modes_other_a": other_a,

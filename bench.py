@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--smooth", type=int, default=4, help="pre- and post-smoothing sweeps")
     ap.add_argument("--omega", type=float, default=1.2,
                     help="relaxation factor of the float32 correction sweeps of the mixed modes (1: plain NGS)")
+    ap.add_argument("--inner", type=int, default=2,
+                    help="float32 correction V-cycles per float64 residual check of the mixed modes, at most")
     ap.add_argument("--coarse-sweeps", type=int, default=None,
                     help="red-black sweeps on the coarsest grid (default: 30 for the uniform mesh, whose 4^3 "
                          "level runs inside one launch; 4 for the adaptive workload, whose refined levels' "
@@ -136,6 +138,7 @@ def mixed_vs_oracle(args, delta, dfr_oracle, dev, log):
     s = mgfr.Solver(mgfr.Params(mesh=N, box=100.0, a=args.a, fr0_abs=args.fr0, tol=1e-8, precision=mgfr.MIXED,
                                 pre_smooth=args.smooth, post_smooth=args.smooth, prolong=prolong_code(args)))
     s.set_relaxation32(args.omega)
+    s.set_inner_cycles(args.inner)
     u, dfr, st = s.solve(torch.tensor(delta, device=dev))
     ref = torch.tensor(dfr_oracle, device=dev)
     err = float((dfr - ref).abs().max() / ref.abs().max())
@@ -218,6 +221,7 @@ def run_mode(mode, args, pos, dev, log, a=None, dfr_ref=None):
     solver = mgfr.Solver(params)
     if precision == mgfr.MIXED:
         solver.set_relaxation32(args.omega)
+        solver.set_inner_cycles(args.inner)
     net = None
     if nn_mode == mgfr.NN_COARSE:
         if not os.path.exists(WEIGHTS):
@@ -389,6 +393,7 @@ def run_sequence(args, log):
     others = {"cold": mk(mgfr.NN_NONE, a0), "network": mk(mgfr.NN_COARSE, a0), "screened": mk(mgfr.NN_NONE, a0)}
     for s in [chain, *others.values()]:
         s.set_relaxation32(args.omega)
+        s.set_inner_cycles(args.inner)
     net = mgfr.Net(seed=0, max_voxels=(N // 4) ** 3)
     net.set_params(np.load(WEIGHTS))
     others["network"].set_net(net)
@@ -429,7 +434,8 @@ def run_sequence(args, log):
         "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"{N}^3 particles and mesh, Zel'dovich k^-2 rms 5 + 20 Plummer halos (seed "
                                f"{args.seed}), linear-theory momenta at a = {a0}, {K} kick-drift-kick steps to "
-                               f"a = 1, |f_R0| = {args.fr0}; mixed solves with omega = {args.omega}; the other "
+                               f"a = 1, |f_R0| = {args.fr0}; mixed solves with omega = {args.omega}, up to {args.inner} "
+                               f"correction cycles per float64 check; the other "
                                f"guesses solve the same density (reported, not part of the step)",
                    "step_ms": step_ms, "modes": out},
         "roofline": None,
@@ -535,7 +541,8 @@ def main():
                         f"V({args.smooth},{args.smooth}), {args.prolong} prolongation, + fifth force; initial guess "
                         f"per mode: u = 0 (fp64, mixed), the network's prediction on the N/4 mesh (mixed_nn, its "
                         f"time included), the screened-limit guess (_scr, its time included); mixed modes: float32 "
-                        f"correction sweeps relaxed by omega = {args.omega}",
+                        f"correction sweeps relaxed by omega = {args.omega}, up to {args.inner} correction cycles per float64 "
+                        f"residual check",
             "mode": args.mode,
             "modes": results,
             "modes_other_a": other_a,

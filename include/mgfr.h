@@ -165,6 +165,17 @@ int mgfr_set_fused_sweep32(mgfr_ctx *ctx, int on);
  * unless 0 < omega < 2. */
 int mgfr_set_relaxation32(mgfr_ctx *ctx, double omega);
 
+/* Float32 correction V-cycles per float64 residual check of the mixed
+ * solve, at most max_inner (1..4; default 1, one cycle per check).  With
+ * max_inner > 1 the solve runs that many cycles between checks while the
+ * residual, reduced at the rate the last check measured, would still be
+ * above tol after one more cycle; near the tolerance it checks after every
+ * cycle again.  Each cycle is a whole FAS V-cycle of the correction equation,
+ * so only the float64 residual passes are skipped; stats.vcycles counts the
+ * correction cycles, stats.outer_iters and res_hist the checks.
+ * Errors: MGFR_ERR_ARG for max_inner outside [1, 4]. */
+int mgfr_set_inner_cycles(mgfr_ctx *ctx, int max_inner);
+
 /* Cloud-in-cell assignment (Sec. 3.1) of np particles onto the N^3 mesh and
  * delta = m / m_bar - 1 with m_bar the mean cell mass of the assignment.
  * pos: float32 [np][3]; mass: float64 [np] or NULL for equal masses;

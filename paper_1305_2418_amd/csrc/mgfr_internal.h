@@ -58,6 +58,7 @@ struct mgfr_ctx {
     int fused32 = 0;          // those sweeps as one fused red-black kernel per sweep instead
     double omega32 = 1.0;     // relaxation factor of the float32 correction sweeps (mixed solve)
     double omega_now = 1.0;   // the factor in use (set to 1 once the outer residual grows)
+    int inner_max = 1;        // float32 correction V-cycles per float64 residual check, at most
     // reduction scratch
     double *partial = nullptr;  // [2 * nparts]
     int nparts = 0;

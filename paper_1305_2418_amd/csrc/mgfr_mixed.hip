@@ -1428,7 +1428,8 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
     if (rc) return rc;
     double res = rmax / D, prev = res;
     st->res0 = res;
-    int it = 0, grow = 0, status;
+    int it = 0, outer = 0, grow = 0, status;
+    double rate = 0.5;  // residual reduction per correction cycle, from the last outer step
     c->omega_now = c->omega32;
     for (;;) {
         if (!std::isfinite(res) || grow >= 3) {
@@ -1437,25 +1438,38 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
             L0.alt = c->alt0;
             MGFR_HIP(hipMemsetAsync(u, 0, n * sizeof(double), c->stream));
             st->fell_back = 1;
-            const int outer = it;
+            const int done = it;
             status = solve_fp64_from(c, u, st, D);
-            st->outer_iters = outer + st->vcycles;
+            st->outer_iters = done + st->vcycles;
             return status;
         }
         if (res <= c->p.tol) { status = MGFR_OK; break; }
         if (it >= c->p.max_vcycles) { status = MGFR_NOT_CONVERGED; break; }
-        if ((rc = mx_vcycle(c, 0))) return rc;
+        // Run up to inner_max correction cycles before the next float64
+        // residual, but not past the cycle before the one the measured rate
+        // predicts to reach the tolerance: each cycle is a full FAS V-cycle
+        // of N_u(e) = r, so only the checks are skipped, and the last cycles
+        // are checked one by one.
+        int k = 1;
+        if (c->inner_max > 1 && rate < 1.0) {
+            const double need = std::ceil(std::log(c->p.tol / res) / std::log(rate));
+            if (need > 2.0) k = (int)std::min<double>({(double)c->inner_max, need - 1.0, (double)(c->p.max_vcycles - it)});
+        }
+        for (int j = 0; j < k; ++j)
+            if ((rc = mx_vcycle(c, 0))) return rc;
         if ((rc = outer_step(c, true, &rmax, &rsq))) return rc;
         if (c->timing && (rc = collect_timing(c, st))) return rc;
         prev = res;
         res = rmax / D;
+        if (res > 0.0 && prev > 0.0) rate = std::min(1.0, std::pow(res / prev, 1.0 / k));
         grow = (res > prev) ? grow + 1 : 0;
         if (grow) c->omega_now = 1.0;  // over-relaxation off for the rest of the solve once the residual grows
-        if (it < MGFR_MAX_HIST) st->res_hist[it] = res;
-        ++it;
+        if (outer < MGFR_MAX_HIST) st->res_hist[outer] = res;
+        it += k;
+        ++outer;
     }
     st->vcycles = it;
-    st->outer_iters = it;
+    st->outer_iters = outer;
     st->res = res;
     st->l2res = std::sqrt(rsq / ncell) / D;
     return status;

@@ -1036,6 +1036,14 @@ extern "C" int mgfr_set_relaxation32(mgfr_ctx *c, double omega)
     return MGFR_OK;
 }
 
+extern "C" int mgfr_set_inner_cycles(mgfr_ctx *c, int max_inner)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (max_inner < 1 || max_inner > 4) return set_error(MGFR_ERR_ARG, "max_inner must be in [1, 4]");
+    c->inner_max = max_inner;
+    return MGFR_OK;
+}
+
 extern "C" int mgfr_set_fused_sweep32(mgfr_ctx *c, int on)
 {
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");

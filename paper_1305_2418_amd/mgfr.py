@@ -124,6 +124,7 @@ def lib() -> C.CDLL:
         L.mgfr_set_colour_min_mesh.argtypes = [_VP, C.c_int]
         L.mgfr_set_fused_sweep32.argtypes = [_VP, C.c_int]
         L.mgfr_set_relaxation32.argtypes = [_VP, C.c_double]
+        L.mgfr_set_inner_cycles.argtypes = [_VP, C.c_int]
         L.mgfr_screened_guess.argtypes = [_VP, _VP, _VP]
         L.mgfr_effective_density.argtypes = [_VP, _VP, _VP, _VP]
         L.mgfr_power_ratio.argtypes = [_VP, _VP, _VP, C.c_int, _VP, _VP, _VP, _VP]
@@ -281,6 +282,10 @@ class Solver:
     def set_relaxation32(self, omega: float):
         """Over-relaxation factor of the float32 correction sweeps (mixed solve)."""
         _check(lib().mgfr_set_relaxation32(self._h, float(omega)))
+
+    def set_inner_cycles(self, max_inner: int):
+        """Float32 correction V-cycles per float64 residual check of the mixed solve (at most)."""
+        _check(lib().mgfr_set_inner_cycles(self._h, int(max_inner)))
 
     def set_fused_sweep32(self, on: bool):
         """Float32 correction sweeps as one fused red-black kernel per sweep."""

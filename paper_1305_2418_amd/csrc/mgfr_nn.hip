@@ -39,8 +39,14 @@ namespace mgfr {
 
 namespace {
 
-constexpr int kConvWaves = 4;   // waves per workgroup in the forward kernel
-constexpr int kConvMT = 4;      // 16-voxel row tiles per wave (256 voxels per workgroup)
+#ifndef MGFR_CONV_WAVES
+#define MGFR_CONV_WAVES 4
+#endif
+#ifndef MGFR_CONV_MT
+#define MGFR_CONV_MT 4
+#endif
+constexpr int kConvWaves = MGFR_CONV_WAVES;  // waves per workgroup in the forward kernel
+constexpr int kConvMT = MGFR_CONV_MT;        // 16-voxel row tiles per wave (256 voxels per workgroup)
 // LDS stride of a staged voxel: 32-channel chunks get 8 bf16 of padding (the
 // 16-byte A-fragment reads of 16 consecutive voxels then spread over the
 // banks: 1.4x faster on those layers; 16-channel chunks are faster without)

@@ -1,7 +1,7 @@
 /*
  * mgfr_oracle.c -- plain, slow FP64 CPU reference of the f(R) field solve.
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the parity judge for the HIP
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity reference for the HIP
  * library: only the test-suite, the smoke check and the CPU-baseline leg of
  * the benchmark load it.  It shares no code, header, table or helper with the
  * GPU path; it is unblocked and unfused on purpose so that it can be read

@@ -1,7 +1,7 @@
 """ctypes front end of the plain FP64 CPU oracle (``mgfr_oracle.c``).
 
 Test infrastructure only: the test-suite, the smoke check and the benchmark's
-CPU-baseline leg use it to judge the HIP library; the library never calls it.
+CPU-baseline leg use it to check the HIP library; the library never calls it.
 """
 from __future__ import annotations
 

@@ -105,6 +105,7 @@ typedef struct mgfr_stats {
     double t_sweep_ms;   /* summed HIP-event time of finest-level smoothing launches (timing on) */
     int n_sweep_launches; /* number of launches in t_sweep_ms */
     double t_nn_ms;      /* HIP-event time of the network warm start, if any */
+    int smooth_used;     /* pre-smoothing sweeps of the last cycle (mgfr_set_adaptive_smoothing may raise them) */
 } mgfr_stats;
 
 typedef struct mgfr_ctx mgfr_ctx;
@@ -175,6 +176,18 @@ int mgfr_set_relaxation32(mgfr_ctx *ctx, double omega);
  * correction cycles, stats.outer_iters and res_hist the checks.
  * Errors: MGFR_ERR_ARG for max_inner outside [1, 4]. */
 int mgfr_set_inner_cycles(mgfr_ctx *ctx, int max_inner);
+
+/* Adaptive smoothing for stalling solves (FP64 and mixed): when a residual
+ * check is not below the one two checks earlier, the pre- and post-smoothing
+ * sweeps of the following cycles double, up to max_sweeps; each solve starts
+ * again from the parameters' counts.  0 (default) keeps the fixed V(pre,post)
+ * cycle of the paper.  Meant for deep screened cores at large |f_R0|, where
+ * red-black Newton sweeps can leave neighbouring cells alternating between
+ * the screened and the unscreened branch and a fixed V(4,4) cycle stalls.
+ * The answer is judged by the same residual.  stats.smooth_used reports the
+ * count in use at the end.  Errors: MGFR_ERR_ARG unless max_sweeps is 0 or
+ * between max(pre_smooth, post_smooth) and 32. */
+int mgfr_set_adaptive_smoothing(mgfr_ctx *ctx, int max_sweeps);
 
 /* Cloud-in-cell assignment (Sec. 3.1) of np particles onto the N^3 mesh and
  * delta = m / m_bar - 1 with m_bar the mean cell mass of the assignment.

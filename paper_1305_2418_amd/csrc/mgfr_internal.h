@@ -59,6 +59,7 @@ struct mgfr_ctx {
     double omega32 = 1.0;     // relaxation factor of the float32 correction sweeps (mixed solve)
     double omega_now = 1.0;   // the factor in use (set to 1 once the outer residual grows)
     int inner_max = 1;        // float32 correction V-cycles per float64 residual check, at most
+    int smooth_max = 0;       // adaptive smoothing: sweeps double up to this when the residual stalls (0: off)
     // reduction scratch
     double *partial = nullptr;  // [2 * nparts]
     int nparts = 0;
@@ -116,6 +117,9 @@ int launch_residual_norm64(mgfr_ctx *c, int l, const double *u, const double *f,
                            double *rsumsq);
 int vcycle64(mgfr_ctx *c, int l);
 int solve_fp64_from(mgfr_ctx *c, double *u, mgfr_stats *st, double D);  // V-cycles from the current u
+// adaptive smoothing: after a residual check, res (this check) against res2
+// (two checks back, < 0 if none); doubles the sweeps when it has not fallen
+void adapt_smoothing(mgfr_ctx *c, double res, double res2);
 int collect_timing(mgfr_ctx *c, mgfr_stats *st);
 
 // mixed precision (mgfr_mixed.hip)

@@ -1426,7 +1426,7 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
     double rmax, rsq;
     int rc = outer_step(c, false, &rmax, &rsq);
     if (rc) return rc;
-    double res = rmax / D, prev = res;
+    double res = rmax / D, prev = res, prev2 = -1.0;  // prev, prev2: one and two checks back
     st->res0 = res;
     int it = 0, outer = 0, grow = 0, status;
     double rate = 0.5;  // residual reduction per correction cycle, from the last outer step
@@ -1459,8 +1459,10 @@ int solve_mixed(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
             if ((rc = mx_vcycle(c, 0))) return rc;
         if ((rc = outer_step(c, true, &rmax, &rsq))) return rc;
         if (c->timing && (rc = collect_timing(c, st))) return rc;
+        prev2 = outer >= 1 ? prev : -1.0;
         prev = res;
         res = rmax / D;
+        adapt_smoothing(c, res, prev2);
         if (res > 0.0 && prev > 0.0) rate = std::min(1.0, std::pow(res / prev, 1.0 / k));
         grow = (res > prev) ? grow + 1 : 0;
         if (grow) c->omega_now = 1.0;  // over-relaxation off for the rest of the solve once the residual grows

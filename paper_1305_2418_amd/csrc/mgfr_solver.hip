@@ -911,6 +911,13 @@ static int finish(mgfr_ctx *c, double *u, double *dfr, mgfr_stats *st, int statu
     return status;
 }
 
+void mgfr::adapt_smoothing(mgfr_ctx *c, double res, double res2)
+{
+    if (c->smooth_max <= 0 || !(res2 >= 0.0) || !(res >= res2)) return;
+    c->p.pre_smooth = std::min(std::max(1, 2 * c->p.pre_smooth), c->smooth_max);
+    c->p.post_smooth = std::min(std::max(1, 2 * c->p.post_smooth), c->smooth_max);
+}
+
 int mgfr::solve_fp64_from(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
 {
     Level &L0 = c->lev[0];
@@ -918,7 +925,7 @@ int mgfr::solve_fp64_from(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
     const double ncell = (double)L0.N * L0.N * L0.N;
     int rc = launch_residual_norm64(c, 0, u, L0.f, &rmax, &rsq);
     if (rc) return rc;
-    double res = rmax / D;
+    double res = rmax / D, res1 = res, res2 = -1.0;  // res1, res2: one and two checks back
     st->res0 = res;
     int cyc = 0, status;
     for (;;) {
@@ -928,7 +935,10 @@ int mgfr::solve_fp64_from(mgfr_ctx *c, double *u, mgfr_stats *st, double D)
         if ((rc = vcycle64(c, 0))) return rc;
         if ((rc = launch_residual_norm64(c, 0, u, L0.f, &rmax, &rsq))) return rc;
         if (c->timing && (rc = collect_timing(c, st))) return rc;
+        res2 = cyc >= 1 ? res1 : -1.0;
+        res1 = res;
         res = rmax / D;
+        adapt_smoothing(c, res, res2);
         if (cyc < MGFR_MAX_HIST) st->res_hist[cyc] = res;
         ++cyc;
     }
@@ -988,11 +998,15 @@ extern "C" int mgfr_solve(mgfr_ctx *c, const double *delta, double *u, double *d
         st->t_nn_ms = tnn;
     }
     int status;
+    const int pre = c->p.pre_smooth, post = c->p.post_smooth;  // adaptive smoothing changes them per solve
     if (c->p.precision == MGFR_MIXED) {
         status = solve_mixed(c, u, st, D);
     } else {
         status = solve_fp64_from(c, u, st, D);
     }
+    st->smooth_used = c->p.pre_smooth;
+    c->p.pre_smooth = pre;
+    c->p.post_smooth = post;
     if (status < 0 && status != MGFR_ERR_NONFINITE) return status;
     if ((rc = restore_level0(c, u))) return rc;
     return finish(c, u, dfr, st, status);
@@ -1033,6 +1047,15 @@ extern "C" int mgfr_set_relaxation32(mgfr_ctx *c, double omega)
     if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
     if (!(omega > 0.0 && omega < 2.0)) return set_error(MGFR_ERR_ARG, "omega must be in (0, 2)");
     c->omega32 = omega;
+    return MGFR_OK;
+}
+
+extern "C" int mgfr_set_adaptive_smoothing(mgfr_ctx *c, int max_sweeps)
+{
+    if (!c) return set_error(MGFR_ERR_ARG, "ctx is NULL");
+    if (max_sweeps != 0 && (max_sweeps < std::max(c->p.pre_smooth, c->p.post_smooth) || max_sweeps > 32))
+        return set_error(MGFR_ERR_ARG, "max_sweeps must be 0 or in [max(pre_smooth, post_smooth), 32]");
+    c->smooth_max = max_sweeps;
     return MGFR_OK;
 }
 

@@ -45,7 +45,7 @@ class _Stats(C.Structure):
                 ("fell_back", C.c_int), ("res0", C.c_double), ("res", C.c_double),
                 ("scale", C.c_double), ("l2res", C.c_double), ("res_hist", C.c_double * MAX_HIST),
                 ("t_solve_ms", C.c_double), ("t_sweep_ms", C.c_double),
-                ("n_sweep_launches", C.c_int), ("t_nn_ms", C.c_double)]
+                ("n_sweep_launches", C.c_int), ("t_nn_ms", C.c_double), ("smooth_used", C.c_int)]
 
 
 @dataclass
@@ -92,13 +92,14 @@ class Stats:
     t_sweep_ms: float = 0.0
     n_sweep_launches: int = 0
     t_nn_ms: float = 0.0
+    smooth_used: int = 0
 
     @classmethod
     def from_c(cls, s: _Stats) -> "Stats":
-        n = min(max(s.vcycles, s.outer_iters), MAX_HIST)
+        n = min(s.outer_iters, MAX_HIST)  # one entry per residual check
         return cls(s.status, s.vcycles, s.outer_iters, s.fell_back, s.res0, s.res, s.scale,
                    s.l2res, list(s.res_hist[:n]), s.t_solve_ms, s.t_sweep_ms,
-                   s.n_sweep_launches, s.t_nn_ms)
+                   s.n_sweep_launches, s.t_nn_ms, s.smooth_used)
 
 
 _lib = None
@@ -125,6 +126,7 @@ def lib() -> C.CDLL:
         L.mgfr_set_fused_sweep32.argtypes = [_VP, C.c_int]
         L.mgfr_set_relaxation32.argtypes = [_VP, C.c_double]
         L.mgfr_set_inner_cycles.argtypes = [_VP, C.c_int]
+        L.mgfr_set_adaptive_smoothing.argtypes = [_VP, C.c_int]
         L.mgfr_screened_guess.argtypes = [_VP, _VP, _VP]
         L.mgfr_effective_density.argtypes = [_VP, _VP, _VP, _VP]
         L.mgfr_power_ratio.argtypes = [_VP, _VP, _VP, C.c_int, _VP, _VP, _VP, _VP]
@@ -282,6 +284,10 @@ class Solver:
     def set_relaxation32(self, omega: float):
         """Over-relaxation factor of the float32 correction sweeps (mixed solve)."""
         _check(lib().mgfr_set_relaxation32(self._h, float(omega)))
+
+    def set_adaptive_smoothing(self, max_sweeps: int):
+        """Double the smoothing sweeps (up to max_sweeps) when the residual stalls; 0: off."""
+        _check(lib().mgfr_set_adaptive_smoothing(self._h, int(max_sweeps)))
 
     def set_inner_cycles(self, max_inner: int):
         """Float32 correction V-cycles per float64 residual check of the mixed solve (at most)."""

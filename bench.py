@@ -60,6 +60,8 @@ def parse():
                          "in several ways")
     ap.add_argument("--also-a", default="0.5",
                     help="comma-separated other scale factors at which mixed, mixed_nn and mixed_scr are also timed")
+    ap.add_argument("--no-fixed-compare", action="store_true",
+                    help="amr workload: skip the untimed adaptive-versus-fixed spectra (profiling the step alone)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also stream 1 GiB through a plain elementwise kernel (reference for HBM counters)")
     return ap.parse_args()
@@ -310,8 +312,8 @@ def run_amr(args, log):
     cells = N0 ** 3 + 512 * sum(nb)
     del amr, pos
     torch.cuda.empty_cache()
-    spectra = {"64^3+2 vs 256^3": amr_vs_fixed(args, log, 64, 256),
-               "128^3+2 vs 512^3": amr_vs_fixed(args, log, 128, 512)}
+    spectra = None if args.no_fixed_compare else {"64^3+2 vs 256^3": amr_vs_fixed(args, log, 64, 256),
+                                                   "128^3+2 vs 512^3": amr_vs_fixed(args, log, 128, 512)}
     log(f"[amr] step {ms:.2f} ms, blocks {nb}, cycles {[s.vcycles for s in st]}, res {[f'{s.res:.1e}' for s in st]}")
     return {
         "metric": "cells/s to converged f_R solve (res<1e-8) on the adaptive mesh (base + refined cells)",
@@ -348,6 +350,7 @@ def amr_vs_fixed(args, log, N0=64, N=256):
     for fr0 in (1e-6, 1e-5):
         amr = mgfr.Amr(mgfr.Params(mesh=N0, fr0_abs=fr0, refine_levels=2, precision=mgfr.MIXED, pre_smooth=4,
                                    post_smooth=4, prolong=1, coarse_sweeps=4), max_blocks=262144)
+        amr.reserve_particles(pos.shape[0])
         amr.solve(pos)
         d_a, e_a = amr.composite()
         nbl = [int(amr.level(l)[0].shape[0]) for l in (1, 2)]

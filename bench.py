@@ -463,8 +463,8 @@ def calibrate_copy(log):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note, not implemented)"}))
+        print(json.dumps({"error": "mgfr runs on one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is designed, not implemented)"}))
         sys.exit(2)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     import torch

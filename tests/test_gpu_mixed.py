@@ -131,3 +131,37 @@ def test_sweep_kernels_agree(N):
         rel = ((u - ref).abs().max() / scale).item()
         print(f"  {k} vs colour passes: rel max diff {rel:.2e}")
         assert rel < (1e-4 if k == "plain" else 1e-6)
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_mixed_with_all_options_matches_oracle(n):
+    """The mixed solve with every option the benchmark or a hard case uses at
+    once -- over-relaxed correction sweeps (omega 1.2), two correction cycles
+    per float64 check and adaptive smoothing -- for Hu-Sawicki n = 1 and 2.
+    Solved to residual 1e-10, so that the comparison measures the path and not
+    the tolerance (at n = 2 a residual of 1e-8 leaves ~1e-6 of field error in
+    float64 too): the oracle's answer to 1e-8 and the oracle's residual of the
+    returned u."""
+    from paper_1305_2418_amd import mgfr
+    N, fr0, a = 64, 1e-6, 0.7
+    print(f"[case] mixed with all options, n={n}", flush=True)
+    d = _delta(N, 5.0, 7, 20)
+    s_o, u_o, dfr_o, st_o = O.solve(O.params(mesh=N, fr0_abs=fr0, a=a, n=n, tol=1e-12, max_vcycles=100), d)
+    assert s_o == 0
+    kw = dict(mesh=N, fr0_abs=fr0, a=a, n=n, pre_smooth=4, post_smooth=4, prolong=mgfr.PROLONG_INJECT)
+    s = mgfr.Solver(mgfr.Params(precision=mgfr.MIXED, tol=1e-10, **kw))
+    s.set_relaxation32(1.2)
+    s.set_inner_cycles(2)
+    s.set_adaptive_smoothing(16)
+    u, dfr, st = s.solve(torch.tensor(d, device=DEV))
+    assert st.status == 0 and st.fell_back == 0 and st.res <= 1e-10
+    err = np.abs(dfr.cpu().numpy() - dfr_o).max() / np.abs(dfr_o).max()
+    _, dfr64, st64 = mgfr.Solver(mgfr.Params(tol=1e-8, **kw)).solve(torch.tensor(d, device=DEV))
+    err64 = np.abs(dfr64.cpu().numpy() - dfr_o).max() / np.abs(dfr_o).max()
+    print(f"  cycles {st.vcycles}, checks {st.outer_iters}, sweeps {st.smooth_used}, rel dfr err {err:.2e} "
+          f"(float64 solve stopped at 1e-8: {err64:.2e})")
+    assert err < 1e-8
+    fb, beta, C = O.background(O.params(mesh=N, fr0_abs=fr0, a=a, n=n))
+    f = beta * 0.3 / a ** 3 * d
+    r = O.residual_max(u.cpu().numpy(), f, 100.0 / N, beta * C, n) / np.abs(f).max()
+    assert r <= 1e-10

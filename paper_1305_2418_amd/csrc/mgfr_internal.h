@@ -81,8 +81,13 @@ struct mgfr_ctx {
     int binning = 1;           // 0: assign by direct global atomics
     int64_t bin_cap = 0;       // particles the binning workspace holds
     int64_t perm_np = 0;       // particle count of the last binning (0: none)
-    uint32_t *bkey = nullptr, *bkey_s = nullptr, *bidx = nullptr, *perm = nullptr;
-    void *sort_tmp = nullptr;
+    uint32_t *bkey = nullptr, *bidx = nullptr, *perm = nullptr;  // tile and rank of each particle, sorted order
+    uint32_t *tcount = nullptr, *tstart = nullptr;  // particles per tile, first sorted slot of each tile
+    uint32_t *unit_n = nullptr, *unit_off = nullptr; // work units per tile and the first of each tile
+    uint4 *units = nullptr;                          // (tile, first slot, end slot, 0) of each work unit
+    uint32_t *unit_total = nullptr;                  // number of work units of the last binning
+    uint32_t unit_grid = 0;                          // workgroups of the unit kernels
+    void *sort_tmp = nullptr;                        // workspace of the scans
     size_t sort_tmp_bytes = 0;
     // particle-mesh potential (mgfr_pm_accel): FFT plans and the half spectrum, made on first use
     void *pm_fwd = nullptr, *pm_inv = nullptr;
@@ -132,8 +137,12 @@ constexpr int kCicPer = 8;                        // particles per thread and wo
 constexpr int kCicChunk = kBlock * kCicPer;
 constexpr int kWin = (1 << kBinLg) + 1;           // LDS window edge: a tile plus one cell
 constexpr int kWin3 = kWin * kWin * kWin;
+// The binned particle kernels work on units: up to kUnit sorted slots of one
+// tile (a tile with more particles is split), kUnit / kBlock per thread.
+constexpr int kUnit = 1024;
+constexpr int kUnitPer = kUnit / kBlock;
 int bin_reserve(mgfr_ctx *c, int64_t np);
-int bin_particles(mgfr_ctx *c, const float *pos, int64_t np);  // keys + sort; sets perm_np
+int bin_particles(mgfr_ctx *c, const float *pos, int64_t np);  // counting sort by tile; sets perm_np
 void bin_free(mgfr_ctx *c);
 // Stable radix sort of (key, value) uint32 pairs on the low `bits` key bits.
 // With tmp == nullptr only *tmp_bytes is set (the workspace the sort needs).
@@ -150,6 +159,26 @@ __device__ __forceinline__ bool cic_axis(float x, double h, int mask, int &i0, d
     double fl = floor(xi);
     t = xi - fl;
     i0 = (int)((long long)fl & (long long)mask);
+    return true;
+}
+
+// cic_axis with the reciprocal r = 1/h given: x/h as x r plus one FMA
+// correction, which by Markstein's theorem is the correctly rounded quotient
+// (r correctly rounded, x r within an ulp), so i0 and t are those of
+// cic_axis.  An int32 conversion serves every position within 2^31 cells.
+__device__ __forceinline__ bool cic_axis_r(float x, double h, double r, int mask, int &i0, double &t)
+{
+    const double xd = (double)x;
+    double q = xd * r;
+    q = fma(fma(-q, h, xd), r, q);
+    const double xi = q - 0.5;
+    if (!(fabs(xi) < 4.0e18)) return false;
+    const double fl = floor(xi);
+    t = xi - fl;
+    if (fabs(fl) < 2147483648.0)
+        i0 = (int)fl & mask;
+    else
+        i0 = (int)((long long)fl & (long long)mask);
     return true;
 }
 

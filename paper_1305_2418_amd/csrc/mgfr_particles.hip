@@ -43,73 +43,61 @@ __global__ __launch_bounds__(kBlock) void k_cic_scatter(const float *__restrict_
             }
 }
 
-// Cloud-in-cell assignment of binned particles.  Workgroup b takes the
-// sorted slots [b kCicChunk, (b + 1) kCicChunk); its slots split into runs of
-// equal tile key.  Each run is accumulated in a 9^3 LDS window (lower corners
-// in the tile, upper corners one cell beyond) and the window's non-zero
-// entries are added to the mesh with float64 atomics.  The slots are loaded
-// once, before the runs are walked.
-__global__ __launch_bounds__(kBlock) void k_cic_binned(const float *__restrict__ pos,
-                                                         const double *__restrict__ mass,
-                                                         const uint32_t *__restrict__ key_s,
-                                                         const uint32_t *__restrict__ perm, int64_t np, int lg,
-                                                         double h, double *__restrict__ m, int *__restrict__ flag)
+// Cloud-in-cell assignment of binned particles.  A workgroup takes one work
+// unit at a time (up to kUnit particles of one 8^3 tile, kUnitPer per
+// thread), accumulates it in a 9^3 LDS window (lower corners in the tile,
+// upper corners one cell beyond) and adds the window's non-zero entries to
+// the mesh with float64 atomics.  (Storing the window cells 1..7 of a tile
+// that is a single unit, which no other unit reaches, instead of adding them
+// was slower: plain stores and atomics then share cache lines.)
+__global__ __launch_bounds__(kBlock) void k_cic_units(const float *__restrict__ pos, const double *__restrict__ mass,
+                                                        const uint32_t *__restrict__ perm,
+                                                        const uint4 *__restrict__ units,
+                                                        const uint32_t *__restrict__ total, int lg, double h,
+                                                        double *__restrict__ m, int *__restrict__ flag)
 {
     __shared__ double win[kWin3];
-    __shared__ int red[kBlock / 64];
     const int tid = threadIdx.x;
-    const int64_t start = (int64_t)blockIdx.x * kCicChunk;
-    const int64_t end = start + kCicChunk < np ? start + kCicChunk : np;
     const int mask = (1 << lg) - 1, tl = lg - kBinLg, tmask = (1 << tl) - 1;
-    uint32_t key[kCicPer];
-    float px[kCicPer], py[kCicPer], pz[kCicPer];
-    double pm[kCicPer];
-#pragma unroll
-    for (int s = 0; s < kCicPer; ++s) {
-        const int64_t i = start + tid + (int64_t)s * kBlock;
-        key[s] = 0xffffffffu;  // above every tile key
-        px[s] = py[s] = pz[s] = 0.0f;
-        pm[s] = 0.0;
-        if (i < end) {
-            key[s] = key_s[i];
-            const size_t p = perm[i];
-            px[s] = pos[3 * p + 0];
-            py[s] = pos[3 * p + 1];
-            pz[s] = pos[3 * p + 2];
-            pm[s] = mass ? mass[p] : 1.0;
-        }
-    }
+    const double r = 1.0 / h;
+    const uint32_t U = *total;
     for (int e = tid; e < kWin3; e += kBlock) win[e] = 0.0;
-    int64_t cur = start;
-    while (cur < end) {
-        const uint32_t t = key_s[cur];
-        // slots before cur hold smaller keys, so the run ends at start + #(key <= t)
-        int cnt = 0;
+    for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
+        const uint4 d = units[u];
+        const int ti = (int)(d.x >> (2 * tl)) << kBinLg, tj = (int)((d.x >> tl) & tmask) << kBinLg,
+                  tk = (int)(d.x & tmask) << kBinLg;
+        float px[kUnitPer], py[kUnitPer], pz[kUnitPer];
+        double pm[kUnitPer];
+        bool live[kUnitPer];
 #pragma unroll
-        for (int s = 0; s < kCicPer; ++s) cnt += key[s] <= t ? 1 : 0;
-        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-        if ((tid & 63) == 0) red[tid >> 6] = cnt;
-        __syncthreads();
-        int total = 0;
+        for (int q = 0; q < kUnitPer; ++q) {
+            const uint32_t sl = d.y + tid + q * kBlock;
+            live[q] = sl < d.z;
+            px[q] = py[q] = pz[q] = 0.0f;
+            pm[q] = 0.0;
+            if (live[q]) {
+                const size_t p = perm[sl];
+                px[q] = pos[3 * p + 0];
+                py[q] = pos[3 * p + 1];
+                pz[q] = pos[3 * p + 2];
+                pm[q] = mass ? mass[p] : 1.0;
+            }
+        }
+        __syncthreads();  // the window is clear
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) total += red[w];
-        const int64_t rend = start + total > cur ? start + total : cur + 1;
-        const int ti = (int)(t >> (2 * tl)) << kBinLg, tj = (int)((t >> tl) & tmask) << kBinLg,
-                  tk = (int)(t & tmask) << kBinLg;
-#pragma unroll
-        for (int s = 0; s < kCicPer; ++s) {
-            if (key[s] != t) continue;
-            int i0, j0, k0;
-            double tx, ty, tz;
-            const bool ok = cic_axis(px[s], h, mask, i0, tx) && cic_axis(py[s], h, mask, j0, ty) &&
-                            cic_axis(pz[s], h, mask, k0, tz) && isfinite(pm[s]);
+        for (int q = 0; q < kUnitPer; ++q) {
+            if (!live[q]) continue;
+            int i0 = 0, j0 = 0, k0 = 0;
+            double tx = 0.0, ty = 0.0, tz = 0.0;
+            const bool ok = cic_axis_r(px[q], h, r, mask, i0, tx) & cic_axis_r(py[q], h, r, mask, j0, ty) &
+                            cic_axis_r(pz[q], h, r, mask, k0, tz) & (bool)isfinite(pm[q]);
             const int a = i0 - ti, b = j0 - tj, c = k0 - tk;
             if (!ok || (unsigned)a >= (1u << kBinLg) || (unsigned)b >= (1u << kBinLg) ||
                 (unsigned)c >= (1u << kBinLg)) {
                 flag[0] = 1;
                 continue;
             }
-            const double mp = pm[s];
+            const double mp = pm[q];
             const double wx0 = (1.0 - tx) * mp, wx1 = tx * mp, wy0 = 1.0 - ty, wy1 = ty, wz0 = 1.0 - tz, wz1 = tz;
             double *w0 = win + (a * kWin + b) * kWin + c;
             atomicAdd(w0, wx0 * wy0 * wz0);
@@ -122,6 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_cic_binned(const float *__restrict__
             atomicAdd(w0 + kWin * kWin + kWin + 1, wx1 * wy1 * wz1);
         }
         __syncthreads();
+        // flush, clearing what was flushed for the next unit
         for (int e = tid; e < kWin3; e += kBlock) {
             const double v = win[e];
             if (v != 0.0) {
@@ -132,8 +121,6 @@ __global__ __launch_bounds__(kBlock) void k_cic_binned(const float *__restrict__
                 win[e] = 0.0;
             }
         }
-        __syncthreads();
-        cur = rend;
     }
 }
 
@@ -264,100 +251,119 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const double *__restric
 
 constexpr int kFW = (1 << kBinLg) + 3;  // f_R window edge: a tile plus one cell below and two above
 constexpr int kFW3 = kFW * kFW * kFW;
-constexpr int kFWinMin = 48;             // shorter runs read f_R from global memory
+constexpr int kFWinMin = 48;             // smaller units read f_R from global memory
 
-// The fifth force for binned particles: the same chunks and tile runs as the
-// binned assignment; a run of at least kFWinMin particles first stages the
-// tile's f_R window (11^3 values) in LDS and gathers from there.  A particle
-// whose current position is not in the run's tile (positions changed since
-// the assignment) is gathered from global memory, so any positions give the
-// same result as k_force_gather.
-__global__ __launch_bounds__(kBlock) void k_force_binned(const double *__restrict__ fr, const float *__restrict__ pos,
-                                                           const uint32_t *__restrict__ key_s,
-                                                           const uint32_t *__restrict__ perm, int64_t np, int lg,
-                                                           double h, double pref, float *__restrict__ acc,
-                                                           int *__restrict__ flag)
+// The gradient sum of one particle read from global memory: the rare particle
+// whose current position has left the tile it was binned in (positions changed
+// since the binning).  Out of line and one block cell at a time, so that it
+// adds neither registers nor code to the window path; the terms are those of
+// grad_sum, in its order.
+__device__ __noinline__ double3 grad_sum_global(const double *__restrict__ fr, int lg, int i0, int j0, int k0,
+                                                double tx, double ty, double tz)
+{
+    const int mask = (1 << lg) - 1;
+    auto at = [&](int di, int dj, int dk) {
+        return fr[(((((size_t)((i0 + di) & mask)) << lg) + (size_t)((j0 + dj) & mask)) << lg) +
+                  (size_t)((k0 + dk) & mask)];
+    };
+    double3 g = make_double3(0.0, 0.0, 0.0);
+#pragma unroll 1
+    for (int e = 0; e < 8; ++e) {
+        const int a = e >> 2, b = (e >> 1) & 1, c = e & 1;
+        const double w = (a ? tx : 1.0 - tx) * (b ? ty : 1.0 - ty) * (c ? tz : 1.0 - tz);
+        g.x += w * (at(a + 1, b, c) - at(a - 1, b, c));
+        g.y += w * (at(a, b + 1, c) - at(a, b - 1, c));
+        g.z += w * (at(a, b, c + 1) - at(a, b, c - 1));
+    }
+    return g;
+}
+
+// The fifth force for binned particles: a workgroup takes one work unit at a
+// time (up to kUnit particles of one tile), stages the tile's f_R window
+// (11^3 values: one cell below the tile, two above) in LDS, loaded together
+// with the unit's particles, and gathers from there (units of fewer than
+// kFWinMin particles gather from global memory).  Any positions give the same
+// result as k_force_gather.
+__global__ __launch_bounds__(kBlock) void k_force_units(const double *__restrict__ fr, const float *__restrict__ pos,
+                                                          const uint32_t *__restrict__ perm,
+                                                          const uint4 *__restrict__ units,
+                                                          const uint32_t *__restrict__ total, int lg, double h,
+                                                          double pref, float *__restrict__ acc,
+                                                          int *__restrict__ flag)
 {
     __shared__ double win[kFW3];
-    __shared__ int red[kBlock / 64];
-    // the chunk's slots (sorted order), kept in LDS so that the slot loop need
-    // not be unrolled (two 32-load gathers per slot would not fit in registers)
-    __shared__ uint32_t skey[kCicPer][kBlock], spid[kCicPer][kBlock];
-    __shared__ float spos[kCicPer][3][kBlock];
     const int tid = threadIdx.x;
-    const int64_t start = (int64_t)blockIdx.x * kCicChunk;
-    const int64_t end = start + kCicChunk < np ? start + kCicChunk : np;
     const int mask = (1 << lg) - 1, tl = lg - kBinLg, tmask = (1 << tl) - 1;
-    const double s = pref / (2.0 * h);
-    for (int q = 0; q < kCicPer; ++q) {
-        const int64_t i = start + tid + (int64_t)q * kBlock;
-        uint32_t k = 0xffffffffu, pp = 0;
-        float x = 0.f, y = 0.f, z = 0.f;
-        if (i < end) {
-            k = key_s[i];
-            pp = perm[i];
-            x = pos[3 * (size_t)pp + 0];
-            y = pos[3 * (size_t)pp + 1];
-            z = pos[3 * (size_t)pp + 2];
-        }
-        skey[q][tid] = k;
-        spid[q][tid] = pp;
-        spos[q][0][tid] = x;
-        spos[q][1][tid] = y;
-        spos[q][2][tid] = z;
-    }
-    int64_t cur = start;
-    while (cur < end) {
-        const uint32_t t = key_s[cur];
-        int cnt = 0;
-        for (int q = 0; q < kCicPer; ++q) cnt += skey[q][tid] <= t ? 1 : 0;
-        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-        if ((tid & 63) == 0) red[tid >> 6] = cnt;
-        __syncthreads();
-        int total = 0;
+    const double s = pref / (2.0 * h), r = 1.0 / h;
+    const uint32_t U = *total;
+    constexpr int kFWPer = (kFW3 + kBlock - 1) / kBlock;  // window values staged per thread
+    for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
+        const uint4 d = units[u];
+        const int ti = (int)(d.x >> (2 * tl)) << kBinLg, tj = (int)((d.x >> tl) & tmask) << kBinLg,
+                  tk = (int)(d.x & tmask) << kBinLg;
+        const bool use_win = d.z - d.y >= (uint32_t)kFWinMin;  // uniform over the workgroup
+        // the window through registers, loaded together with the particles
+        double wv[kFWPer];
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) total += red[w];
-        const int64_t rend = start + total > cur ? start + total : cur + 1;
-        const bool use_win = rend - cur >= kFWinMin;  // uniform over the workgroup
-        const int ti = (int)(t >> (2 * tl)) << kBinLg, tj = (int)((t >> tl) & tmask) << kBinLg,
-                  tk = (int)(t & tmask) << kBinLg;
-        if (use_win)
-            for (int e = tid; e < kFW3; e += kBlock) {
+        for (int q = 0; q < kFWPer; ++q) {
+            const int e = tid + q * kBlock;
+            wv[q] = 0.0;
+            if (use_win && e < kFW3) {
                 const int a = e / (kFW * kFW), b = (e / kFW) % kFW, c = e % kFW;
-                win[e] = fr[(((((size_t)((ti - 1 + a) & mask)) << lg) + (size_t)((tj - 1 + b) & mask)) << lg) +
-                            (size_t)((tk - 1 + c) & mask)];
+                wv[q] = fr[(((((size_t)((ti - 1 + a) & mask)) << lg) + (size_t)((tj - 1 + b) & mask)) << lg) +
+                           (size_t)((tk - 1 + c) & mask)];
             }
+        }
+        uint32_t pid[kUnitPer];
+        float px[kUnitPer], py[kUnitPer], pz[kUnitPer];
+#pragma unroll
+        for (int q = 0; q < kUnitPer; ++q) {
+            const uint32_t sl = d.y + tid + q * kBlock;
+            pid[q] = 0xffffffffu;
+            px[q] = py[q] = pz[q] = 0.0f;
+            if (sl < d.z) {
+                pid[q] = perm[sl];
+                px[q] = pos[3 * (size_t)pid[q] + 0];
+                py[q] = pos[3 * (size_t)pid[q] + 1];
+                pz[q] = pos[3 * (size_t)pid[q] + 2];
+            }
+        }
+        __syncthreads();  // the previous unit's gathers are done
+        if (use_win) {
+#pragma unroll
+            for (int q = 0; q < kFWPer; ++q)
+                if (tid + q * kBlock < kFW3) win[tid + q * kBlock] = wv[q];
+        }
         __syncthreads();
-#pragma unroll 1
-        for (int q = 0; q < kCicPer; ++q) {
-            if (skey[q][tid] != t) continue;
-            const int64_t p = spid[q][tid];
-            int i0, j0, k0;
-            double tx, ty, tz;
-            if (!(cic_axis(spos[q][0][tid], h, mask, i0, tx) && cic_axis(spos[q][1][tid], h, mask, j0, ty) &&
-                  cic_axis(spos[q][2][tid], h, mask, k0, tz))) {
+#pragma unroll
+        for (int q = 0; q < kUnitPer; ++q) {
+            if (pid[q] == 0xffffffffu) continue;
+            const size_t p = pid[q];
+            int i0 = 0, j0 = 0, k0 = 0;
+            double tx = 0.0, ty = 0.0, tz = 0.0;
+            if (!(cic_axis_r(px[q], h, r, mask, i0, tx) & cic_axis_r(py[q], h, r, mask, j0, ty) &
+                  cic_axis_r(pz[q], h, r, mask, k0, tz))) {
                 flag[0] = 1;
-                store_nan3(acc, p);
+                store_nan3(acc, (int64_t)p);
                 continue;
             }
             const int a0 = i0 - ti, b0 = j0 - tj, c0 = k0 - tk;
             double gx, gy, gz;
             if (use_win && (unsigned)a0 < (1u << kBinLg) && (unsigned)b0 < (1u << kBinLg) &&
-                (unsigned)c0 < (1u << kBinLg)) {
-                grad_sum([&](int di, int dj, int dk) { return win[((a0 + di + 1) * kFW + (b0 + dj + 1)) * kFW + (c0 + dk + 1)]; },
-                         tx, ty, tz, gx, gy, gz);
-            } else {
+                (unsigned)c0 < (1u << kBinLg))
                 grad_sum([&](int di, int dj, int dk) {
-                    return fr[(((((size_t)((i0 + di) & mask)) << lg) + (size_t)((j0 + dj) & mask)) << lg) +
-                              (size_t)((k0 + dk) & mask)];
+                    return win[((a0 + di + 1) * kFW + (b0 + dj + 1)) * kFW + (c0 + dk + 1)];
                 }, tx, ty, tz, gx, gy, gz);
+            else {
+                const double3 g = grad_sum_global(fr, lg, i0, j0, k0, tx, ty, tz);
+                gx = g.x;
+                gy = g.y;
+                gz = g.z;
             }
             acc[3 * p + 0] = (float)(s * gx);
             acc[3 * p + 1] = (float)(s * gy);
             acc[3 * p + 2] = (float)(s * gz);
         }
-        __syncthreads();
-        cur = rend;
     }
 }
 
@@ -420,8 +426,8 @@ extern "C" int mgfr_assign_density(mgfr_ctx *c, const float *pos, const double *
     c->perm_np = 0;
     if (c->binning && np <= c->bin_cap) {
         if (int e = bin_particles(c, pos, np)) return e;
-        k_cic_binned<<<(unsigned)((np + kCicChunk - 1) / kCicChunk), kBlock, 0, c->stream>>>(
-            pos, mass, c->bkey_s, c->perm, np, L0.lg, L0.h, delta, c->dflag);
+        k_cic_units<<<c->unit_grid, kBlock, 0, c->stream>>>(pos, mass, c->perm, c->units, c->unit_total, L0.lg,
+                                                             L0.h, delta, c->dflag);
     } else {
         k_cic_scatter<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(pos, mass, np, L0.lg, L0.h, delta, c->dflag);
     }
@@ -455,8 +461,8 @@ extern "C" int mgfr_fifth_force(mgfr_ctx *c, const double *u, const float *pos, 
     if (pblocks > 0x7fffffffULL) return set_error(MGFR_ERR_ARG, "np too large");
     const double pref = kCkms * kCkms / (2.0 * c->p.a);
     if (c->perm_np == np && c->perm) {
-        k_force_binned<<<(unsigned)((np + kCicChunk - 1) / kCicChunk), kBlock, 0, c->stream>>>(
-            fr, pos, c->bkey_s, c->perm, np, L0.lg, L0.h, pref, acc, c->dflag);
+        k_force_units<<<c->unit_grid, kBlock, 0, c->stream>>>(fr, pos, c->perm, c->units, c->unit_total, L0.lg,
+                                                               L0.h, pref, acc, c->dflag);
     } else {
         k_force_gather<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(fr, pos, nullptr, np, L0.lg, L0.h, pref, acc,
                                                                      c->dflag);
@@ -486,8 +492,8 @@ extern "C" int mgfr_pm_accel(mgfr_ctx *c, const double *delta, const double *u, 
     if (pblocks > 0x7fffffffULL) return set_error(MGFR_ERR_ARG, "np too large");
     const double pref = -1.0 / c->p.a;
     if (c->perm_np == np && c->perm) {
-        k_force_binned<<<(unsigned)((np + kCicChunk - 1) / kCicChunk), kBlock, 0, c->stream>>>(
-            psi, pos, c->bkey_s, c->perm, np, L0.lg, L0.h, pref, acc, c->dflag);
+        k_force_units<<<c->unit_grid, kBlock, 0, c->stream>>>(psi, pos, c->perm, c->units, c->unit_total, L0.lg,
+                                                               L0.h, pref, acc, c->dflag);
     } else {
         k_force_gather<<<(unsigned)pblocks, kBlock, 0, c->stream>>>(psi, pos, nullptr, np, L0.lg, L0.h, pref, acc,
                                                                      c->dflag);

@@ -401,6 +401,31 @@ def test_fifth_force_after_binned_assignment():
         assert np.all(np.abs(acc - ref) <= 6.0e-8 * np.abs(ref) + 1e-10 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("N", [8, 64])
+def test_fifth_force_binned_dense_clump(N):
+    """The binned force where one tile holds tens of thousands of particles (its
+    slots cut into many work units) beside sparse tiles that gather from global
+    memory; at N = 8 the whole mesh is one tile and its f_R window wraps."""
+    mg = _mg()
+    print(f"[case] binned force, dense clump N={N}", flush=True)
+    rng = np.random.default_rng(100 + N)
+    h = 100.0 / N
+    clump = (37.3 + rng.normal(0.0, 0.6 * h, (23001, 3))).astype(np.float32)
+    back = rng.uniform(0.0, 100.0, (3011, 3)).astype(np.float32)
+    pos = np.concatenate([back[:1000], clump, back[1000:]])
+    s = mg.Solver(_params(mg, N, fr0_abs=1e-5))
+    ref_d = O.density_contrast(O.cic_assign(N, 100.0, pos))
+    d = s.assign_density(torch.tensor(pos, device=DEV)).cpu().numpy()
+    assert np.abs(d - ref_d).max() < 1e-12 * max(1.0, np.abs(ref_d).max())
+    x = 2.0 * np.pi * np.arange(N) / N
+    u_o = (0.3 * np.sin(x)[:, None, None] + 0.2 * np.cos(2 * x)[None, :, None]
+           + 0.1 * np.sin(3 * x)[None, None, :]) - 0.001 * np.tanh(ref_d)
+    ref = O.fifth_force(O.params(mesh=N, fr0_abs=1e-5), u_o, pos)
+    acc = s.fifth_force(torch.tensor(u_o, device=DEV), torch.tensor(pos, device=DEV)).cpu().numpy()
+    acc = acc.astype(np.float64)
+    assert np.all(np.abs(acc - ref) <= 6.0e-8 * np.abs(ref) + 1e-10 * np.abs(ref).max())
+
+
 # ----------------------------------------------------------------- error behaviour
 
 def test_nonfinite_delta_rejected_and_arguments_validated():

@@ -242,7 +242,7 @@ def run_mode(mode, args, pos, dev, log, a=None, dfr_ref=None):
         solver.assign_density(pos, out=delta)
         if screened:
             solver.screened_guess(delta, out=u)
-        else:
+        elif nn_mode != mgfr.NN_COARSE:  # the network's guess overwrites u
             u.zero_()
         _, dfr, st = solver.solve(delta, u=u, want_dfr=True)
         solver.fifth_force(u, pos, out=acc)

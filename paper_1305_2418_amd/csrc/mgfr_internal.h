@@ -139,7 +139,10 @@ constexpr int kWin = (1 << kBinLg) + 1;           // LDS window edge: a tile plu
 constexpr int kWin3 = kWin * kWin * kWin;
 // The binned particle kernels work on units: up to kUnit sorted slots of one
 // tile (a tile with more particles is split), kUnit / kBlock per thread.
-constexpr int kUnit = 1024;
+#ifndef MGFR_UNIT
+#define MGFR_UNIT 1024
+#endif
+constexpr int kUnit = MGFR_UNIT;
 constexpr int kUnitPer = kUnit / kBlock;
 int bin_reserve(mgfr_ctx *c, int64_t np);
 int bin_particles(mgfr_ctx *c, const float *pos, int64_t np);  // counting sort by tile; sets perm_np

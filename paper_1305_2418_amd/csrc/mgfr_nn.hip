@@ -510,12 +510,30 @@ __global__ void k_restrict_mean(const double *__restrict__ fine, int lgc, double
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_prolong_field(double *__restrict__ u, const double *__restrict__ uc,
-                                                            const double *__restrict__ zero, int lgc)
+// u = P(uc) on the finer mesh: the linear reconstruction (parent value plus
+// the central-difference gradient, Sec. 3.3), stored (no clearing pass)
+__global__ __launch_bounds__(kBlock) void k_prolong_field_set(double *__restrict__ u, const double *__restrict__ uc,
+                                                                int lgc)
 {
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)), I = (int)(t >> (2 * lgc));
-    prolong_block(u, uc, zero, I, J, K, lgc, 0);
+    const int m = (1 << lgc) - 1, lg = lgc + 1;
+    const double v0 = uc[cidx(I, J, K, lgc)];
+    const double gx = uc[cidx((I + 1) & m, J, K, lgc)] - uc[cidx((I - 1) & m, J, K, lgc)];
+    const double gy = uc[cidx(I, (J + 1) & m, K, lgc)] - uc[cidx(I, (J - 1) & m, K, lgc)];
+    const double gz = uc[cidx(I, J, (K + 1) & m, lgc)] - uc[cidx(I, J, (K - 1) & m, lgc)];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double v = v0;
+                v += (a ? 0.125 : -0.125) * gx;
+                v += (b ? 0.125 : -0.125) * gy;
+                v += (c ? 0.125 : -0.125) * gz;
+                u[cidx(2 * I + a, 2 * J + b, 2 * K + c, lg)] = v;
+            }
 }
 
 inline unsigned gridn(size_t n, unsigned cap = 16384) { return (unsigned)std::min<size_t>((n + 255) / 256, cap); }
@@ -1112,15 +1130,10 @@ int nn_warm_start(mgfr_ctx *c, const double *delta, double *u, double *t_ms)
             if ((rc = vcycle64(c, 2))) return rc;
     }
     // prolong twice with the linear reconstruction (Sec. 3.3)
-    MGFR_HIP(hipMemsetAsync(L2.ubar, 0, n2 * sizeof(double), c->stream));
-    MGFR_HIP(hipMemsetAsync(L1.u, 0, n1 * sizeof(double), c->stream));
-    k_prolong_field<<<(unsigned)((n2 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(L1.u, L2.u, L2.ubar, lg2);
+    k_prolong_field_set<<<(unsigned)((n2 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(L1.u, L2.u, lg2);
     for (int k = 0; k < cc; ++k)
         if ((rc = vcycle64(c, 1))) return rc;
-    MGFR_HIP(hipMemsetAsync(L1.ubar, 0, n1 * sizeof(double), c->stream));
-    const size_t n0 = (size_t)c->lev[0].N * c->lev[0].N * c->lev[0].N;
-    MGFR_HIP(hipMemsetAsync(u, 0, n0 * sizeof(double), c->stream));
-    k_prolong_field<<<(unsigned)((n1 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(u, L1.u, L1.ubar, L1.lg);
+    k_prolong_field_set<<<(unsigned)((n1 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(u, L1.u, L1.lg);
     MGFR_HIP(hipGetLastError());
     MGFR_HIP(hipEventRecord(c->ev_b, c->stream));
     MGFR_HIP(hipEventSynchronize(c->ev_b));

@@ -60,6 +60,7 @@ struct mgfr_ctx {
     double omega_now = 1.0;   // the factor in use (set to 1 once the outer residual grows)
     int inner_max = 1;        // float32 correction V-cycles per float64 residual check, at most
     int smooth_max = 0;       // adaptive smoothing: sweeps double up to this when the residual stalls (0: off)
+    bool e32_zero = false;    // level-0 e32 is zero but not cleared: its first colour pass writes it
     // reduction scratch
     double *partial = nullptr;  // [2 * nparts]
     int nparts = 0;

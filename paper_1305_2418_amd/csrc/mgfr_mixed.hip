@@ -320,7 +320,10 @@ struct ColourArgs {
 };
 
 // The plane loop of one wave whose updated column in the first plane is S0.
-template <int S0>
+// ZERO: e is zero everywhere (the first pass of a correction cycle): nothing
+// of e is read, and the cells of the other colour are written as 0, so that
+// the array need not be cleared beforehand.
+template <int S0, bool ZERO>
 __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int j0, int k0, int wv, int lane,
                                                float4 *sB)
 {
@@ -339,6 +342,7 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
     // u in natural order; e and r split by colour (column 0 of plane pl lies in half (pl + jg) & 1)
     auto ldu = [&](int pl) { return at_off<float2>(A.u + pb(pl), kk); };
     auto lde = [&](int pl) {
+        if constexpr (ZERO) return make_float2(0.0f, 0.0f);
         const bool odd = ((pl + jg) & 1) != 0;
         const float *h0 = A.e + pb(pl) + (odd ? hN : 0), *h1 = A.e + pb(pl) + (odd ? 0 : hN);
         return make_float2(at_off<float>(h0, kh2), at_off<float>(h1, kh2));
@@ -382,7 +386,7 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
         w.e = lde(p + 1);
         w.r = at_off<float>(row_r(p), kh2);
         w.khu = A.u[kh_u(p)];
-        w.khe = A.e[kh_e(p)];
+        w.khe = ZERO ? 0.0f : A.e[kh_e(p)];
         return w;
     };
     Raw ra = load(i0), rb = kColourPf >= 2 ? load(i0 + 1) : Raw{}, rc = kColourPf == 3 ? load(i0 + 2) : Raw{}, rd;
@@ -405,6 +409,7 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
             const float en = S ? mx_update(c1, cur.r, c0, sd, up, dn, prev, n1, A.kc)
                                : mx_update(c0, cur.r, c1, sd, up, dn, prev, n0, A.kc);
             at_off<float>(row_c(p), kh2) = en;
+            if constexpr (ZERO) at_off<float>(A.e + pb(p) + (size_t)(1 - A.colour) * hN, kh2) = 0.0f;
         }
         prev = S ? c0 : c1;
         c0 = n0;
@@ -437,9 +442,9 @@ __device__ __forceinline__ void mx_colour_rows(const ColourArgs &A, int i0, int 
 
 // grid: 1-D, (N / CKW) ceil(N / CTJ) (N / chunk) workgroups, spread so that
 // workgroups adjacent in j run on the same XCD (they share halo rows)
-__global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour(ColourArgs A)
+template <bool ZERO>
+__device__ __forceinline__ void mx_colour_pass(const ColourArgs &A, float4 *sB)
 {
-    __shared__ float4 sB[2 * (CTJ + 2) * CLW];
     const int lg = A.lg;
     const unsigned nb = gridDim.x, b = blockIdx.x;
     const unsigned L = (b & 7u) * (nb >> 3) + (b >> 3);  // nb is a multiple of 8
@@ -451,9 +456,22 @@ __global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour(ColourArgs A)
     const int lane = threadIdx.x & 63;
     const int s0 = (A.colour + i0 + j0 + wv - 1) & 1;  // updated column of this wave's row in plane i0
     if (s0)
-        mx_colour_rows<1>(A, i0, j0, k0, wv, lane, sB);
+        mx_colour_rows<1, ZERO>(A, i0, j0, k0, wv, lane, sB);
     else
-        mx_colour_rows<0>(A, i0, j0, k0, wv, lane, sB);
+        mx_colour_rows<0, ZERO>(A, i0, j0, k0, wv, lane, sB);
+}
+
+__global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour(ColourArgs A)
+{
+    __shared__ float4 sB[2 * (CTJ + 2) * CLW];
+    mx_colour_pass<false>(A, sB);
+}
+
+// the first pass of a correction cycle, from e = 0
+__global__ __launch_bounds__(64 * (CTJ + 2)) void k_mx_colour_zero(ColourArgs A)
+{
+    __shared__ float4 sB[2 * (CTJ + 2) * CLW];
+    mx_colour_pass<true>(A, sB);
 }
 
 // ------------------------------------------- fused red-black sweep (N >= 128)
@@ -1268,8 +1286,14 @@ int mx_launch_sweeps(mgfr_ctx *c, int l, int sweeps, bool timed)
             const int chunk = L.N / kChunks;
             const unsigned nb = (unsigned)((L.N / CKW) * ((L.N + CTJ - 1) / CTJ) * kChunks);
             for (int colour = 0; colour < 2; ++colour) {
+                const ColourArgs A{L.e32, L.u32, L.r32, L.lg, colour, chunk, kc};
+                if (l == 0 && c->e32_zero) {  // first pass after a float64 check; not timed
+                    k_mx_colour_zero<<<nb, 64 * (CTJ + 2), 0, c->stream>>>(A);
+                    c->e32_zero = false;
+                    continue;
+                }
                 if ((rc = timer_slot(c, timed, slot))) return rc;
-                k_mx_colour<<<nb, 64 * (CTJ + 2), 0, c->stream>>>(ColourArgs{L.e32, L.u32, L.r32, L.lg, colour, chunk, kc});
+                k_mx_colour<<<nb, 64 * (CTJ + 2), 0, c->stream>>>(A);
                 if ((rc = timer_end(c, slot))) return rc;
             }
         } else {
@@ -1408,7 +1432,10 @@ static int outer_step(mgfr_ctx *c, bool add_e, double *rmax, double *rsq)
     else
         k_mx_correct_residual<false><<<g, 64 * (RTJ + 2), 0, c->stream>>>(A);
     if (add_e) std::swap(L0.u, L0.alt);
-    MGFR_HIP(hipMemsetAsync(L0.e32, 0, n * sizeof(float), c->stream));
+    // e = 0: cleared here, or by the first colour pass of the next cycle, which
+    // then reads no e and writes the cells it does not update as 0
+    c->e32_zero = split_level(c, 0) && c->p.pre_smooth >= 1 && !(c->fused32 && L0.e32alt);
+    if (!c->e32_zero) MGFR_HIP(hipMemsetAsync(L0.e32, 0, n * sizeof(float), c->stream));
     k_mx_final<<<1, 1024, 0, c->stream>>>(c->partial, g, c->dscal);
     MGFR_HIP(hipGetLastError());
     MGFR_HIP(hipMemcpyAsync(c->hscal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -950,57 +950,110 @@ struct MxTail {
     float bC, q, max_du, omega;
 };
 
-__device__ void mx_tail_sweeps(const MxTail &A, int l, int sweeps)
+// The tail (levels with N <= kTailN: 16^3, 8^3, 4^3) runs in one workgroup
+// with every array in LDS: e, u and r of its top level are copied in and e is
+// copied out at the end; the coarser levels' arrays (e, u, r and the restricted
+// e) live only here.  Level l0 + k holds 2^(3 (lg0 - k)) cells; its arrays sit
+// after those of the finer levels (three at l0, four below).
+constexpr int kTailLdsFloats = 3 * (1 << 12) + 4 * (1 << 9) + 4 * (1 << 6);
+static_assert(kTailN <= 16, "the tail's LDS holds levels up to 16^3");
+
+struct TailLds {
+    float *lds;
+    int l0, lg0;
+    __device__ int cells(int l) const { return 1 << (3 * (lg0 - (l - l0))); }
+    __device__ float *base(int l) const
+    {
+        int off = 0;
+        if (l > l0) {
+            off = 3 * cells(l0);
+            for (int k = l0 + 1; k < l; ++k) off += 4 * cells(k);
+        }
+        return lds + off;
+    }
+    __device__ float *e(int l) const { return base(l); }
+    __device__ float *u(int l) const { return base(l) + cells(l); }
+    __device__ float *r(int l) const { return base(l) + 2 * cells(l); }
+    __device__ float *eb(int l) const { return base(l) + 3 * cells(l); }  // l > l0
+};
+
+// Red-black sweeps of one tail level.  The 4^3 level (32 cells per colour) is
+// swept by the first wave alone: within one wave the LDS accesses of a
+// half-sweep are done before the next one's, and the fences keep the compiler
+// from moving them, so no workgroup barrier is needed per half-sweep.
+__device__ void mx_tail_sweeps(const MxTail &A, const TailLds &T, int l, int sweeps)
 {
     const MxConst kc{A.ih2[l], A.bC, A.q, A.max_du, A.omega};
     const int lg = A.lg[l];
-    const size_t half = (size_t)1 << (3 * lg - 1);
+    const int half = 1 << (3 * lg - 1);
+    float *e = T.e(l);
+    const float *u = T.u(l), *r = T.r(l);
+    if (half <= 32) {  // uniform
+        if (threadIdx.x < 64)
+            for (int s = 0; s < sweeps; ++s)
+                for (int colour = 0; colour < 2; ++colour) {
+                    if ((int)threadIdx.x < half) mx_sweep_cell(e, u, r, threadIdx.x, lg, colour, kc);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                }
+        __syncthreads();
+        return;
+    }
     for (int s = 0; s < sweeps; ++s)
         for (int colour = 0; colour < 2; ++colour) {
-            for (size_t t = threadIdx.x; t < half; t += kTailThreads) mx_sweep_cell(A.e[l], A.u[l], A.r[l], t, lg, colour, kc);
+            for (int t = threadIdx.x; t < half; t += kTailThreads) mx_sweep_cell(e, u, r, t, lg, colour, kc);
             __syncthreads();
         }
 }
 
 __global__ __launch_bounds__(kTailThreads) void k_mx_tail(MxTail A)
 {
+    __shared__ float lds[kTailLdsFloats];
+    const TailLds T{lds, A.l0, A.lg[A.l0]};
+    const int n0 = T.cells(A.l0);
+    for (int t = threadIdx.x; t < n0; t += kTailThreads) {
+        T.e(A.l0)[t] = A.e[A.l0][t];
+        T.u(A.l0)[t] = A.u[A.l0][t];
+        T.r(A.l0)[t] = A.r[A.l0][t];
+    }
+    __syncthreads();
     for (int l = A.l0; l < A.nlev - 1; ++l) {
-        mx_tail_sweeps(A, l, A.pre);
+        mx_tail_sweeps(A, T, l, A.pre);
         const MxConst kc{A.ih2[l], A.bC, A.q, A.max_du};
         const int lg = A.lg[l], lgc = lg - 1;
-        const size_t nc = (size_t)1 << (3 * lgc);
-        for (size_t t = threadIdx.x; t < nc; t += kTailThreads) {
-            const int K = (int)(t & ((1u << lgc) - 1)), J = (int)((t >> lgc) & ((1u << lgc) - 1)),
-                      I = (int)(t >> (2 * lgc));
+        const int nc = 1 << (3 * lgc);
+        for (int t = threadIdx.x; t < nc; t += kTailThreads) {
+            const int K = t & ((1 << lgc) - 1), J = (t >> lgc) & ((1 << lgc) - 1), I = t >> (2 * lgc);
             float em, um, rm;
-            mx_restrict_cell(A.e[l], A.u[l], A.r[l], I, J, K, lg, kc, em, um, rm);
-            A.eb[l + 1][t] = em;
-            A.u[l + 1][t] = um;
-            A.r[l + 1][t] = rm;
+            mx_restrict_cell(T.e(l), T.u(l), T.r(l), I, J, K, lg, kc, em, um, rm);
+            T.eb(l + 1)[t] = em;
+            T.u(l + 1)[t] = um;
+            T.r(l + 1)[t] = rm;
         }
         __syncthreads();
         const MxConst kcc{A.ih2[l + 1], A.bC, A.q, A.max_du};
         const int mc = (1 << lgc) - 1;
-        for (size_t t = threadIdx.x; t < nc; t += kTailThreads) {
-            const int k = (int)(t & mc), j = (int)((t >> lgc) & mc), i = (int)(t >> (2 * lgc));
-            A.r[l + 1][t] += mx_value_at(A.eb[l + 1], A.u[l + 1], i, j, k, lgc, kcc);
+        for (int t = threadIdx.x; t < nc; t += kTailThreads) {
+            const int k = t & mc, j = (t >> lgc) & mc, i = t >> (2 * lgc);
+            T.r(l + 1)[t] += mx_value_at(T.eb(l + 1), T.u(l + 1), i, j, k, lgc, kcc);
         }
         __syncthreads();
-        for (size_t t = threadIdx.x; t < nc; t += kTailThreads) A.e[l + 1][t] = A.eb[l + 1][t];
+        for (int t = threadIdx.x; t < nc; t += kTailThreads) T.e(l + 1)[t] = T.eb(l + 1)[t];
         __syncthreads();
     }
-    mx_tail_sweeps(A, A.nlev - 1, A.coarse);
+    mx_tail_sweeps(A, T, A.nlev - 1, A.coarse);
     for (int l = A.nlev - 2; l >= A.l0; --l) {
         const int lg = A.lg[l];
-        const size_t n = (size_t)1 << (3 * lg);
+        const int n = 1 << (3 * lg);
         const int m = (1 << lg) - 1;
-        for (size_t t = threadIdx.x; t < n; t += kTailThreads) {
-            const int k = (int)(t & m), j = (int)((t >> lg) & m), i = (int)(t >> (2 * lg));
-            A.e[l][t] += mx_prolong(A.e[l + 1], A.eb[l + 1], i, j, k, lg - 1, A.mode);
+        for (int t = threadIdx.x; t < n; t += kTailThreads) {
+            const int k = t & m, j = (t >> lg) & m, i = t >> (2 * lg);
+            T.e(l)[t] += mx_prolong(T.e(l + 1), T.eb(l + 1), i, j, k, lg - 1, A.mode);
         }
         __syncthreads();
-        mx_tail_sweeps(A, l, A.post);
+        mx_tail_sweeps(A, T, l, A.post);
     }
+    for (int t = threadIdx.x; t < n0; t += kTailThreads) A.e[A.l0][t] = T.e(A.l0)[t];
 }
 
 // float64 residual of u on the finest level, its float32 copies for the inner

@@ -94,12 +94,14 @@ def _hash(files):
 def traffic(dfetch, dwrite, mesh, out):
     fa, wa = _counters(dfetch), _counters(dwrite)
 
-    def pick(agg, counter, sub, largest=True):
-        vals = [max(v) if largest else sum(v) / len(v) for (k, c), v in agg.items() if sub in k and c == counter]
+    def pick(agg, counter, name, largest=True, exact=True):
+        # exact: the kernel itself (k_mx_colour, not k_mx_colour_zero); else a substring of its name
+        vals = [max(v) if largest else sum(v) / len(v) for (k, c), v in agg.items()
+                if c == counter and (_short(k).split("<")[0] == name if exact else name in k)]
         return max(vals) if vals else None
 
-    cf = pick(fa, "FETCH_SIZE", COPY)
-    cw = pick(wa, "WRITE_SIZE", COPY)
+    cf = pick(fa, "FETCH_SIZE", COPY, exact=False)
+    cw = pick(wa, "WRITE_SIZE", COPY, exact=False)
     gib_kib = float(1 << 20)
     res = {"calibration": {"copy_fetch_kib": cf, "copy_write_kib": cw, "copy_bytes": 1 << 30}}
     for name, src in SWEEPS.items():

@@ -8,7 +8,8 @@ tolerance), delta f_R at sampled cells, and the force at sampled particles;
 and the mixed solves (network warm start, screened-limit guess) must agree
 with the float64 solve.  A 1024^3 mesh (the
 largest the library accepts) is solved from a synthetic multi-sphere field
-and checked the same way."""
+and checked the same way, and a 256^3 particle load is assigned to it and
+its force gathered (the binning's largest tile count)."""
 import math
 import os
 
@@ -119,6 +120,22 @@ def test_largest_mesh_1024():
     cells = np.concatenate([rng.choice(N ** 3, 100000, replace=False), np.argsort(flat)[-500:]]).astype(np.int64)
     r = O.residual_at(u_h, f, 200.0 / N, beta * C, cells)
     assert np.abs(r).max() / np.abs(f).max() <= 1e-8
+    # binned particles on the largest mesh: 2^21 tiles, eight replica counters
+    # per tile, mostly sparse work units (a 256^3 load: eight particles per tile)
+    print("[case] 1024^3 binned assignment and force", flush=True)
+    pos = synth.clustered_load(256, 200.0, rms=5.0, seed=6, n_halos=10, device=DEV)
+    delta = s.assign_density(pos)
+    acc = s.fifth_force(u, pos)
+    pos_h = pos.cpu().numpy()
+    dflat = delta.cpu().numpy().reshape(-1)
+    cells = np.concatenate([rng.choice(N ** 3, 40, replace=False), np.argsort(dflat)[-4:]]).astype(np.int64)
+    mcell = O.cic_cells(N, 200.0, pos_h, cells)
+    mbar = pos_h.shape[0] / N ** 3
+    assert np.allclose(dflat[cells], mcell / mbar - 1.0, rtol=1e-12, atol=1e-12)
+    pidx = rng.choice(pos_h.shape[0], 2000, replace=False)
+    ref = O.fifth_force_at(O.params(mesh=N, box=200.0, a=1.0, fr0_abs=1e-6), u_h, pos_h[pidx])
+    got = acc.cpu().numpy()[pidx].astype(np.float64)
+    assert np.all(np.abs(got - ref) <= 6e-8 * np.abs(ref) + 1e-10 * np.abs(ref).max())
 
 
 def test_mesh_limits_rejected():

@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--smooth", type=int, default=4, help="pre- and post-smoothing sweeps")
     ap.add_argument("--omega", type=float, default=1.2,
                     help="relaxation factor of the float32 correction sweeps of the mixed modes (1: plain NGS)")
-    ap.add_argument("--inner", type=int, default=2,
+    ap.add_argument("--inner", type=int, default=3,
                     help="float32 correction V-cycles per float64 residual check of the mixed modes, at most")
     ap.add_argument("--coarse-sweeps", type=int, default=None,
                     help="red-black sweeps on the coarsest grid (default: 30 for the uniform mesh, whose 4^3 "

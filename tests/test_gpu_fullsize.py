@@ -36,7 +36,7 @@ def test_512_workload_sampled_against_oracle():
     s = mgfr.Solver(mgfr.Params(mesh=N, a=a, fr0_abs=fr0, precision=mgfr.MIXED, nn_mode=mode,
                                 pre_smooth=sm, post_smooth=sm, prolong=pro))
     s.set_relaxation32(1.2)  # as timed
-    s.set_inner_cycles(2)
+    s.set_inner_cycles(3)
     net = None
     if mode == mgfr.NN_COARSE:
         net = mgfr.Net(seed=0, max_voxels=(N // 4) ** 3)
@@ -58,7 +58,7 @@ def test_512_workload_sampled_against_oracle():
     s2 = mgfr.Solver(mgfr.Params(mesh=N, a=a, fr0_abs=fr0, precision=mgfr.MIXED, pre_smooth=sm, post_smooth=sm,
                                  prolong=pro))
     s2.set_relaxation32(1.2)
-    s2.set_inner_cycles(2)
+    s2.set_inner_cycles(3)
     u2, dfr2, st2 = s2.solve(delta, u=s2.screened_guess(delta))
     assert st2.status == 0 and st2.res <= 1e-8 and st2.fell_back == 0
     rel2 = (torch.abs(dfr2 - dfr64).max() / torch.abs(dfr64).max()).item()

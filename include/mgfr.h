@@ -217,16 +217,18 @@ int mgfr_assign_density(mgfr_ctx *ctx, const float *pos, const double *mass, int
 int mgfr_assign_density_noalloc(int mesh, double box, void *stream, const float *pos, const double *mass,
                                 int64_t np, double *delta);
 
-/* Workspace for particle binning (Sec. 3.1 assignment, Sec. 2 force): four
- * uint32 arrays of max_np entries plus radix-sort scratch, owned by the
- * context, freed by mgfr_destroy or by a later call with a larger max_np
- * (which synchronizes the stream first).  With it, mgfr_assign_density for
- * np <= max_np sorts the particle indices by the 8^3-cell tile of their
- * lower CIC corner, accumulates each tile's run in on-chip memory and adds
- * the 9^3 window to the mesh; mgfr_fifth_force for the same np then visits
- * the particles in that order (any order gives the same forces; only the
- * speed depends on it).  Without it (or for larger np) both work in particle
- * index order.  max_np <= 2^31 - 1; MGFR_ERR_OOM if the allocation fails. */
+/* Workspace for particle binning (Sec. 3.1 assignment, Sec. 2 force): three
+ * uint32 arrays of max_np entries, the per-tile counts and first slots, a
+ * list of work units and a scan's scratch, owned by the context, freed by
+ * mgfr_destroy or by a later call with a larger max_np (which synchronizes
+ * the stream first).  With it, mgfr_assign_density for np <= max_np orders
+ * the particle indices by the 8^3-cell tile of their lower CIC corner (a
+ * counting sort; the order within a tile may differ between calls),
+ * accumulates each tile's particles in on-chip memory and adds the 9^3
+ * window to the mesh; mgfr_fifth_force for the same np then visits the
+ * particles in that order (any order gives the same forces; only the speed
+ * depends on it).  Without it (or for larger np) both work in particle index
+ * order.  max_np <= 2^31 - 1; MGFR_ERR_OOM if the allocation fails. */
 int mgfr_reserve_particles(mgfr_ctx *ctx, int64_t max_np);
 
 /* 1 (default): use the binning workspace when it is large enough; 0: never. */

@@ -52,7 +52,9 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_traffic_summary_scales_by_the_streaming_kernel(tmp_path):
     """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are scaled by what they read
-    for the 1 GiB streaming kernel; the largest dispatch of a kernel is taken."""
+    for the 1 GiB streaming kernel; the largest dispatch of a kernel is taken,
+    matched by its exact name (not k_mx_colour_zero for k_mx_colour); the
+    record carries the source hash the benchmark checks before using it."""
     from paper_1305_2418_amd import profile_summary as ps
     fdir, wdir = tmp_path / "f", tmp_path / "w"
     fdir.mkdir()
@@ -60,7 +62,8 @@ def test_traffic_summary_scales_by_the_streaming_kernel(tmp_path):
     hdr = "Kernel_Name,Counter_Name,Counter_Value\n"
     (fdir / "x_counter_collection.csv").write_text(
         hdr + "void at::native::bitwise_not_kernel(...),FETCH_SIZE,524288\n"
-        "k_mx_colour(ColourArgs),FETCH_SIZE,1000\nk_mx_colour(ColourArgs),FETCH_SIZE,800000\n")
+        "k_mx_colour(ColourArgs),FETCH_SIZE,1000\nk_mx_colour(ColourArgs),FETCH_SIZE,800000\n"
+        "mgfr::(anonymous namespace)::k_mx_colour_zero(ColourArgs),FETCH_SIZE,900000\n")
     (wdir / "x_counter_collection.csv").write_text(
         hdr + "void at::native::bitwise_not_kernel(...),WRITE_SIZE,1048576\nk_mx_colour(ColourArgs),WRITE_SIZE,262144\n")
     out = tmp_path / "t.json"
@@ -71,6 +74,9 @@ def test_traffic_summary_scales_by_the_streaming_kernel(tmp_path):
     assert e["fetch_scale"] == pytest.approx(2.0) and e["write_scale"] == pytest.approx(1.0)
     assert e["bytes_per_launch"] == pytest.approx((800000 * 2.0 + 262144 * 1.0) * 1024)
     assert e["mesh"] == 512 and len(e["source_hash"]) == 16
+    sys.path.insert(0, ROOT)
+    import bench
+    assert e["source_hash"] == bench.source_hash(bench.KERNEL_SRC["mixed"])
 
 
 def test_synthetic_loads_are_seeded_and_in_the_box():
